@@ -1,0 +1,235 @@
+/*
+ * aidw.h -- C ABI of the MI355X (gfx950) implementation of Adaptive IDW
+ * interpolation with even-grid kNN search (Mei, Xu & Xu, arXiv 1601.05904).
+ *
+ * The method has two stages (Section 3.1, Fig. 1):
+ *   stage 1  bin the data points into an even grid (Section 4.1.1-4.1.3) and
+ *            find, for every interpolated ("query") point, its k nearest data
+ *            points by searching rings of cells outward (Section 3.2.4, 4.1.4);
+ *            r_obs = mean of the k distances (Eq. 3);
+ *   stage 2  R = r_obs / r_exp (Eq. 2, 4), mu = fuzzy membership of R (Eq. 5),
+ *            alpha = triangular membership of mu over five levels (Eq. 6), and
+ *            z = sum_i z_i d_i^-alpha / sum_i d_i^-alpha over ALL n data points (Eq. 1).
+ *
+ * Conventions for every entry point
+ *   - n = number of data points (x, y, z), m = number of query points (qx, qy).
+ *   - Arrays are structure-of-arrays float32 (Section 4.2), DEVICE pointers owned
+ *     by the caller, contiguous, naturally aligned.  They must stay valid until
+ *     the work queued on the given stream has completed.
+ *   - Work is queued on the given HIP stream (0 = the null stream).  Calls
+ *     return when the work is queued, except where a call states that it
+ *     synchronises the stream.
+ *   - Errors are reported by return code only; nothing is thrown and nothing
+ *     aborts.  Argument checks run on the host before any GPU work is queued,
+ *     so a call that returns AIDW_EINVAL has touched neither the GPU nor the
+ *     outputs.  After any other error the output contents are unspecified.
+ *     aidw_last_error_detail() gives a message for the last error on the
+ *     calling thread.
+ *   - Results are deterministic: the same inputs give bitwise identical outputs
+ *     (no floating-point atomics; every reduction has a fixed order).
+ */
+#ifndef AIDW_H
+#define AIDW_H
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  AIDW_OK = 0,
+  AIDW_EINVAL = -1,       /* invalid argument (null pointer, size, k, parameters)            */
+  AIDW_EDEGENERATE = -2,  /* the area A of Eq. 2 resolves to <= 0 (collinear / single point) */
+  AIDW_ENOMEM = -3,       /* device allocation failed                                        */
+  AIDW_EDEVICE = -4,      /* a HIP runtime call failed                                        */
+  AIDW_ENONFINITE = -5,   /* a coordinate is NaN or infinite                                  */
+  AIDW_ECAPACITY = -6     /* the grid would exceed AIDW_MAX_CELLS cells, or a size exceeds int32 */
+} aidw_status;
+
+#define AIDW_KMAX 64                 /* largest supported k */
+#define AIDW_MAX_CELLS (1LL << 28)   /* largest grid (nCol * nRow) */
+
+/*
+ * Method parameters.
+ *   k          neighbours used for r_obs (Eq. 3); 1 <= k <= min(n, AIDW_KMAX).
+ *   alpha[5]   the five distance-decay levels alpha_1..alpha_5 of Eq. 6 (finite, > 0).
+ *   r_min, r_max  the bounds of the fuzzy membership of Eq. 5; 0 <= r_min < r_max.
+ *              Eq. 5 is applied as printed: the cosine argument is
+ *              (pi / r_max) (R - r_min); this equals the symmetric ramp only
+ *              when r_min = 0 (the paper's suggested 0 and 2).
+ *   area       A of Eq. 2.  <= 0 selects the bounding-box area of data and
+ *              queries (the region the grid covers, Section 4.1.1).
+ *   cell_width > 0 fixes the grid's cell side; <= 0 selects
+ *              sqrt(occupancy * A / n).  (The paper's own choice, the width of
+ *              Eq. 2, is occupancy = 0.25.)  The kNN result does not depend on
+ *              the cell width: the search stops only when no point outside the
+ *              searched block can be nearer than the current k-th neighbour.
+ *   occupancy  target mean data points per cell when cell_width <= 0 (> 0).
+ */
+typedef struct {
+  int32_t k;
+  double alpha[5];
+  double r_min, r_max;
+  double area;
+  double cell_width;
+  double occupancy;
+} aidw_params;
+
+/* Fills the defaults: k = 10, alpha = {1,2,3,4,5}, r_min = 0, r_max = 2 (Eq. 5's
+ * suggested values), area = 0 (bounding box), cell_width = 0, occupancy = 2. */
+void aidw_params_default(aidw_params* p);
+
+/* Opaque even grid over the data points (device-resident, library-owned,
+ * immutable after aidw_build_grid; safe for concurrent read-only use). */
+typedef struct aidw_grid aidw_grid;
+
+/* Host-side description of a grid (Section 4.1.1).  The grid covers
+ * [min_x, min_x + ncol * cell_width) x [min_y, min_y + nrow * cell_width);
+ * a point's cell is row * ncol + col with col = (int)((x - min_x) * inv_cell_width)
+ * computed in float32 and clamped to [0, ncol - 1] (rows likewise). */
+typedef struct {
+  int64_t n;                 /* data points binned                                 */
+  float min_x, min_y;        /* lower bounds over data and queries                 */
+  float max_x, max_y;        /* upper bounds over data and queries                 */
+  double area;               /* A used by Eq. 2                                    */
+  double r_exp;              /* Eq. 2: 1 / (2 sqrt(n / A))                          */
+  double cell_width;         /* cell side                                          */
+  float inv_cell_width;      /* float32 reciprocal used for binning                */
+  int32_t ncol, nrow;        /* (int)((max - min + cell_width) / cell_width)       */
+} aidw_grid_desc;
+
+/*
+ * Stage 1, grid build (Section 3.2.1-3.2.3, 4.1.1-4.1.3).
+ * Bounds over the n data points AND the m query points (qx, qy may be NULL
+ * when m = 0); A, r_exp and the cell width from Eq. 2 and p; every data point
+ * binned to its cell; the points sorted by cell with a stable counting sort,
+ * so that each cell is one contiguous segment ordered by original index and
+ * is described by two integers (Section 3.2.3: head and size, stored here as
+ * CSR offsets cell_start[c] .. cell_start[c + 1]).
+ * Synchronises the stream once (to size the grid from the device-computed
+ * bounds).  On success *out owns device memory until aidw_grid_destroy.
+ * Errors: AIDW_EINVAL (null pointers, n < 1, m < 0, sizes > INT32_MAX, invalid p),
+ * AIDW_ENONFINITE (a NaN / inf coordinate), AIDW_EDEGENERATE (A <= 0),
+ * AIDW_ECAPACITY (more than AIDW_MAX_CELLS cells), AIDW_ENOMEM, AIDW_EDEVICE.
+ */
+aidw_status aidw_build_grid(const float* x, const float* y, int64_t n, const float* qx, const float* qy, int64_t m,
+                            const aidw_params* p, hipStream_t stream, aidw_grid** out);
+
+/* Copies the grid's description to *out (host only, no GPU work). */
+aidw_status aidw_grid_describe(const aidw_grid* g, aidw_grid_desc* out);
+
+/* Device pointers of the grid's arrays (library-owned, read-only, valid until
+ * aidw_grid_destroy): cell_start [ncol*nrow + 1] int32 CSR offsets;
+ * sx, sy [n] float32 and sidx [n] int32 = the data points in cell order.
+ * Any output pointer may be NULL. */
+aidw_status aidw_grid_arrays(const aidw_grid* g, const int32_t** cell_start, const float** sx, const float** sy,
+                             const int32_t** sidx);
+
+/* Copies the grid's arrays (see aidw_grid_arrays) into caller-owned device
+ * buffers on `stream`: cell_start [ncol*nrow + 1], sx, sy, sidx [n]; any may be
+ * NULL.  Asynchronous. */
+aidw_status aidw_grid_copy_arrays(const aidw_grid* g, int32_t* cell_start, float* sx, float* sy, int32_t* sidx,
+                                  hipStream_t stream);
+
+/* Frees the grid (waits for the device to finish using it).  NULL is a no-op. */
+void aidw_grid_destroy(aidw_grid* g);
+
+/*
+ * Stage 1, kNN search (Section 3.2.4, 4.1.4) and Eq. 3.
+ * For each query j: the k data points nearest to (qx[j], qy[j]) in the order
+ * of (squared distance, data index) -- ties go to the smaller index, so the
+ * neighbour set is unique.  Squared distances are formed in float64 from the
+ * float32 inputs (exact for coordinates on a 2^-20 lattice in [0, 1)).
+ * The search visits rings of cells around the query's cell and stops only when
+ * the block searched so far provably contains the k nearest points (the
+ * paper's "one more level" rule, the Remark in Section 3.2.4, is not always
+ * sufficient and is not used).  The queries are binned to cells first so that
+ * the lanes of a wavefront search neighbouring cells.
+ * Outputs (device, caller-owned):
+ *   r_obs [m]   float32, (1/k) * sum of the k distances, summed in float64 in
+ *               ascending order (Eq. 3);
+ *   d1sq  [m]   float32 squared distance to the nearest neighbour, or NULL;
+ *               exactly 0 iff the query coincides with a data point;
+ *   nn_idx [m*k] int32 neighbour indices, row-major, ascending order, or NULL.
+ * Errors: AIDW_EINVAL (null grid / pointers, m < 0, k outside [1, min(n, AIDW_KMAX)]),
+ * AIDW_ENOMEM, AIDW_EDEVICE.  m = 0 is AIDW_OK and does nothing.
+ */
+aidw_status aidw_knn(const aidw_grid* g, const float* qx, const float* qy, int64_t m, int32_t k, float* r_obs,
+                     float* d1sq, int32_t* nn_idx, hipStream_t stream);
+
+/*
+ * Stage 2, adaptive power and weighted interpolation (Eq. 1, 2, 4, 5, 6;
+ * Section 3.3, 4.2).
+ * For each query j: R = r_obs[j] / r_exp with r_exp = 1 / (2 sqrt(n / A)),
+ * mu(R) by Eq. 5 and alpha(mu) by Eq. 6 (float64), then
+ *   qz[j] = sum_i z_i d_ij^-alpha / sum_i d_ij^-alpha  over all n data points.
+ * Pairs are evaluated in float32 as w = 2^(-(alpha/2) log2(d^2 / d1sq[j]))
+ * (the common factor d1sq^(alpha/2) cancels and keeps w <= ~1); the data are
+ * streamed through the chip in tiles shared by every query of a wavefront, the
+ * per-tile float32 partial sums are folded into compensated (two-sum) pairs,
+ * and the final numerator / denominator are combined in float64.
+ * A query with d1sq[j] == 0 coincides with data points and gets the mean z of
+ * those points (the limit of Eq. 1).
+ * Arguments: r_obs, d1sq as produced by aidw_knn (device, [m]); p->alpha,
+ * p->r_min, p->r_max are used and p->area must be > 0 unless a grid g is
+ * given, whose area is then used; g (may be NULL) also speeds up the
+ * coincident-query fix-up.  alpha_out [m] (may be NULL) receives alpha.
+ * Accuracy: |qz - z_exact| <= ~1e-5 * max(|z_exact|, sum_i w_i |z_i| / sum_i w_i).
+ * Errors: AIDW_EINVAL, AIDW_ENOMEM, AIDW_EDEVICE.  m = 0 is AIDW_OK.
+ */
+aidw_status aidw_interpolate(const float* x, const float* y, const float* z, int64_t n, const float* qx,
+                             const float* qy, int64_t m, const float* r_obs, const float* d1sq,
+                             const aidw_params* p, const aidw_grid* g, float* qz, float* alpha_out,
+                             hipStream_t stream);
+
+/*
+ * The whole method (Fig. 1): aidw_build_grid -> aidw_knn -> aidw_interpolate
+ * on one stream, with library-owned temporaries.  qz [m] receives the
+ * interpolated values; alpha_out [m] and r_obs_out [m] may be NULL.
+ * Synchronises the stream once (grid sizing), like aidw_build_grid.
+ * Errors: those of the three stages.
+ */
+aidw_status aidw_run(const float* x, const float* y, const float* z, int64_t n, const float* qx, const float* qy,
+                     int64_t m, const aidw_params* p, float* qz, float* alpha_out, float* r_obs_out,
+                     hipStream_t stream);
+
+/* Per-stage device times of the last aidw_run on the calling thread, recorded
+ * with HIP events on the run's stream when timing is enabled. */
+typedef struct {
+  float grid_ms;        /* bounds, binning, counting sort                  */
+  float knn_ms;         /* query binning and kNN search with Eq. 3         */
+  float interp_ms;      /* the pair-evaluation kernel(s) of Eq. 1          */
+  float finish_ms;      /* split combine and coincident-query fix-up       */
+  int32_t interp_q;     /* queries per lane used by the pair kernel        */
+  int32_t interp_split; /* data-axis splits used by the pair kernel        */
+} aidw_timing;
+
+/* Enables (1) or disables (0) per-stage timing for aidw_run on the calling
+ * thread.  Timing adds events only; the kernels are unchanged. */
+aidw_status aidw_set_timing(int enable);
+
+/* Waits for the last timed aidw_run of the calling thread and reports its
+ * stage times.  AIDW_EINVAL if timing was off or no run was timed. */
+aidw_status aidw_last_timing(aidw_timing* out);
+
+/* Overrides the pair kernel's launch shape for later calls on the calling
+ * thread: q = queries per lane (1, 2, 4 or 8), split = data-axis splits
+ * (>= 1).  0 for either restores the built-in choice. */
+aidw_status aidw_set_interp_config(int32_t q, int32_t split);
+
+/* Static text for a status code. */
+const char* aidw_status_string(aidw_status st);
+
+/* Message for the last error on the calling thread ("" if none). */
+const char* aidw_last_error_detail(void);
+
+/* Library version string. */
+const char* aidw_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* AIDW_H */

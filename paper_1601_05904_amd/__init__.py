@@ -1,1 +1,273 @@
-"""AIDW with even-grid kNN on MI355X (placeholder; binding added with the library)."""
+"""Adaptive IDW with even-grid kNN on MI355X (gfx950): thin Python binding.
+
+Every call goes through the C ABI of ``include/aidw.h`` exported by the HIP
+library ``libaidw.so`` in this directory.  This module only marshals
+arguments: it checks that tensors are float32, contiguous and on the GPU,
+allocates the output tensors with torch and passes raw device pointers and the
+current HIP stream.  All computation happens in the library's kernels; if the
+library cannot be loaded, every call raises (there is no fallback).
+
+    import torch, paper_1601_05904_amd as aidw
+    p = aidw.Params(k=10)
+    qz = aidw.run(x, y, z, qx, qy, p)          # the whole method (Fig. 1)
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+from dataclasses import dataclass
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libaidw.so")
+HEADER = os.path.join(os.path.dirname(_HERE), "include", "aidw.h")
+
+OK, EINVAL, EDEGENERATE, ENOMEM, EDEVICE, ENONFINITE, ECAPACITY = 0, -1, -2, -3, -4, -5, -6
+KMAX = 64
+
+
+class AidwError(RuntimeError):
+    """A non-zero aidw_status; ``code`` is the status, ``detail`` the library's message."""
+
+    def __init__(self, code, detail):
+        super().__init__("aidw status %d (%s): %s" % (code, _STATUS.get(code, "?"), detail))
+        self.code = code
+        self.detail = detail
+
+
+_STATUS = {0: "ok", -1: "invalid argument", -2: "degenerate study area", -3: "out of device memory",
+           -4: "HIP runtime error", -5: "non-finite coordinate", -6: "capacity exceeded"}
+
+
+class _Params(ctypes.Structure):
+    _fields_ = [("k", ctypes.c_int32), ("alpha", ctypes.c_double * 5), ("r_min", ctypes.c_double),
+                ("r_max", ctypes.c_double), ("area", ctypes.c_double), ("cell_width", ctypes.c_double),
+                ("occupancy", ctypes.c_double)]
+
+
+class _GridDesc(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("min_x", ctypes.c_float), ("min_y", ctypes.c_float),
+                ("max_x", ctypes.c_float), ("max_y", ctypes.c_float), ("area", ctypes.c_double),
+                ("r_exp", ctypes.c_double), ("cell_width", ctypes.c_double), ("inv_cell_width", ctypes.c_float),
+                ("ncol", ctypes.c_int32), ("nrow", ctypes.c_int32)]
+
+
+class _Timing(ctypes.Structure):
+    _fields_ = [("grid_ms", ctypes.c_float), ("knn_ms", ctypes.c_float), ("interp_ms", ctypes.c_float),
+                ("finish_ms", ctypes.c_float), ("interp_q", ctypes.c_int32), ("interp_split", ctypes.c_int32)]
+
+
+@dataclass
+class Params:
+    """aidw_params: k (Eq. 3), levels alpha_1..alpha_5 (Eq. 6), r_min / r_max (Eq. 5),
+    area (Eq. 2; <= 0: bounding box), cell_width (<= 0: from occupancy), occupancy."""
+    k: int = 10
+    levels: tuple = (1.0, 2.0, 3.0, 4.0, 5.0)
+    r_min: float = 0.0
+    r_max: float = 2.0
+    area: float = 0.0
+    cell_width: float = 0.0
+    occupancy: float = 2.0
+
+    def _c(self):
+        p = _Params()
+        p.k = int(self.k)
+        for i in range(5):
+            p.alpha[i] = float(self.levels[i])
+        p.r_min, p.r_max = float(self.r_min), float(self.r_max)
+        p.area, p.cell_width, p.occupancy = float(self.area), float(self.cell_width), float(self.occupancy)
+        return p
+
+
+_lib = None
+_VP = ctypes.c_void_p
+
+
+def exported_functions():
+    """Names of the functions declared in include/aidw.h."""
+    with open(HEADER) as f:
+        text = f.read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?[a-z_0-9]+\**\s+\**(aidw_[a-z_0-9]+)\s*\(", text, flags=re.M)))
+
+
+def load(build_if_missing: bool = True):
+    """Loads libaidw.so (building it once if it is absent) and declares the C ABI."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        if not build_if_missing:
+            raise OSError("libaidw.so not built: run __graft_entry__.build()")
+        from . import build as _b
+        _b.build()
+    L = ctypes.CDLL(LIB_PATH)
+    i64, i32 = ctypes.c_int64, ctypes.c_int32
+    P = ctypes.POINTER
+    L.aidw_params_default.argtypes = [P(_Params)]
+    L.aidw_params_default.restype = None
+    L.aidw_build_grid.argtypes = [_VP, _VP, i64, _VP, _VP, i64, P(_Params), _VP, P(_VP)]
+    L.aidw_grid_describe.argtypes = [_VP, P(_GridDesc)]
+    L.aidw_grid_arrays.argtypes = [_VP, P(_VP), P(_VP), P(_VP), P(_VP)]
+    L.aidw_grid_copy_arrays.argtypes = [_VP, _VP, _VP, _VP, _VP, _VP]
+    L.aidw_grid_destroy.argtypes = [_VP]
+    L.aidw_grid_destroy.restype = None
+    L.aidw_knn.argtypes = [_VP, _VP, _VP, i64, i32, _VP, _VP, _VP, _VP]
+    L.aidw_interpolate.argtypes = [_VP, _VP, _VP, i64, _VP, _VP, i64, _VP, _VP, P(_Params), _VP, _VP, _VP, _VP]
+    L.aidw_run.argtypes = [_VP, _VP, _VP, i64, _VP, _VP, i64, P(_Params), _VP, _VP, _VP, _VP]
+    L.aidw_set_timing.argtypes = [ctypes.c_int]
+    L.aidw_last_timing.argtypes = [P(_Timing)]
+    L.aidw_set_interp_config.argtypes = [i32, i32]
+    L.aidw_status_string.argtypes = [ctypes.c_int]
+    L.aidw_status_string.restype = ctypes.c_char_p
+    L.aidw_last_error_detail.argtypes = []
+    L.aidw_last_error_detail.restype = ctypes.c_char_p
+    L.aidw_version.restype = ctypes.c_char_p
+    for name in ("aidw_build_grid", "aidw_grid_describe", "aidw_grid_arrays", "aidw_grid_copy_arrays", "aidw_knn",
+                 "aidw_interpolate", "aidw_run", "aidw_set_timing", "aidw_last_timing", "aidw_set_interp_config"):
+        getattr(L, name).restype = ctypes.c_int
+    _lib = L
+    return L
+
+
+def _check(st):
+    if st != OK:
+        raise AidwError(st, load().aidw_last_error_detail().decode())
+
+
+def _dev(t, name, dtype=None):
+    """Marshals a device tensor to a raw pointer (float32 / int32, 1-D, contiguous, on the GPU)."""
+    import torch
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor):
+        raise TypeError("%s must be a torch tensor" % name)
+    want = dtype or torch.float32
+    if t.dtype != want:
+        raise TypeError("%s must be %s (got %s)" % (name, want, t.dtype))
+    if not t.is_cuda:
+        raise TypeError("%s must be on the GPU" % name)
+    if not t.is_contiguous():
+        raise TypeError("%s must be contiguous" % name)
+    return t.data_ptr()
+
+
+def _stream(stream):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return s.cuda_stream
+
+
+class Grid:
+    """An aidw_grid handle (library-owned device memory, freed by close() / garbage collection)."""
+
+    def __init__(self, handle, n):
+        self._h = handle
+        self.n = n
+
+    @property
+    def handle(self):
+        if not self._h:
+            raise ValueError("grid is closed")
+        return self._h
+
+    def describe(self) -> dict:
+        d = _GridDesc()
+        _check(load().aidw_grid_describe(self.handle, ctypes.byref(d)))
+        return {f: getattr(d, f) for f, _ in _GridDesc._fields_}
+
+    def arrays(self, stream=None):
+        """Copies (cell_start, sx, sy, sidx) into new device tensors."""
+        import torch
+        d = self.describe()
+        dev = torch.device("cuda", torch.cuda.current_device())
+        cs = torch.empty(d["ncol"] * d["nrow"] + 1, dtype=torch.int32, device=dev)
+        sx = torch.empty(self.n, dtype=torch.float32, device=dev)
+        sy = torch.empty(self.n, dtype=torch.float32, device=dev)
+        si = torch.empty(self.n, dtype=torch.int32, device=dev)
+        _check(load().aidw_grid_copy_arrays(self.handle, cs.data_ptr(), sx.data_ptr(), sy.data_ptr(), si.data_ptr(),
+                                            _stream(stream)))
+        return cs, sx, sy, si
+
+    def close(self):
+        if self._h:
+            load().aidw_grid_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def build_grid(x, y, qx=None, qy=None, params: Params | None = None, stream=None) -> Grid:
+    """aidw_build_grid: even grid over the data points; bounds over data and queries."""
+    p = (params or Params())._c()
+    m = 0 if qx is None else qx.numel()
+    h = _VP()
+    _check(load().aidw_build_grid(_dev(x, "x"), _dev(y, "y"), x.numel(), _dev(qx, "qx"), _dev(qy, "qy"), m,
+                                  ctypes.byref(p), _stream(stream), ctypes.byref(h)))
+    return Grid(h.value, x.numel())
+
+
+def knn(grid: Grid, qx, qy, k: int, want_d1sq=True, want_idx=False, stream=None):
+    """aidw_knn -> (r_obs [m], d1sq [m] or None, nn_idx [m, k] or None)."""
+    import torch
+    m = qx.numel()
+    r = torch.empty(m, dtype=torch.float32, device=qx.device)
+    d1 = torch.empty(m, dtype=torch.float32, device=qx.device) if want_d1sq else None
+    ix = torch.empty((m, k), dtype=torch.int32, device=qx.device) if want_idx else None
+    _check(load().aidw_knn(grid.handle, _dev(qx, "qx"), _dev(qy, "qy"), m, int(k), r.data_ptr(),
+                           None if d1 is None else d1.data_ptr(), None if ix is None else ix.data_ptr(),
+                           _stream(stream)))
+    return r, d1, ix
+
+
+def interpolate(x, y, z, qx, qy, r_obs, d1sq, params: Params | None = None, grid: Grid | None = None,
+                want_alpha=False, stream=None):
+    """aidw_interpolate -> qz [m] (and alpha [m] if requested)."""
+    import torch
+    p = (params or Params())._c()
+    m = qx.numel()
+    qz = torch.empty(m, dtype=torch.float32, device=qx.device)
+    al = torch.empty(m, dtype=torch.float32, device=qx.device) if want_alpha else None
+    _check(load().aidw_interpolate(_dev(x, "x"), _dev(y, "y"), _dev(z, "z"), x.numel(), _dev(qx, "qx"),
+                                   _dev(qy, "qy"), m, _dev(r_obs, "r_obs"), _dev(d1sq, "d1sq"), ctypes.byref(p),
+                                   None if grid is None else grid.handle, qz.data_ptr(),
+                                   None if al is None else al.data_ptr(), _stream(stream)))
+    return (qz, al) if want_alpha else qz
+
+
+def run(x, y, z, qx, qy, params: Params | None = None, want_alpha=False, want_robs=False, out=None, stream=None):
+    """aidw_run: the whole method.  Returns qz, or (qz, alpha, r_obs) with the requested extras (else None)."""
+    import torch
+    p = (params or Params())._c()
+    m = qx.numel()
+    qz = out if out is not None else torch.empty(m, dtype=torch.float32, device=qx.device)
+    al = torch.empty(m, dtype=torch.float32, device=qx.device) if want_alpha else None
+    ro = torch.empty(m, dtype=torch.float32, device=qx.device) if want_robs else None
+    _check(load().aidw_run(_dev(x, "x"), _dev(y, "y"), _dev(z, "z"), x.numel(), _dev(qx, "qx"), _dev(qy, "qy"), m,
+                           ctypes.byref(p), _dev(qz, "qz"), None if al is None else al.data_ptr(),
+                           None if ro is None else ro.data_ptr(), _stream(stream)))
+    if want_alpha or want_robs:
+        return qz, al, ro
+    return qz
+
+
+def set_timing(enable: bool):
+    _check(load().aidw_set_timing(1 if enable else 0))
+
+
+def last_timing() -> dict:
+    t = _Timing()
+    _check(load().aidw_last_timing(ctypes.byref(t)))
+    return {f: getattr(t, f) for f, _ in _Timing._fields_}
+
+
+def set_interp_config(q: int = 0, split: int = 0):
+    _check(load().aidw_set_interp_config(int(q), int(split)))
+
+
+def version() -> str:
+    return load().aidw_version().decode()

@@ -1,0 +1,78 @@
+// Internal declarations shared by the HIP sources of libaidw (not part of the C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/aidw.h"
+
+namespace aidw {
+
+// Device-resident grid scalars, written by the finalize kernel (Section 4.1.1, Eq. 2).
+struct GridScalars {
+  float minx, miny, maxx, maxy;
+  double area;    // A
+  double r_exp;   // 1 / (2 sqrt(n / A))
+  double cw;      // cell side
+  double cwd;     // 1 / (double)inv_cw: the side implied by the float32 reciprocal
+  float inv_cw;   // float32 reciprocal used for binning
+  int32_t ncol, nrow;
+  int32_t status; // 0 ok, else an aidw_status value
+  int64_t ncells;
+};
+
+// Per-block partial of the bounds reduction.
+struct BoundsPartial {
+  float minx, miny, maxx, maxy;
+  int32_t nonfinite;
+  int32_t pad[3];
+};
+
+constexpr int kBoundsBlocks = 512;
+constexpr int kBoundsThreads = 256;
+constexpr int kSortThreads = 256;
+constexpr int kSortItems = 16;                       // elements per thread per block
+constexpr int kSortTile = kSortThreads * kSortItems; // elements per block
+constexpr int kRadixBits = 8;
+constexpr int kRadix = 1 << kRadixBits;
+
+// Host-side launchers (all asynchronous on `s`; return the first HIP error).
+hipError_t launch_bounds(const float* x, const float* y, int n, const float* qx, const float* qy, int m,
+                         BoundsPartial* partial, hipStream_t s);
+hipError_t launch_finalize(const BoundsPartial* partial, int nparts, int64_t n, double area_in, double cw_in,
+                           double occ, GridScalars* out, hipStream_t s);
+hipError_t launch_cell_keys(const float* x, const float* y, int n, const GridScalars* gs, uint32_t* keys,
+                            uint32_t* vals, hipStream_t s);
+// Stable LSD radix sort of (key, value) pairs on the low `bits` bits of the keys.
+// tmp_* are ping-pong buffers of n entries; hist needs radix_hist_words(n) words and
+// scan_tmp radix_scan_tmp_words(n) words.  The result ends in (keys, vals).
+size_t radix_hist_words(int n);
+size_t radix_scan_tmp_words(int n);
+hipError_t radix_sort_pairs(uint32_t* keys, uint32_t* vals, uint32_t* tmp_keys, uint32_t* tmp_vals, int n, int bits,
+                            uint32_t* hist, uint32_t* scan_tmp, hipStream_t s);
+hipError_t launch_cell_start_gather(const uint32_t* keys, const uint32_t* vals, int n, int64_t ncells, const float* x,
+                                    const float* y, int32_t* cell_start, float* sx, float* sy, int32_t* sidx,
+                                    hipStream_t s);
+
+hipError_t launch_knn(const GridScalars* gs, const int32_t* cell_start, const float* sx, const float* sy,
+                      const int32_t* sidx, const float* qx, const float* qy, const uint32_t* qperm, int m, int k,
+                      double slack_cells, float* r_obs, float* d1sq, int32_t* nn_idx, hipStream_t s);
+
+struct AlphaParams {
+  double r_exp;
+  double r_min, r_max;
+  double levels[5];
+};
+
+hipError_t launch_interp(const float* x, const float* y, const float* z, int n, const float* qx, const float* qy,
+                         const float* r_obs, const float* d1sq, int m, const AlphaParams& ap, int q, int split,
+                         float* qz, double2* partial, float* alpha_out, hipStream_t s);
+hipError_t launch_combine(const double2* partial, int m, int split, float* qz, hipStream_t s);
+hipError_t launch_coincident_list(const float* d1sq, int m, uint32_t* count, uint32_t* list, hipStream_t s);
+hipError_t launch_fixup_grid(const uint32_t* count, const uint32_t* list, const float* qx, const float* qy,
+                             const GridScalars* gs, const int32_t* cell_start, const float* sx, const float* sy,
+                             const int32_t* sidx, const float* z, float* qz, hipStream_t s);
+hipError_t launch_fixup_scan(const uint32_t* count, const uint32_t* list, const float* qx, const float* qy,
+                             const float* x, const float* y, const float* z, int n, float* qz, hipStream_t s);
+
+}  // namespace aidw

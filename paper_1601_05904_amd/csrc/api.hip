@@ -1,0 +1,489 @@
+// Host side of the C ABI declared in include/aidw.h: argument checks, device
+// memory, stream ordering and the composition of the two stages.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <string>
+
+#include "aidw_internal.h"
+
+using namespace aidw;
+
+struct aidw_grid {
+  int64_t n = 0;
+  GridScalars host{};            // host copy of the device scalars
+  GridScalars* dev = nullptr;    // device scalars
+  int32_t* cell_start = nullptr; // [ncells + 1]
+  float* sx = nullptr;           // [n]
+  float* sy = nullptr;           // [n]
+  int32_t* sidx = nullptr;       // [n]
+  hipStream_t async_stream = nullptr;  // non-null: arrays are stream-ordered allocations on this stream
+  bool async = false;
+};
+
+namespace {
+
+thread_local std::string g_detail;
+thread_local int g_timing = 0;
+thread_local int g_cfg_q = 0, g_cfg_split = 0;
+
+struct Timing {
+  hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+  bool valid = false;
+  int q = 0, split = 0;
+  ~Timing() {
+    for (auto& e : ev)
+      if (e) (void)hipEventDestroy(e);
+  }
+};
+thread_local Timing g_tm;
+
+aidw_status fail(aidw_status st, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+aidw_status fail(aidw_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_detail = buf;
+  return st;
+}
+
+aidw_status hip_fail(hipError_t e, const char* what) {
+  if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation)
+    return fail(AIDW_ENOMEM, "%s: %s", what, hipGetErrorString(e));
+  return fail(AIDW_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+#define HIP_TRY(expr, what)                      \
+  do {                                           \
+    hipError_t e_ = (expr);                      \
+    if (e_ != hipSuccess) return hip_fail(e_, what); \
+  } while (0)
+
+// Test hook: AIDW_FAULT=alloc makes every device allocation fail (host-forced ENOMEM).
+bool fault_alloc() {
+  const char* f = getenv("AIDW_FAULT");
+  return f && strcmp(f, "alloc") == 0;
+}
+
+hipError_t dmalloc(void** p, size_t bytes) {
+  *p = nullptr;
+  if (fault_alloc()) return hipErrorOutOfMemory;
+  return hipMalloc(p, bytes ? bytes : 1);
+}
+
+hipError_t dmalloc_async(void** p, size_t bytes, hipStream_t s) {
+  *p = nullptr;
+  if (fault_alloc()) return hipErrorOutOfMemory;
+  return hipMallocAsync(p, bytes ? bytes : 1, s);
+}
+
+void dfree_async(void* p, hipStream_t s) {
+  if (p) (void)hipFreeAsync(p, s);
+}
+
+// Scoped stream-ordered temporaries.
+struct Temps {
+  hipStream_t s;
+  void* ptrs[16];
+  int count = 0;
+  explicit Temps(hipStream_t st) : s(st) {}
+  ~Temps() {
+    for (int i = 0; i < count; ++i) dfree_async(ptrs[i], s);
+  }
+  template <typename T>
+  hipError_t get(T** out, size_t elems) {
+    void* p = nullptr;
+    hipError_t e = dmalloc_async(&p, elems * sizeof(T), s);
+    if (e != hipSuccess) return e;
+    ptrs[count++] = p;
+    *out = static_cast<T*>(p);
+    return hipSuccess;
+  }
+};
+
+bool finite_pos(double v) { return isfinite(v) && v > 0; }
+
+aidw_status check_params(const aidw_params* p) {
+  if (!p) return fail(AIDW_EINVAL, "params is NULL");
+  for (int i = 0; i < 5; ++i)
+    if (!finite_pos(p->alpha[i])) return fail(AIDW_EINVAL, "alpha[%d] = %g must be finite and > 0", i, p->alpha[i]);
+  if (!isfinite(p->r_min) || !isfinite(p->r_max) || p->r_min < 0 || !(p->r_max > p->r_min))
+    return fail(AIDW_EINVAL, "need 0 <= r_min < r_max (got %g, %g)", p->r_min, p->r_max);
+  if (!isfinite(p->area)) return fail(AIDW_EINVAL, "area must be finite");
+  if (!isfinite(p->cell_width)) return fail(AIDW_EINVAL, "cell_width must be finite");
+  if (!(p->cell_width > 0) && !finite_pos(p->occupancy))
+    return fail(AIDW_EINVAL, "occupancy must be finite and > 0 when cell_width <= 0");
+  return AIDW_OK;
+}
+
+int bits_for(int64_t ncells) {
+  int b = 0;
+  while (b < 31 && (1LL << b) < ncells) ++b;
+  return b;
+}
+
+// Slack (in cells) that covers the float32 binning error of a coordinate in
+// column c: |fl(fl(x - minX) * inv) - (x - minX) * inv| <= (c + 1) * 2^-23.
+double slack_cells(const GridScalars& g) {
+  const double span = (double)(g.ncol > g.nrow ? g.ncol : g.nrow) + 1.0;
+  return span * ldexp(1.0, -21) + 1e-9;
+}
+
+aidw_status build_grid_impl(const float* x, const float* y, int64_t n, const float* qx, const float* qy, int64_t m,
+                            const aidw_params* p, hipStream_t s, bool async, aidw_grid** out) {
+  aidw_grid* g = new aidw_grid();
+  g->n = n;
+  g->async = async;
+  g->async_stream = s;
+  auto cleanup = [&](aidw_status st) {
+    aidw_grid_destroy(g);
+    return st;
+  };
+  hipError_t e = async ? dmalloc_async((void**)&g->dev, sizeof(GridScalars), s)
+                       : dmalloc((void**)&g->dev, sizeof(GridScalars));
+  if (e != hipSuccess) return cleanup(hip_fail(e, "allocating grid scalars"));
+  {
+    Temps t(s);
+    BoundsPartial* part = nullptr;
+    if ((e = t.get(&part, kBoundsBlocks)) != hipSuccess) return cleanup(hip_fail(e, "allocating bounds partials"));
+    if ((e = launch_bounds(x, y, (int)n, qx, qy, (int)m, part, s)) != hipSuccess)
+      return cleanup(hip_fail(e, "bounds kernel"));
+    if ((e = launch_finalize(part, kBoundsBlocks, n, p->area, p->cell_width, p->occupancy, g->dev, s)) != hipSuccess)
+      return cleanup(hip_fail(e, "finalize kernel"));
+    if ((e = hipMemcpyAsync(&g->host, g->dev, sizeof(GridScalars), hipMemcpyDeviceToHost, s)) != hipSuccess)
+      return cleanup(hip_fail(e, "reading grid scalars"));
+  }
+  if ((e = hipStreamSynchronize(s)) != hipSuccess) return cleanup(hip_fail(e, "synchronising grid scalars"));
+  const GridScalars& h = g->host;
+  if (h.status == AIDW_ENONFINITE) return cleanup(fail(AIDW_ENONFINITE, "a coordinate is NaN or infinite"));
+  if (h.status == AIDW_EDEGENERATE)
+    return cleanup(fail(AIDW_EDEGENERATE, "the study area resolves to %g (collinear or coincident points); pass params.area",
+                        h.area));
+  if (h.status == AIDW_ECAPACITY)
+    return cleanup(fail(AIDW_ECAPACITY, "grid would exceed %lld cells; increase cell_width or occupancy",
+                        (long long)AIDW_MAX_CELLS));
+  if (h.status != AIDW_OK) return cleanup(fail(AIDW_EDEVICE, "grid finalize status %d", h.status));
+
+  const int64_t ncells = h.ncells;
+  auto alloc = [&](void** ptr, size_t bytes) { return async ? dmalloc_async(ptr, bytes, s) : dmalloc(ptr, bytes); };
+  if ((e = alloc((void**)&g->cell_start, sizeof(int32_t) * (ncells + 1))) != hipSuccess ||
+      (e = alloc((void**)&g->sx, sizeof(float) * n)) != hipSuccess ||
+      (e = alloc((void**)&g->sy, sizeof(float) * n)) != hipSuccess ||
+      (e = alloc((void**)&g->sidx, sizeof(int32_t) * n)) != hipSuccess)
+    return cleanup(hip_fail(e, "allocating grid arrays"));
+  {
+    Temps t(s);
+    uint32_t *keys, *vals, *tk, *tv, *hist, *scan;
+    if ((e = t.get(&keys, n)) != hipSuccess || (e = t.get(&vals, n)) != hipSuccess ||
+        (e = t.get(&tk, n)) != hipSuccess || (e = t.get(&tv, n)) != hipSuccess ||
+        (e = t.get(&hist, radix_hist_words((int)n))) != hipSuccess ||
+        (e = t.get(&scan, radix_scan_tmp_words((int)n))) != hipSuccess)
+      return cleanup(hip_fail(e, "allocating sort buffers"));
+    if ((e = launch_cell_keys(x, y, (int)n, g->dev, keys, vals, s)) != hipSuccess)
+      return cleanup(hip_fail(e, "cell key kernel"));
+    if ((e = radix_sort_pairs(keys, vals, tk, tv, (int)n, bits_for(ncells), hist, scan, s)) != hipSuccess)
+      return cleanup(hip_fail(e, "radix sort"));
+    if ((e = launch_cell_start_gather(keys, vals, (int)n, ncells, x, y, g->cell_start, g->sx, g->sy, g->sidx, s)) !=
+        hipSuccess)
+      return cleanup(hip_fail(e, "cell offsets / gather"));
+  }
+  *out = g;
+  return AIDW_OK;
+}
+
+aidw_status check_data(const float* x, const float* y, int64_t n, const float* qx, const float* qy, int64_t m) {
+  if (!x || !y) return fail(AIDW_EINVAL, "x / y is NULL");
+  if (n < 1) return fail(AIDW_EINVAL, "n = %lld: need at least one data point", (long long)n);
+  if (n > INT32_MAX) return fail(AIDW_ECAPACITY, "n = %lld exceeds INT32_MAX", (long long)n);
+  if (m < 0) return fail(AIDW_EINVAL, "m = %lld < 0", (long long)m);
+  if (m > INT32_MAX) return fail(AIDW_ECAPACITY, "m = %lld exceeds INT32_MAX", (long long)m);
+  if (m > 0 && (!qx || !qy)) return fail(AIDW_EINVAL, "qx / qy is NULL");
+  return AIDW_OK;
+}
+
+aidw_status knn_impl(const aidw_grid* g, const float* qx, const float* qy, int64_t m, int32_t k, float* r_obs,
+                     float* d1sq, int32_t* nn_idx, hipStream_t s) {
+  Temps t(s);
+  uint32_t *keys, *vals, *tk, *tv, *hist, *scan;
+  hipError_t e;
+  if ((e = t.get(&keys, m)) != hipSuccess || (e = t.get(&vals, m)) != hipSuccess || (e = t.get(&tk, m)) != hipSuccess ||
+      (e = t.get(&tv, m)) != hipSuccess || (e = t.get(&hist, radix_hist_words((int)m))) != hipSuccess ||
+      (e = t.get(&scan, radix_scan_tmp_words((int)m))) != hipSuccess)
+    return hip_fail(e, "allocating query-binning buffers");
+  // bin the queries with the data's cell formula, then sort them by cell
+  HIP_TRY(launch_cell_keys(qx, qy, (int)m, g->dev, keys, vals, s), "query key kernel");
+  HIP_TRY(radix_sort_pairs(keys, vals, tk, tv, (int)m, bits_for(g->host.ncells), hist, scan, s), "query sort");
+  HIP_TRY(launch_knn(g->dev, g->cell_start, g->sx, g->sy, g->sidx, qx, qy, vals, (int)m, k, slack_cells(g->host), r_obs,
+                     d1sq, nn_idx, s),
+          "kNN kernel");
+  return AIDW_OK;
+}
+
+void choose_interp_config(int64_t n, int64_t m, int* q, int* split) {
+  // Aim for >= 4 wavefronts per SIMD (256 CUs x 4 SIMDs) with 4 queries per lane;
+  // split the data axis when there are too few queries, keeping >= 2048 points per split.
+  int qq = g_cfg_q ? g_cfg_q : 4;
+  int64_t waves = (m + 64LL * qq - 1) / (64LL * qq);
+  int sp = 1;
+  if (g_cfg_split) {
+    sp = g_cfg_split;
+  } else {
+    const int64_t target = 4096;
+    while (waves * sp < target && (n / (sp * 2)) >= 2048 && sp < 1024) sp *= 2;
+  }
+  if (sp > n) sp = (int)n;
+  *q = qq;
+  *split = sp < 1 ? 1 : sp;
+}
+
+aidw_status interp_impl(const float* x, const float* y, const float* z, int64_t n, const float* qx, const float* qy,
+                        int64_t m, const float* r_obs, const float* d1sq, const aidw_params* p, const aidw_grid* g,
+                        float* qz, float* alpha_out, hipStream_t s, hipEvent_t ev_begin, hipEvent_t ev_end,
+                        int* used_q, int* used_split) {
+  double area = p->area > 0 ? p->area : (g ? g->host.area : 0.0);
+  if (!(area > 0)) return fail(AIDW_EINVAL, "aidw_interpolate needs params.area > 0 or a grid");
+  AlphaParams ap;
+  ap.r_exp = (g && !(p->area > 0) && g->n == n) ? g->host.r_exp : 1.0 / (2.0 * sqrt((double)n / area));
+  ap.r_min = p->r_min;
+  ap.r_max = p->r_max;
+  for (int i = 0; i < 5; ++i) ap.levels[i] = p->alpha[i];
+  int q, split;
+  choose_interp_config(n, m, &q, &split);
+  if (used_q) *used_q = q;
+  if (used_split) *used_split = split;
+  Temps t(s);
+  double2* partial = nullptr;
+  uint32_t *count, *list;
+  hipError_t e;
+  if (split > 1 && (e = t.get(&partial, (size_t)split * m)) != hipSuccess) return hip_fail(e, "allocating partials");
+  if ((e = t.get(&count, 1)) != hipSuccess || (e = t.get(&list, m)) != hipSuccess)
+    return hip_fail(e, "allocating coincidence list");
+  HIP_TRY(hipMemsetAsync(count, 0, sizeof(uint32_t), s), "clearing coincidence count");
+  HIP_TRY(launch_coincident_list(d1sq, (int)m, count, list, s), "coincidence list kernel");
+  if (ev_begin) HIP_TRY(hipEventRecord(ev_begin, s), "event");
+  HIP_TRY(launch_interp(x, y, z, (int)n, qx, qy, r_obs, d1sq, (int)m, ap, q, split, qz, partial, alpha_out, s),
+          "interpolation kernel");
+  if (ev_end) HIP_TRY(hipEventRecord(ev_end, s), "event");
+  if (split > 1) HIP_TRY(launch_combine(partial, (int)m, split, qz, s), "combine kernel");
+  if (g && g->n == n)
+    HIP_TRY(launch_fixup_grid(count, list, qx, qy, g->dev, g->cell_start, g->sx, g->sy, g->sidx, z, qz, s),
+            "coincidence fix-up kernel");
+  else
+    HIP_TRY(launch_fixup_scan(count, list, qx, qy, x, y, z, (int)n, qz, s), "coincidence fix-up kernel");
+  return AIDW_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void aidw_params_default(aidw_params* p) {
+  if (!p) return;
+  p->k = 10;
+  for (int i = 0; i < 5; ++i) p->alpha[i] = i + 1.0;
+  p->r_min = 0.0;
+  p->r_max = 2.0;
+  p->area = 0.0;
+  p->cell_width = 0.0;
+  p->occupancy = 2.0;
+}
+
+aidw_status aidw_build_grid(const float* x, const float* y, int64_t n, const float* qx, const float* qy, int64_t m,
+                            const aidw_params* p, hipStream_t stream, aidw_grid** out) {
+  g_detail.clear();
+  if (!out) return fail(AIDW_EINVAL, "out is NULL");
+  *out = nullptr;
+  aidw_status st = check_data(x, y, n, qx, qy, m);
+  if (st != AIDW_OK) return st;
+  if ((st = check_params(p)) != AIDW_OK) return st;
+  return build_grid_impl(x, y, n, qx, qy, m, p, stream, false, out);
+}
+
+aidw_status aidw_grid_describe(const aidw_grid* g, aidw_grid_desc* out) {
+  if (!g || !out) return fail(AIDW_EINVAL, "grid / out is NULL");
+  out->n = g->n;
+  out->min_x = g->host.minx;
+  out->min_y = g->host.miny;
+  out->max_x = g->host.maxx;
+  out->max_y = g->host.maxy;
+  out->area = g->host.area;
+  out->r_exp = g->host.r_exp;
+  out->cell_width = g->host.cw;
+  out->inv_cell_width = g->host.inv_cw;
+  out->ncol = g->host.ncol;
+  out->nrow = g->host.nrow;
+  return AIDW_OK;
+}
+
+aidw_status aidw_grid_arrays(const aidw_grid* g, const int32_t** cell_start, const float** sx, const float** sy,
+                             const int32_t** sidx) {
+  if (!g) return fail(AIDW_EINVAL, "grid is NULL");
+  if (cell_start) *cell_start = g->cell_start;
+  if (sx) *sx = g->sx;
+  if (sy) *sy = g->sy;
+  if (sidx) *sidx = g->sidx;
+  return AIDW_OK;
+}
+
+aidw_status aidw_grid_copy_arrays(const aidw_grid* g, int32_t* cell_start, float* sx, float* sy, int32_t* sidx,
+                                  hipStream_t stream) {
+  if (!g) return fail(AIDW_EINVAL, "grid is NULL");
+  const size_t n = (size_t)g->n;
+  if (cell_start)
+    HIP_TRY(hipMemcpyAsync(cell_start, g->cell_start, sizeof(int32_t) * (size_t)(g->host.ncells + 1),
+                           hipMemcpyDeviceToDevice, stream),
+            "copying cell_start");
+  if (sx) HIP_TRY(hipMemcpyAsync(sx, g->sx, sizeof(float) * n, hipMemcpyDeviceToDevice, stream), "copying sx");
+  if (sy) HIP_TRY(hipMemcpyAsync(sy, g->sy, sizeof(float) * n, hipMemcpyDeviceToDevice, stream), "copying sy");
+  if (sidx) HIP_TRY(hipMemcpyAsync(sidx, g->sidx, sizeof(int32_t) * n, hipMemcpyDeviceToDevice, stream), "copying sidx");
+  return AIDW_OK;
+}
+
+void aidw_grid_destroy(aidw_grid* g) {
+  if (!g) return;
+  void* ptrs[5] = {g->dev, g->cell_start, g->sx, g->sy, g->sidx};
+  for (void* p : ptrs) {
+    if (!p) continue;
+    if (g->async)
+      (void)hipFreeAsync(p, g->async_stream);
+    else
+      (void)hipFree(p);
+  }
+  delete g;
+}
+
+aidw_status aidw_knn(const aidw_grid* g, const float* qx, const float* qy, int64_t m, int32_t k, float* r_obs,
+                     float* d1sq, int32_t* nn_idx, hipStream_t stream) {
+  g_detail.clear();
+  if (!g) return fail(AIDW_EINVAL, "grid is NULL");
+  if (m < 0) return fail(AIDW_EINVAL, "m = %lld < 0", (long long)m);
+  if (m > INT32_MAX) return fail(AIDW_ECAPACITY, "m exceeds INT32_MAX");
+  if (k < 1 || k > AIDW_KMAX || k > g->n)
+    return fail(AIDW_EINVAL, "k = %d must be in [1, min(n = %lld, %d)]", k, (long long)g->n, AIDW_KMAX);
+  if (m == 0) return AIDW_OK;
+  if (!qx || !qy || !r_obs) return fail(AIDW_EINVAL, "qx / qy / r_obs is NULL");
+  if ((int64_t)m * k > INT32_MAX && nn_idx) return fail(AIDW_ECAPACITY, "m * k exceeds INT32_MAX");
+  return knn_impl(g, qx, qy, m, k, r_obs, d1sq, nn_idx, stream);
+}
+
+aidw_status aidw_interpolate(const float* x, const float* y, const float* z, int64_t n, const float* qx,
+                             const float* qy, int64_t m, const float* r_obs, const float* d1sq, const aidw_params* p,
+                             const aidw_grid* g, float* qz, float* alpha_out, hipStream_t stream) {
+  g_detail.clear();
+  aidw_status st = check_data(x, y, n, qx, qy, m);
+  if (st != AIDW_OK) return st;
+  if (!z) return fail(AIDW_EINVAL, "z is NULL");
+  if ((st = check_params(p)) != AIDW_OK) return st;
+  if (m == 0) return AIDW_OK;
+  if (!r_obs || !d1sq || !qz) return fail(AIDW_EINVAL, "r_obs / d1sq / qz is NULL");
+  return interp_impl(x, y, z, n, qx, qy, m, r_obs, d1sq, p, g, qz, alpha_out, stream, nullptr, nullptr, nullptr,
+                     nullptr);
+}
+
+aidw_status aidw_run(const float* x, const float* y, const float* z, int64_t n, const float* qx, const float* qy,
+                     int64_t m, const aidw_params* p, float* qz, float* alpha_out, float* r_obs_out,
+                     hipStream_t stream) {
+  g_detail.clear();
+  aidw_status st = check_data(x, y, n, qx, qy, m);
+  if (st != AIDW_OK) return st;
+  if (!z) return fail(AIDW_EINVAL, "z is NULL");
+  if ((st = check_params(p)) != AIDW_OK) return st;
+  if (p->k < 1 || p->k > AIDW_KMAX || p->k > n)
+    return fail(AIDW_EINVAL, "k = %d must be in [1, min(n = %lld, %d)]", p->k, (long long)n, AIDW_KMAX);
+  if (m == 0) return AIDW_OK;
+  if (!qz) return fail(AIDW_EINVAL, "qz is NULL");
+  hipEvent_t* ev = nullptr;
+  if (g_timing) {
+    for (auto& e : g_tm.ev)
+      if (!e) HIP_TRY(hipEventCreate(&e), "creating timing events");
+    ev = g_tm.ev;
+    g_tm.valid = false;
+    HIP_TRY(hipEventRecord(ev[0], stream), "event");
+  }
+  aidw_grid* g = nullptr;
+  if ((st = build_grid_impl(x, y, n, qx, qy, m, p, stream, true, &g)) != AIDW_OK) return st;
+  if (ev) {
+    hipError_t e = hipEventRecord(ev[1], stream);
+    if (e != hipSuccess) {
+      aidw_grid_destroy(g);
+      return hip_fail(e, "event");
+    }
+  }
+  {
+    Temps t(stream);
+    float *robs = r_obs_out, *d1sq = nullptr;
+    hipError_t e = hipSuccess;
+    if (!robs) e = t.get(&robs, m);
+    if (e == hipSuccess) e = t.get(&d1sq, m);
+    if (e != hipSuccess) st = hip_fail(e, "allocating r_obs / d1sq");
+    if (st == AIDW_OK) st = knn_impl(g, qx, qy, m, p->k, robs, d1sq, nullptr, stream);
+    int q = 0, split = 0;
+    if (st == AIDW_OK)
+      st = interp_impl(x, y, z, n, qx, qy, m, robs, d1sq, p, g, qz, alpha_out, stream, ev ? ev[2] : nullptr,
+                       ev ? ev[3] : nullptr, &q, &split);
+    if (st == AIDW_OK && ev) {
+      if ((e = hipEventRecord(ev[4], stream)) != hipSuccess) st = hip_fail(e, "event");
+      g_tm.valid = st == AIDW_OK;
+      g_tm.q = q;
+      g_tm.split = split;
+    }
+  }
+  aidw_grid_destroy(g);
+  return st;
+}
+
+aidw_status aidw_set_timing(int enable) {
+  g_timing = enable ? 1 : 0;
+  if (!enable) g_tm.valid = false;
+  return AIDW_OK;
+}
+
+aidw_status aidw_last_timing(aidw_timing* out) {
+  if (!out) return fail(AIDW_EINVAL, "out is NULL");
+  if (!g_timing || !g_tm.valid) return fail(AIDW_EINVAL, "no timed run (enable with aidw_set_timing(1))");
+  HIP_TRY(hipEventSynchronize(g_tm.ev[4]), "waiting for timed run");
+  float a = 0, b = 0, c = 0, d = 0;
+  HIP_TRY(hipEventElapsedTime(&a, g_tm.ev[0], g_tm.ev[1]), "event time");
+  HIP_TRY(hipEventElapsedTime(&b, g_tm.ev[1], g_tm.ev[2]), "event time");
+  HIP_TRY(hipEventElapsedTime(&c, g_tm.ev[2], g_tm.ev[3]), "event time");
+  HIP_TRY(hipEventElapsedTime(&d, g_tm.ev[3], g_tm.ev[4]), "event time");
+  out->grid_ms = a;
+  out->knn_ms = b;
+  out->interp_ms = c;
+  out->finish_ms = d;
+  out->interp_q = g_tm.q;
+  out->interp_split = g_tm.split;
+  return AIDW_OK;
+}
+
+aidw_status aidw_set_interp_config(int32_t q, int32_t split) {
+  if (!(q == 0 || q == 1 || q == 2 || q == 4 || q == 8)) return fail(AIDW_EINVAL, "q must be 0, 1, 2, 4 or 8");
+  if (split < 0) return fail(AIDW_EINVAL, "split must be >= 0");
+  g_cfg_q = q;
+  g_cfg_split = split;
+  return AIDW_OK;
+}
+
+const char* aidw_status_string(aidw_status st) {
+  switch (st) {
+    case AIDW_OK: return "ok";
+    case AIDW_EINVAL: return "invalid argument";
+    case AIDW_EDEGENERATE: return "degenerate study area";
+    case AIDW_ENOMEM: return "out of device memory";
+    case AIDW_EDEVICE: return "HIP runtime error";
+    case AIDW_ENONFINITE: return "non-finite coordinate";
+    case AIDW_ECAPACITY: return "capacity exceeded";
+  }
+  return "unknown status";
+}
+
+const char* aidw_last_error_detail(void) { return g_detail.c_str(); }
+
+const char* aidw_version(void) { return "aidw-mi355x 0.1 (gfx950)"; }
+
+}  // extern "C"

@@ -1,0 +1,396 @@
+// Stage 1, grid build (Section 3.2.1-3.2.3 and 4.1.1-4.1.3 of the paper):
+//   bounds over data and queries -> grid scalars (Eq. 2) -> cell key per data
+//   point -> stable LSD radix sort of (cell, index) -> CSR cell offsets and the
+//   data coordinates gathered into cell order.
+// The paper sorts with a library sort_by_key and recovers per-cell size and head
+// with segmented reduce / unique; here one stable counting sort per 8-bit digit
+// produces the same cell-ordered segments, and the CSR offsets (head of cell c =
+// cell_start[c], size = cell_start[c+1] - cell_start[c]) come from a binary
+// search over the sorted keys, which also covers empty cells.
+#include "aidw_internal.h"
+
+namespace aidw {
+
+namespace {
+
+__device__ inline float wave_min(float v) {
+  for (int o = 32; o > 0; o >>= 1) v = fminf(v, __shfl_xor(v, o, 64));
+  return v;
+}
+__device__ inline float wave_max(float v) {
+  for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
+  return v;
+}
+__device__ inline int wave_or(int v) {
+  for (int o = 32; o > 0; o >>= 1) v |= __shfl_xor(v, o, 64);
+  return v;
+}
+
+// Per-block min / max of x and y over the data points followed by the queries
+// (Section 4.1.1: the grid encloses both sets), plus a non-finite flag.
+__global__ __launch_bounds__(kBoundsThreads) void k_bounds(const float* __restrict__ x, const float* __restrict__ y,
+                                                           int n, const float* __restrict__ qx,
+                                                           const float* __restrict__ qy, int m,
+                                                           BoundsPartial* __restrict__ partial) {
+  float mnx = INFINITY, mny = INFINITY, mxx = -INFINITY, mxy = -INFINITY;
+  int bad = 0;
+  const int64_t total = (int64_t)n + m;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    float a, b;
+    if (e < n) {
+      a = x[e];
+      b = y[e];
+    } else {
+      a = qx[e - n];
+      b = qy[e - n];
+    }
+    bad |= !(isfinite(a) && isfinite(b));
+    mnx = fminf(mnx, a);
+    mxx = fmaxf(mxx, a);
+    mny = fminf(mny, b);
+    mxy = fmaxf(mxy, b);
+  }
+  mnx = wave_min(mnx);
+  mny = wave_min(mny);
+  mxx = wave_max(mxx);
+  mxy = wave_max(mxy);
+  bad = wave_or(bad);
+  __shared__ BoundsPartial s[kBoundsThreads / 64];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 0) s[wave] = BoundsPartial{mnx, mny, mxx, mxy, bad, {0, 0, 0}};
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    BoundsPartial r = s[0];
+    for (int w = 1; w < kBoundsThreads / 64; ++w) {
+      r.minx = fminf(r.minx, s[w].minx);
+      r.miny = fminf(r.miny, s[w].miny);
+      r.maxx = fmaxf(r.maxx, s[w].maxx);
+      r.maxy = fmaxf(r.maxy, s[w].maxy);
+      r.nonfinite |= s[w].nonfinite;
+    }
+    partial[blockIdx.x] = r;
+  }
+}
+
+// Reduces the partials and derives the grid scalars (Eq. 2, Section 4.1.1), in
+// float64: A = bounding-box area unless given, r_exp = 1 / (2 sqrt(n / A)),
+// cell side = given or sqrt(occ * A / n), nCol = (int)((W + cw) / cw), nRow likewise.
+__global__ __launch_bounds__(256) void k_finalize(const BoundsPartial* __restrict__ partial, int nparts, int64_t n,
+                                                  double area_in, double cw_in, double occ,
+                                                  GridScalars* __restrict__ out) {
+  float mnx = INFINITY, mny = INFINITY, mxx = -INFINITY, mxy = -INFINITY;
+  int bad = 0;
+  for (int i = threadIdx.x; i < nparts; i += blockDim.x) {
+    mnx = fminf(mnx, partial[i].minx);
+    mny = fminf(mny, partial[i].miny);
+    mxx = fmaxf(mxx, partial[i].maxx);
+    mxy = fmaxf(mxy, partial[i].maxy);
+    bad |= partial[i].nonfinite;
+  }
+  mnx = wave_min(mnx);
+  mny = wave_min(mny);
+  mxx = wave_max(mxx);
+  mxy = wave_max(mxy);
+  bad = wave_or(bad);
+  __shared__ BoundsPartial s[4];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 0) s[wave] = BoundsPartial{mnx, mny, mxx, mxy, bad, {0, 0, 0}};
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  for (int w = 1; w < 4; ++w) {
+    s[0].minx = fminf(s[0].minx, s[w].minx);
+    s[0].miny = fminf(s[0].miny, s[w].miny);
+    s[0].maxx = fmaxf(s[0].maxx, s[w].maxx);
+    s[0].maxy = fmaxf(s[0].maxy, s[w].maxy);
+    s[0].nonfinite |= s[w].nonfinite;
+  }
+  GridScalars g{};
+  g.minx = s[0].minx;
+  g.miny = s[0].miny;
+  g.maxx = s[0].maxx;
+  g.maxy = s[0].maxy;
+  g.status = AIDW_OK;
+  if (s[0].nonfinite) {
+    g.status = AIDW_ENONFINITE;
+    *out = g;
+    return;
+  }
+  const double W = (double)g.maxx - (double)g.minx;
+  const double H = (double)g.maxy - (double)g.miny;
+  const double area = area_in > 0 ? area_in : W * H;
+  if (!(area > 0) || !isfinite(area)) {
+    g.status = AIDW_EDEGENERATE;
+    *out = g;
+    return;
+  }
+  g.area = area;
+  g.r_exp = 1.0 / (2.0 * sqrt((double)n / area));
+  const double cw = cw_in > 0 ? cw_in : sqrt(occ * area / (double)n);
+  const double fc = (W + cw) / cw;
+  const double fr = (H + cw) / cw;
+  if (!(cw > 0) || !(fc < (double)AIDW_MAX_CELLS) || !(fr < (double)AIDW_MAX_CELLS)) {
+    g.status = AIDW_ECAPACITY;
+    *out = g;
+    return;
+  }
+  g.ncol = (int32_t)fc;
+  g.nrow = (int32_t)fr;
+  g.ncells = (int64_t)g.ncol * g.nrow;
+  if (g.ncells > AIDW_MAX_CELLS) {
+    g.status = AIDW_ECAPACITY;
+    *out = g;
+    return;
+  }
+  g.cw = cw;
+  g.inv_cw = (float)(1.0 / cw);
+  g.cwd = 1.0 / (double)g.inv_cw;
+  *out = g;
+}
+
+// Section 4.1.2: cell of each data point, (x - minX) * inv_cw in float32 truncated,
+// clamped into the grid; key = row * nCol + col, value = original index.
+__global__ __launch_bounds__(256) void k_cell_keys(const float* __restrict__ x, const float* __restrict__ y, int n,
+                                                   const GridScalars* __restrict__ gs, uint32_t* __restrict__ keys,
+                                                   uint32_t* __restrict__ vals) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float minx = gs->minx, miny = gs->miny, inv = gs->inv_cw;
+  const int ncol = gs->ncol, nrow = gs->nrow;
+  const float tx = (x[i] - minx) * inv;
+  const float ty = (y[i] - miny) * inv;
+  int col = (int)tx, row = (int)ty;
+  col = col > ncol - 1 ? ncol - 1 : (col < 0 ? 0 : col);
+  row = row > nrow - 1 ? nrow - 1 : (row < 0 ? 0 : row);
+  keys[i] = (uint32_t)(row * ncol + col);
+  vals[i] = (uint32_t)i;
+}
+
+// ---- stable LSD radix sort ------------------------------------------------------
+
+__global__ __launch_bounds__(kSortThreads) void k_radix_hist(const uint32_t* __restrict__ keys, int n, int shift,
+                                                             uint32_t* __restrict__ hist, int nblocks) {
+  __shared__ uint32_t h[kRadix];
+  for (int i = threadIdx.x; i < kRadix; i += kSortThreads) h[i] = 0;
+  __syncthreads();
+  const int base = blockIdx.x * kSortTile;
+  for (int r = 0; r < kSortItems; ++r) {
+    const int i = base + r * kSortThreads + threadIdx.x;
+    if (i < n) atomicAdd(&h[(keys[i] >> shift) & (kRadix - 1)], 1u);
+  }
+  __syncthreads();
+  for (int d = threadIdx.x; d < kRadix; d += kSortThreads) hist[(size_t)d * nblocks + blockIdx.x] = h[d];
+}
+
+constexpr int kScanThreads = 256;
+constexpr int kScanItems = 16;
+constexpr int kScanChunk = kScanThreads * kScanItems;
+
+// Exclusive block scan of one value per thread; returns the block total in *total.
+__device__ inline uint32_t block_exclusive_scan(uint32_t v, uint32_t* total) {
+  __shared__ uint32_t wsum[kScanThreads / 64];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  uint32_t incl = v;
+  for (int o = 1; o < 64; o <<= 1) {
+    uint32_t t = __shfl_up(incl, o, 64);
+    if (lane >= o) incl += t;
+  }
+  if (lane == 63) wsum[wave] = incl;
+  __syncthreads();
+  uint32_t wpre = 0, tot = 0;
+  for (int w = 0; w < kScanThreads / 64; ++w) {
+    if (w < wave) wpre += wsum[w];
+    tot += wsum[w];
+  }
+  __syncthreads();
+  *total = tot;
+  return wpre + incl - v;
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_scan_reduce(const uint32_t* __restrict__ in, size_t len,
+                                                              uint32_t* __restrict__ sums) {
+  const size_t base = (size_t)blockIdx.x * kScanChunk + (size_t)threadIdx.x * kScanItems;
+  uint32_t s = 0;
+  for (int i = 0; i < kScanItems; ++i)
+    if (base + i < len) s += in[base + i];
+  uint32_t tot;
+  block_exclusive_scan(s, &tot);
+  if (threadIdx.x == 0) sums[blockIdx.x] = tot;
+}
+
+// Exclusive scan of the block sums in place (one block, any length).
+__global__ __launch_bounds__(kScanThreads) void k_scan_top(uint32_t* __restrict__ sums, int nsums) {
+  uint32_t carry = 0;
+  for (int base = 0; base < nsums; base += kScanThreads) {
+    const int i = base + threadIdx.x;
+    const uint32_t v = i < nsums ? sums[i] : 0u;
+    uint32_t tot;
+    const uint32_t ex = block_exclusive_scan(v, &tot);
+    if (i < nsums) sums[i] = carry + ex;
+    carry += tot;
+  }
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_scan_down(const uint32_t* __restrict__ in, size_t len,
+                                                            const uint32_t* __restrict__ sums,
+                                                            uint32_t* __restrict__ out) {
+  const size_t base = (size_t)blockIdx.x * kScanChunk + (size_t)threadIdx.x * kScanItems;
+  uint32_t v[kScanItems];
+  uint32_t s = 0;
+  for (int i = 0; i < kScanItems; ++i) {
+    v[i] = base + i < len ? in[base + i] : 0u;
+    s += v[i];
+  }
+  uint32_t tot;
+  uint32_t run = sums[blockIdx.x] + block_exclusive_scan(s, &tot);
+  for (int i = 0; i < kScanItems; ++i) {
+    if (base + i < len) out[base + i] = run;
+    run += v[i];
+  }
+}
+
+// Stable scatter of one digit: within a block, elements are taken in index order,
+// one per thread per round; a wavefront ranks equal digits with ballots, waves
+// are ordered by an LDS prefix, rounds by a running per-digit base.
+__global__ __launch_bounds__(kSortThreads) void k_radix_scatter(const uint32_t* __restrict__ kin,
+                                                                const uint32_t* __restrict__ vin,
+                                                                uint32_t* __restrict__ kout,
+                                                                uint32_t* __restrict__ vout, int n, int shift,
+                                                                const uint32_t* __restrict__ offs, int nblocks) {
+  constexpr int W = kSortThreads / 64;
+  __shared__ uint32_t base[kRadix];
+  __shared__ uint32_t wcnt[W][kRadix];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  for (int d = tid; d < kRadix; d += kSortThreads) base[d] = offs[(size_t)d * nblocks + blockIdx.x];
+  const uint64_t lt_mask = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+  const int tile = blockIdx.x * kSortTile;
+  for (int r = 0; r < kSortItems; ++r) {
+    for (int d = lane; d < kRadix; d += 64) wcnt[wave][d] = 0;
+    __syncthreads();
+    const int i = tile + r * kSortThreads + tid;
+    const bool valid = i < n;
+    const uint32_t key = valid ? kin[i] : 0u;
+    const uint32_t val = valid ? vin[i] : 0u;
+    const uint32_t d = (key >> shift) & (kRadix - 1);
+    uint64_t match = __ballot(valid);
+#pragma unroll
+    for (int b = 0; b < kRadixBits; ++b) {
+      const bool bit = (d >> b) & 1u;
+      const uint64_t bb = __ballot(bit);
+      match &= bit ? bb : ~bb;
+    }
+    const uint32_t rank = __popcll(match & lt_mask);
+    if (valid && rank == 0) wcnt[wave][d] = __popcll(match);
+    __syncthreads();
+    if (valid) {
+      uint32_t pre = 0;
+      for (int w = 0; w < wave; ++w) pre += wcnt[w][d];
+      const uint32_t pos = base[d] + pre + rank;
+      kout[pos] = key;
+      vout[pos] = val;
+    }
+    __syncthreads();
+    for (int dd = tid; dd < kRadix; dd += kSortThreads) {
+      uint32_t tot = 0;
+      for (int w = 0; w < W; ++w) tot += wcnt[w][dd];
+      base[dd] += tot;
+    }
+    __syncthreads();
+  }
+}
+
+// CSR offsets: cell_start[c] = first sorted position whose key >= c (c = 0 .. ncells).
+__global__ __launch_bounds__(256) void k_cell_start(const uint32_t* __restrict__ keys, int n, int64_t ncells,
+                                                    int32_t* __restrict__ start) {
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c > ncells) return;
+  int lo = 0, hi = n;
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if ((int64_t)keys[mid] < c)
+      lo = mid + 1;
+    else
+      hi = mid;
+  }
+  start[c] = lo;
+}
+
+__global__ __launch_bounds__(256) void k_gather(const uint32_t* __restrict__ vals, int n, const float* __restrict__ x,
+                                                const float* __restrict__ y, float* __restrict__ sx,
+                                                float* __restrict__ sy, int32_t* __restrict__ sidx) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n) return;
+  const uint32_t v = vals[p];
+  sx[p] = x[v];
+  sy[p] = y[v];
+  sidx[p] = (int32_t)v;
+}
+
+inline int div_up(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
+
+}  // namespace
+
+hipError_t launch_bounds(const float* x, const float* y, int n, const float* qx, const float* qy, int m,
+                         BoundsPartial* partial, hipStream_t s) {
+  hipLaunchKernelGGL(k_bounds, dim3(kBoundsBlocks), dim3(kBoundsThreads), 0, s, x, y, n, qx, qy, m, partial);
+  return hipGetLastError();
+}
+
+hipError_t launch_finalize(const BoundsPartial* partial, int nparts, int64_t n, double area_in, double cw_in,
+                           double occ, GridScalars* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, s, partial, nparts, n, area_in, cw_in, occ, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_cell_keys(const float* x, const float* y, int n, const GridScalars* gs, uint32_t* keys,
+                            uint32_t* vals, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_cell_keys, dim3(div_up(n, 256)), dim3(256), 0, s, x, y, n, gs, keys, vals);
+  return hipGetLastError();
+}
+
+size_t radix_hist_words(int n) { return (size_t)kRadix * (size_t)div_up(n > 0 ? n : 1, kSortTile); }
+
+size_t radix_scan_tmp_words(int n) { return (size_t)div_up((int64_t)radix_hist_words(n), kScanChunk) + 1; }
+
+hipError_t radix_sort_pairs(uint32_t* keys, uint32_t* vals, uint32_t* tmp_keys, uint32_t* tmp_vals, int n, int bits,
+                            uint32_t* hist, uint32_t* scan_tmp, hipStream_t s) {
+  if (n <= 1 || bits <= 0) return hipSuccess;
+  const int nblocks = div_up(n, kSortTile);
+  const size_t hlen = (size_t)kRadix * nblocks;
+  const int nsb = div_up((int64_t)hlen, kScanChunk);
+  uint32_t *ki = keys, *vi = vals, *ko = tmp_keys, *vo = tmp_vals;
+  int passes = 0;
+  for (int shift = 0; shift < bits; shift += kRadixBits, ++passes) {
+    hipLaunchKernelGGL(k_radix_hist, dim3(nblocks), dim3(kSortThreads), 0, s, ki, n, shift, hist, nblocks);
+    hipLaunchKernelGGL(k_scan_reduce, dim3(nsb), dim3(kScanThreads), 0, s, hist, hlen, scan_tmp);
+    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kScanThreads), 0, s, scan_tmp, nsb);
+    hipLaunchKernelGGL(k_scan_down, dim3(nsb), dim3(kScanThreads), 0, s, hist, hlen, scan_tmp, hist);
+    hipLaunchKernelGGL(k_radix_scatter, dim3(nblocks), dim3(kSortThreads), 0, s, ki, vi, ko, vo, n, shift, hist,
+                       nblocks);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    uint32_t* t = ki;
+    ki = ko;
+    ko = t;
+    t = vi;
+    vi = vo;
+    vo = t;
+  }
+  if (passes & 1) {  // result is in the temporaries: copy back
+    hipError_t e = hipMemcpyAsync(keys, ki, sizeof(uint32_t) * n, hipMemcpyDeviceToDevice, s);
+    if (e != hipSuccess) return e;
+    e = hipMemcpyAsync(vals, vi, sizeof(uint32_t) * n, hipMemcpyDeviceToDevice, s);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+hipError_t launch_cell_start_gather(const uint32_t* keys, const uint32_t* vals, int n, int64_t ncells, const float* x,
+                                    const float* y, int32_t* cell_start, float* sx, float* sy, int32_t* sidx,
+                                    hipStream_t s) {
+  hipLaunchKernelGGL(k_cell_start, dim3(div_up(ncells + 1, 256)), dim3(256), 0, s, keys, n, ncells, cell_start);
+  if (sx) hipLaunchKernelGGL(k_gather, dim3(div_up(n, 256)), dim3(256), 0, s, vals, n, x, y, sx, sy, sidx);
+  return hipGetLastError();
+}
+
+}  // namespace aidw

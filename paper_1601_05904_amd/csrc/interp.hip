@@ -1,0 +1,320 @@
+// Stage 2: adaptive power (Eq. 2, 4, 5, 6) and the weighted mean of Eq. 1 over
+// all n data points (Section 3.3, 4.2 of the paper).
+//
+// The paper's tiled kernel gives each thread one query and stages blocks of
+// data points through shared memory, so that all threads of a block reuse each
+// loaded point.  On CDNA the same reuse is available without LDS traffic: the
+// data index is the same for every lane of a wavefront, so the compiler
+// fetches each chunk of x, y, z once per wavefront with scalar loads into SGPRs
+// and every VALU instruction reads the point directly as a scalar operand.
+// Each lane holds Q queries, which gives Q independent dependency chains per
+// data point.  Per pair (query j, point i) the lane evaluates, in float32,
+//     d2 = (qx - x)^2 + (qy - y)^2,  t = d2 * s_j,  w = 2^(nh_j * log2 t),
+//     num += w z,  den += w,
+// with s_j = 1 / d1sq_j (d1 = nearest-neighbour distance) and nh_j = -alpha_j / 2,
+// i.e. w = (d1 / d)^alpha_j: the common factor d1^alpha cancels in num / den,
+// keeps w <= ~1 (no overflow for any alpha) and keeps the argument of log2 near
+// 1 for the dominant near points, where the hardware log2 is most accurate.
+// The float32 sums of each tile of kTile points are folded into (hi, lo)
+// two-sum pairs; the final num / den is formed in float64.  Splitting the data
+// axis (blockIdx.y) gives more wavefronts when m is small; the splits' float64
+// partials are then combined in split order by a second kernel.
+#include <float.h>
+
+#include "aidw_internal.h"
+
+namespace aidw {
+
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kChunk = 8;    // data points per scalar fetch
+constexpr int kTile = 256;   // data points per float32 partial before the two-sum fold
+
+// Eq. 5 as printed: 0 below R_min, 1 above R_max, else 0.5 - 0.5 cos(pi / R_max (R - R_min)).
+__device__ inline double fuzzy_mu(double R, double rmin, double rmax) {
+  if (R <= rmin) return 0.0;
+  if (R >= rmax) return 1.0;
+  return 0.5 - 0.5 * cos((M_PI / rmax) * (R - rmin));
+}
+
+// Eq. 6: piecewise-linear between the levels at mu = 0.1, 0.3, 0.5, 0.7, 0.9, constant outside.
+__device__ inline double level_alpha(double mu, const double* a) {
+  if (mu <= 0.1) return a[0];
+  if (mu <= 0.3) return a[0] * (1.0 - 5.0 * (mu - 0.1)) + 5.0 * a[1] * (mu - 0.1);
+  if (mu <= 0.5) return 5.0 * a[2] * (mu - 0.3) + a[1] * (1.0 - 5.0 * (mu - 0.3));
+  if (mu <= 0.7) return a[2] * (1.0 - 5.0 * (mu - 0.5)) + 5.0 * a[3] * (mu - 0.5);
+  if (mu <= 0.9) return 5.0 * a[4] * (mu - 0.7) + a[3] * (1.0 - 5.0 * (mu - 0.7));
+  return a[4];
+}
+
+struct Acc {
+  float num_t, den_t;   // current tile
+  float num_h, num_l;   // folded: two-sum hi / lo
+  float den_h, den_l;
+};
+
+__device__ inline void two_sum_fold(float& hi, float& lo, float v) {
+  const float s = hi + v;
+  const float bp = s - hi;
+  const float err = (hi - (s - bp)) + (v - bp);
+  hi = s;
+  lo += err;
+}
+
+template <int Q>
+struct Lane {
+  float qx[Q], qy[Q], nh[Q], sc[Q];
+  Acc acc[Q];
+
+  __device__ inline void pair(float x, float y, float z) {
+#pragma unroll
+    for (int j = 0; j < Q; ++j) {
+      const float dx = qx[j] - x;
+      const float dy = qy[j] - y;
+      const float d2 = __builtin_fmaf(dx, dx, dy * dy);
+      const float t = d2 * sc[j];
+      const float w = __builtin_amdgcn_exp2f(__builtin_amdgcn_logf(t) * nh[j]);
+      acc[j].num_t = __builtin_fmaf(w, z, acc[j].num_t);
+      acc[j].den_t += w;
+    }
+  }
+  __device__ inline void fold() {
+#pragma unroll
+    for (int j = 0; j < Q; ++j) {
+      two_sum_fold(acc[j].num_h, acc[j].num_l, acc[j].num_t);
+      two_sum_fold(acc[j].den_h, acc[j].den_l, acc[j].den_t);
+      acc[j].num_t = 0.0f;
+      acc[j].den_t = 0.0f;
+    }
+  }
+};
+
+template <int Q>
+__global__ __launch_bounds__(kThreads) void k_interp(const float* __restrict__ x, const float* __restrict__ y,
+                                                     const float* __restrict__ z, int n, int chunk,
+                                                     const float* __restrict__ qx, const float* __restrict__ qy,
+                                                     const float* __restrict__ r_obs, const float* __restrict__ d1sq,
+                                                     int m, AlphaParams ap, float* __restrict__ qz,
+                                                     double2* __restrict__ partial, float* __restrict__ alpha_out) {
+  Lane<Q> L;
+  const int qbase = blockIdx.x * kThreads * Q + threadIdx.x;
+  const int split = blockIdx.y;
+#pragma unroll
+  for (int j = 0; j < Q; ++j) {
+    const int q = qbase + j * kThreads;
+    float fx = 0.0f, fy = 0.0f, nh = 0.0f, sc = 1.0f;
+    if (q < m) {
+      fx = qx[q];
+      fy = qy[q];
+      const double R = (double)r_obs[q] / ap.r_exp;                          // Eq. 4
+      const double alpha = level_alpha(fuzzy_mu(R, ap.r_min, ap.r_max), ap.levels);  // Eq. 5, 6
+      if (alpha_out && split == 0) alpha_out[q] = (float)alpha;
+      nh = (float)(-0.5 * alpha);
+      const float d1 = d1sq[q];
+      sc = d1 > 0.0f ? (float)(1.0 / (double)d1) : 1.0f;  // d1 == 0: coincident query, fixed up later
+    }
+    L.qx[j] = fx;
+    L.qy[j] = fy;
+    L.nh[j] = nh;
+    L.sc[j] = sc;
+    L.acc[j] = Acc{0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+  }
+
+  const int lo = split * chunk;
+  const int hi = min(n, lo + chunk);
+  int p = lo;
+  for (; p + kTile <= hi; p += kTile) {
+    for (int c = 0; c < kTile; c += kChunk) {
+      float xs[kChunk], ys[kChunk], zs[kChunk];
+#pragma unroll
+      for (int i = 0; i < kChunk; ++i) {
+        xs[i] = x[p + c + i];
+        ys[i] = y[p + c + i];
+        zs[i] = z[p + c + i];
+      }
+#pragma unroll
+      for (int i = 0; i < kChunk; ++i) L.pair(xs[i], ys[i], zs[i]);
+    }
+    L.fold();
+  }
+  for (; p + kChunk <= hi; p += kChunk) {
+    float xs[kChunk], ys[kChunk], zs[kChunk];
+#pragma unroll
+    for (int i = 0; i < kChunk; ++i) {
+      xs[i] = x[p + i];
+      ys[i] = y[p + i];
+      zs[i] = z[p + i];
+    }
+#pragma unroll
+    for (int i = 0; i < kChunk; ++i) L.pair(xs[i], ys[i], zs[i]);
+  }
+  for (; p < hi; ++p) L.pair(x[p], y[p], z[p]);
+  L.fold();
+
+#pragma unroll
+  for (int j = 0; j < Q; ++j) {
+    const int q = qbase + j * kThreads;
+    if (q >= m) continue;
+    const double num = (double)L.acc[j].num_h + (double)L.acc[j].num_l;
+    const double den = (double)L.acc[j].den_h + (double)L.acc[j].den_l;
+    if (gridDim.y == 1)
+      qz[q] = (float)(num / den);
+    else
+      partial[(size_t)split * m + q] = make_double2(num, den);
+  }
+}
+
+__global__ __launch_bounds__(256) void k_combine(const double2* __restrict__ partial, int m, int split,
+                                                 float* __restrict__ qz) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= m) return;
+  double num = 0.0, den = 0.0;
+  for (int s = 0; s < split; ++s) {
+    const double2 v = partial[(size_t)s * m + q];
+    num += v.x;
+    den += v.y;
+  }
+  qz[q] = (float)(num / den);
+}
+
+// Queries whose nearest neighbour is at distance 0 coincide with data points.
+__global__ __launch_bounds__(256) void k_coincident_list(const float* __restrict__ d1sq, int m,
+                                                         uint32_t* __restrict__ count, uint32_t* __restrict__ list) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= m) return;
+  if (d1sq[q] == 0.0f) list[atomicAdd(count, 1u)] = (uint32_t)q;
+}
+
+__device__ inline int clamp_cell(float t, int nc) {
+  if (!(t >= 0.0f)) return 0;
+  if (t >= 2147483520.0f) return nc - 1;
+  const int c = (int)t;
+  return c > nc - 1 ? nc - 1 : c;
+}
+
+// Coincident query = mean z of the data points at its exact position (the limit
+// of Eq. 1).  Those points share the query's cell; the cell is ordered by index,
+// so the sum runs in index order.
+__global__ __launch_bounds__(256) void k_fixup_grid(const uint32_t* __restrict__ count,
+                                                    const uint32_t* __restrict__ list, const float* __restrict__ qx,
+                                                    const float* __restrict__ qy, const GridScalars* __restrict__ gs,
+                                                    const int32_t* __restrict__ cell_start,
+                                                    const float* __restrict__ sx, const float* __restrict__ sy,
+                                                    const int32_t* __restrict__ sidx, const float* __restrict__ z,
+                                                    float* __restrict__ qz) {
+  const uint32_t cnt = *count;
+  for (uint32_t e = blockIdx.x * blockDim.x + threadIdx.x; e < cnt; e += gridDim.x * blockDim.x) {
+    const uint32_t q = list[e];
+    const float fx = qx[q], fy = qy[q];
+    const int col = clamp_cell((fx - gs->minx) * gs->inv_cw, gs->ncol);
+    const int row = clamp_cell((fy - gs->miny) * gs->inv_cw, gs->nrow);
+    const int c = row * gs->ncol + col;
+    double s = 0.0;
+    int hits = 0;
+    for (int p = cell_start[c]; p < cell_start[c + 1]; ++p) {
+      if (sx[p] == fx && sy[p] == fy) {
+        s += (double)z[sidx[p]];
+        ++hits;
+      }
+    }
+    if (hits > 0) qz[q] = (float)(s / hits);
+  }
+}
+
+// Same without a grid: one block per listed query scans all n points; per-thread
+// float64 sums in stride order, then a fixed-order tree reduction.
+__global__ __launch_bounds__(256) void k_fixup_scan(const uint32_t* __restrict__ count,
+                                                    const uint32_t* __restrict__ list, const float* __restrict__ qx,
+                                                    const float* __restrict__ qy, const float* __restrict__ x,
+                                                    const float* __restrict__ y, const float* __restrict__ z, int n,
+                                                    float* __restrict__ qz) {
+  __shared__ double ss[256];
+  __shared__ int sc[256];
+  const uint32_t cnt = *count;
+  for (uint32_t e = blockIdx.x; e < cnt; e += gridDim.x) {
+    const uint32_t q = list[e];
+    const float fx = qx[q], fy = qy[q];
+    double s = 0.0;
+    int hits = 0;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+      if (x[i] == fx && y[i] == fy) {
+        s += (double)z[i];
+        ++hits;
+      }
+    }
+    ss[threadIdx.x] = s;
+    sc[threadIdx.x] = hits;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+      if ((int)threadIdx.x < w) {
+        ss[threadIdx.x] += ss[threadIdx.x + w];
+        sc[threadIdx.x] += sc[threadIdx.x + w];
+      }
+      __syncthreads();
+    }
+    if (threadIdx.x == 0 && sc[0] > 0) qz[q] = (float)(ss[0] / sc[0]);
+    __syncthreads();
+  }
+}
+
+}  // namespace
+
+hipError_t launch_interp(const float* x, const float* y, const float* z, int n, const float* qx, const float* qy,
+                         const float* r_obs, const float* d1sq, int m, const AlphaParams& ap, int q, int split,
+                         float* qz, double2* partial, float* alpha_out, hipStream_t s) {
+  if (m <= 0) return hipSuccess;
+  int chunk = (n + split - 1) / split;
+  chunk = (chunk + kChunk - 1) / kChunk * kChunk;
+  const dim3 block(kThreads);
+  const dim3 grid((m + kThreads * q - 1) / (kThreads * q), split);
+  switch (q) {
+    case 1:
+      hipLaunchKernelGGL(k_interp<1>, grid, block, 0, s, x, y, z, n, chunk, qx, qy, r_obs, d1sq, m, ap, qz, partial,
+                         alpha_out);
+      break;
+    case 2:
+      hipLaunchKernelGGL(k_interp<2>, grid, block, 0, s, x, y, z, n, chunk, qx, qy, r_obs, d1sq, m, ap, qz, partial,
+                         alpha_out);
+      break;
+    case 4:
+      hipLaunchKernelGGL(k_interp<4>, grid, block, 0, s, x, y, z, n, chunk, qx, qy, r_obs, d1sq, m, ap, qz, partial,
+                         alpha_out);
+      break;
+    case 8:
+      hipLaunchKernelGGL(k_interp<8>, grid, block, 0, s, x, y, z, n, chunk, qx, qy, r_obs, d1sq, m, ap, qz, partial,
+                         alpha_out);
+      break;
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_combine(const double2* partial, int m, int split, float* qz, hipStream_t s) {
+  if (m <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_combine, dim3((m + 255) / 256), dim3(256), 0, s, partial, m, split, qz);
+  return hipGetLastError();
+}
+
+hipError_t launch_coincident_list(const float* d1sq, int m, uint32_t* count, uint32_t* list, hipStream_t s) {
+  if (m <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_coincident_list, dim3((m + 255) / 256), dim3(256), 0, s, d1sq, m, count, list);
+  return hipGetLastError();
+}
+
+hipError_t launch_fixup_grid(const uint32_t* count, const uint32_t* list, const float* qx, const float* qy,
+                             const GridScalars* gs, const int32_t* cell_start, const float* sx, const float* sy,
+                             const int32_t* sidx, const float* z, float* qz, hipStream_t s) {
+  hipLaunchKernelGGL(k_fixup_grid, dim3(64), dim3(256), 0, s, count, list, qx, qy, gs, cell_start, sx, sy, sidx, z,
+                     qz);
+  return hipGetLastError();
+}
+
+hipError_t launch_fixup_scan(const uint32_t* count, const uint32_t* list, const float* qx, const float* qy,
+                             const float* x, const float* y, const float* z, int n, float* qz, hipStream_t s) {
+  hipLaunchKernelGGL(k_fixup_scan, dim3(256), dim3(256), 0, s, count, list, qx, qy, x, y, z, n, qz);
+  return hipGetLastError();
+}
+
+}  // namespace aidw

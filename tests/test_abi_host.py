@@ -1,0 +1,81 @@
+"""C ABI checks that need no GPU: the library loads, exports every declared
+function, and rejects invalid arguments on the host before any GPU work."""
+import ctypes
+
+import pytest
+
+import paper_1601_05904_amd as aidw
+
+
+@pytest.fixture(scope="module")
+def L():
+    return aidw.load()
+
+
+def test_every_declared_function_is_exported(L):
+    names = aidw.exported_functions()
+    assert {"aidw_build_grid", "aidw_knn", "aidw_interpolate", "aidw_run"} <= set(names)
+    for n in names:
+        assert hasattr(L, n), n
+
+
+def test_status_strings_and_version(L):
+    for code in (0, -1, -2, -3, -4, -5, -6):
+        assert L.aidw_status_string(code).decode() != "unknown status"
+    assert b"gfx950" in L.aidw_version()
+
+
+def test_params_default(L):
+    p = aidw._Params()
+    L.aidw_params_default(ctypes.byref(p))
+    assert p.k == 10 and list(p.alpha) == [1, 2, 3, 4, 5]
+    assert (p.r_min, p.r_max, p.area, p.cell_width, p.occupancy) == (0.0, 2.0, 0.0, 0.0, 2.0)
+
+
+def _p(**kw):
+    p = aidw.Params(**kw)._c()
+    return ctypes.byref(p)
+
+
+FAKE = ctypes.c_void_p(0x1000)  # never dereferenced: every call below fails host validation first
+
+
+@pytest.mark.parametrize("case", [
+    dict(n=0), dict(x=None), dict(m=-1), dict(qx=None), dict(z=None), dict(qz=None),
+    dict(p=dict(k=0)), dict(p=dict(k=65)), dict(p=dict(k=11), n=10),
+    dict(p=dict(r_min=2.0, r_max=1.0)), dict(p=dict(r_min=-1.0)), dict(p=dict(levels=(1, 2, float("nan"), 4, 5))),
+    dict(p=dict(levels=(1, 2, 0, 4, 5))), dict(p=dict(area=float("inf"))), dict(p=dict(occupancy=0.0)),
+])
+def test_run_rejects_invalid_arguments(L, case):
+    args = dict(x=FAKE, y=FAKE, z=FAKE, n=100, qx=FAKE, qy=FAKE, m=10, qz=FAKE, p={})
+    args.update({k: v for k, v in case.items() if k != "p"})
+    p = _p(**case.get("p", {}))
+    st = L.aidw_run(args["x"], args["y"], args["z"], args["n"], args["qx"], args["qy"], args["m"], p, args["qz"],
+                    None, None, None)
+    assert st == aidw.EINVAL
+    assert L.aidw_last_error_detail().decode() != ""
+
+
+def test_sizes_beyond_int32_are_capacity_errors(L):
+    st = L.aidw_run(FAKE, FAKE, FAKE, 1 << 31, FAKE, FAKE, 10, _p(), FAKE, None, None, None)
+    assert st == aidw.ECAPACITY
+
+
+def test_empty_query_set_is_a_no_op(L):
+    st = L.aidw_run(FAKE, FAKE, FAKE, 100, None, None, 0, _p(), None, None, None, None)
+    assert st == aidw.OK
+
+
+def test_other_entry_points_validate(L):
+    assert L.aidw_knn(None, FAKE, FAKE, 10, 5, FAKE, None, None, None) == aidw.EINVAL
+    assert L.aidw_build_grid(None, FAKE, 10, None, None, 0, _p(), None, None) == aidw.EINVAL
+    out = ctypes.c_void_p()
+    assert L.aidw_build_grid(FAKE, FAKE, 0, None, None, 0, _p(), None, ctypes.byref(out)) == aidw.EINVAL
+    assert L.aidw_interpolate(FAKE, FAKE, FAKE, 10, FAKE, FAKE, 5, None, FAKE, _p(), None, FAKE, None,
+                              None) == aidw.EINVAL
+    assert L.aidw_grid_describe(None, None) == aidw.EINVAL
+    assert L.aidw_set_interp_config(3, 0) == aidw.EINVAL
+    assert L.aidw_set_interp_config(0, 0) == aidw.OK
+    t = aidw._Timing()
+    assert L.aidw_last_timing(ctypes.byref(t)) == aidw.EINVAL
+    L.aidw_grid_destroy(None)

@@ -1,0 +1,296 @@
+"""Parity of the HIP path with the FP64 oracle, through the C ABI (needs an MI355X).
+
+Bars: grid arrays and kNN index sets bit-exact; d1sq exact; r_obs within one
+float32 ulp; alpha within 1e-6; z within 1e-5 in the normwise relative metric
+e = |z - z64| / max(|z64|, sum w|z| / sum w).
+"""
+import os
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1601_05904_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+Z_TOL = 1e-5
+
+
+@pytest.fixture(scope="module")
+def T():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1601_05904_amd as aidw
+    aidw.load(build_if_missing=False)
+    return torch
+
+
+def aidw_mod():
+    import paper_1601_05904_amd as aidw
+    return aidw
+
+
+def dev(T, a):
+    return T.from_numpy(np.ascontiguousarray(a)).to("cuda")
+
+
+def upload(T, ds):
+    return [dev(T, getattr(ds, k)) for k in ("x", "y", "z", "qx", "qy")]
+
+
+def zerr(zg, ref):
+    zg = np.asarray(zg, np.float64)
+    return np.abs(zg - ref["z"]) / np.maximum(np.abs(ref["z"]), ref["s"])
+
+
+def tiny_lattice(seed, n, m, res=8):
+    rng = np.random.default_rng(seed)
+    x = (rng.integers(0, res, n) / res).astype(np.float32)
+    y = (rng.integers(0, res, n) / res).astype(np.float32)
+    z = rng.standard_normal(n).astype(np.float32)
+    qx = (rng.integers(0, 2 * res, m) / (2 * res)).astype(np.float32)
+    qy = (rng.integers(0, 2 * res, m) / (2 * res)).astype(np.float32)
+    return W.Dataset("lattice%d" % seed, x, y, z, qx, qy, 8, seed)
+
+
+# ------------------------------------------------------------------ grid build
+
+def _check_grid(T, ds, params):
+    aidw = aidw_mod()
+    x, y, z, qx, qy = upload(T, ds)
+    g = aidw.build_grid(x, y, qx, qy, params)
+    d = g.describe()
+    b = O.bounds(ds.x, ds.y, ds.qx, ds.qy)
+    gp = O.grid_params(b, ds.n, params.area, params.cell_width, params.occupancy)
+    assert [d["min_x"], d["min_y"], d["max_x"], d["max_y"]] == list(np.float32(b))
+    assert d["area"] == gp["area"] and d["r_exp"] == gp["r_exp"] and d["cell_width"] == gp["cw"]
+    assert np.float32(d["inv_cell_width"]) == gp["inv_cw"]
+    assert (d["ncol"], d["nrow"]) == (gp["ncol"], gp["nrow"])
+    cs, sx, sy, si = (a.cpu().numpy() for a in g.arrays())
+    cells = O.cell_index(ds.x, ds.y, b[0], b[1], gp["inv_cw"], gp["ncol"], gp["nrow"])
+    counts = np.bincount(cells, minlength=gp["ncol"] * gp["nrow"])
+    assert np.array_equal(cs, np.concatenate([[0], np.cumsum(counts)]).astype(np.int32))
+    order = np.argsort(cells, kind="stable")  # each cell's segment ordered by original index
+    assert np.array_equal(si, order.astype(np.int32))
+    assert np.array_equal(sx, ds.x[order]) and np.array_equal(sy, ds.y[order])
+    g.close()
+
+
+@pytest.mark.parametrize("name", ["uniform_4k", "mixture", "ragged_rect", "lattice"])
+def test_grid_matches_oracle(T, name):
+    aidw = aidw_mod()
+    if name == "uniform_4k":
+        ds, p = W.uniform_4k(), aidw.Params()
+    elif name == "mixture":
+        ds, p = W.make(20000, 3000, 15, 31, "mixture"), aidw.Params(k=15)
+    elif name == "ragged_rect":
+        ds = W.make(1237, 999, 7, 32)
+        ds.x = (ds.x * np.float32(0.25)).astype(np.float32)  # a 1/4 x 1 rectangle
+        ds.qx = (ds.qx * np.float32(0.25)).astype(np.float32)
+        p = aidw.Params(k=7, occupancy=3.0)
+    else:
+        ds, p = tiny_lattice(5, 300, 50), aidw.Params(k=8, occupancy=0.5)
+    _check_grid(T, ds, p)
+
+
+# ------------------------------------------------------------------ kNN
+
+def _knn_case(T, ds, k, params=None):
+    aidw = aidw_mod()
+    params = params or aidw.Params(k=k)
+    x, y, z, qx, qy = upload(T, ds)
+    g = aidw.build_grid(x, y, qx, qy, params)
+    r, d1, ix = aidw.knn(g, qx, qy, k, want_d1sq=True, want_idx=True)
+    T.cuda.synchronize()
+    ref_i, ref_d2 = O.knn(ds.x, ds.y, ds.qx, ds.qy, k)
+    assert np.array_equal(ix.cpu().numpy(), ref_i), "kNN index sets differ"
+    assert np.array_equal(d1.cpu().numpy(), ref_d2[:, 0].astype(np.float32))
+    assert np.allclose(r.cpu().numpy(), O.robs(ref_d2), rtol=1.2e-7, atol=0)
+    g.close()
+
+
+@pytest.mark.parametrize("case", ["uniform_4k_k10", "mixture_k15", "ragged_k7", "k1", "k8", "k16", "k17", "k64",
+                                  "k_equals_n"])
+def test_knn_bit_exact(T, case):
+    if case == "uniform_4k_k10":
+        _knn_case(T, W.uniform_4k(), 10)
+    elif case == "mixture_k15":
+        _knn_case(T, W.make(20000, 3000, 15, 41, "mixture"), 15)
+    elif case == "ragged_k7":
+        _knn_case(T, W.make(1237, 999, 7, 42), 7)
+    elif case == "k_equals_n":
+        _knn_case(T, W.make(20, 33, 20, 43), 20)
+    else:
+        k = int(case[1:])
+        _knn_case(T, W.make(3001, 517, k, 44 + k), k)
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_knn_ties_and_duplicates(T, seed):
+    # coarse lattice: many equal distances and duplicate data points; ties go to the smaller index
+    ds = tiny_lattice(seed, 150 + 37 * seed, 40 + seed)
+    for k in (1, 5, 12):
+        _knn_case(T, ds, k)
+
+
+@pytest.mark.parametrize("mode", ["tiny", "paper_r_exp", "one_cell", "wide"])
+def test_knn_independent_of_cell_width(T, mode):
+    aidw = aidw_mod()
+    ds = W.make(5000, 800, 10, 51, "mixture", 8)
+    if mode == "tiny":
+        p = aidw.Params(k=10, occupancy=0.02)
+    elif mode == "paper_r_exp":
+        p = aidw.Params(k=10, occupancy=0.25)  # the cell width of Eq. 2, the paper's choice
+    elif mode == "one_cell":
+        p = aidw.Params(k=10, cell_width=4.0)
+    else:
+        p = aidw.Params(k=10, occupancy=40.0)
+    _knn_case(T, ds, 10, p)
+
+
+# ------------------------------------------------------------------ whole method
+
+def _run_case(T, ds, params=None, qsel=None):
+    aidw = aidw_mod()
+    params = params or aidw.Params(k=ds.k)
+    x, y, z, qx, qy = upload(T, ds)
+    qz, al, ro = aidw.run(x, y, z, qx, qy, params, want_alpha=True, want_robs=True)
+    T.cuda.synchronize()
+    ref = O.aidw(ds.x, ds.y, ds.z, ds.qx, ds.qy, k=params.k, levels=params.levels, r_min=params.r_min,
+                 r_max=params.r_max, area=params.area, cell_width=params.cell_width, occupancy=params.occupancy,
+                 qsel=qsel)
+    sel = slice(None) if qsel is None else qsel
+    zq = qz.cpu().numpy()[sel]
+    e = zerr(zq, ref)
+    assert np.all(np.isfinite(zq))
+    assert e.max() <= Z_TOL, "max z error %.3e" % e.max()
+    assert np.allclose(ro.cpu().numpy()[sel], ref["r_obs"], rtol=1.2e-7, atol=0)
+    assert np.allclose(al.cpu().numpy()[sel], ref["alpha"], rtol=0, atol=2e-6)
+    return qz, e
+
+
+def test_run_uniform_4k(T):
+    _run_case(T, W.uniform_4k())
+
+
+def test_run_mixture(T):
+    _run_case(T, W.make(20000, 20000, 15, 61, "mixture"))
+
+
+def test_run_other_levels_and_rmin(T):
+    aidw = aidw_mod()
+    ds = W.make(3000, 1500, 12, 62, "mixture", 4)
+    _run_case(T, ds, aidw.Params(k=12, levels=(0.5, 1.25, 2.0, 3.5, 7.0), r_min=0.3, r_max=3.0))
+
+
+@pytest.mark.parametrize("q,split", [(1, 1), (2, 3), (4, 1), (4, 7), (8, 1), (8, 16)])
+def test_run_launch_shapes(T, q, split):
+    aidw = aidw_mod()
+    ds = W.make(4099, 2053, 10, 63)  # ragged: n not a multiple of the chunk or tile, m not of the block
+    aidw.set_interp_config(q, split)
+    try:
+        _run_case(T, ds)
+    finally:
+        aidw.set_interp_config(0, 0)
+
+
+def test_run_deterministic(T):
+    aidw = aidw_mod()
+    ds = W.uniform_4k()
+    x, y, z, qx, qy = upload(T, ds)
+    a = aidw.run(x, y, z, qx, qy, aidw.Params())
+    b = aidw.run(x, y, z, qx, qy, aidw.Params())
+    assert T.equal(a, b)
+
+
+def test_coincident_queries(T):
+    ds = W.make(3000, 500, 10, 71)
+    # duplicate some data points, and put queries exactly on data points (some on duplicates)
+    ds.x[10], ds.y[10] = ds.x[20], ds.y[20]
+    ds.x[11], ds.y[11] = ds.x[20], ds.y[20]
+    for j, i in enumerate([20, 5, 1000, 2999, 10]):
+        ds.qx[j], ds.qy[j] = ds.x[i], ds.y[i]
+    qz, _ = _run_case(T, ds)
+    got = qz.cpu().numpy()
+    assert got[0] == np.float32((np.float64(ds.z[10]) + ds.z[11] + ds.z[20]) / 3)
+    assert got[1] == ds.z[5] and got[2] == ds.z[1000] and got[3] == ds.z[2999]
+
+
+def test_interpolate_without_grid(T):
+    aidw = aidw_mod()
+    ds = W.make(2500, 700, 10, 72)
+    ds.qx[3], ds.qy[3] = ds.x[9], ds.y[9]
+    x, y, z, qx, qy = upload(T, ds)
+    p = aidw.Params(k=10)
+    g = aidw.build_grid(x, y, qx, qy, p)
+    r, d1, _ = aidw.knn(g, qx, qy, 10)
+    area = g.describe()["area"]
+    g.close()
+    qz, al = aidw.interpolate(x, y, z, qx, qy, r, d1, aidw.Params(k=10, area=area), grid=None, want_alpha=True)
+    ref = O.aidw(ds.x, ds.y, ds.z, ds.qx, ds.qy, k=10)
+    assert zerr(qz.cpu().numpy(), ref).max() <= Z_TOL
+    assert qz.cpu().numpy()[3] == ds.z[9]
+
+
+@pytest.mark.parametrize("n,m,k", [(1, 3, 1), (2, 1, 2), (3, 7, 2), (65, 1, 64), (257, 300, 3)])
+def test_small_and_edge_sizes(T, n, m, k):
+    ds = W.make(n, m, k, 80 + n)
+    _run_case(T, ds)
+
+
+def test_error_paths_on_gpu(T):
+    aidw = aidw_mod()
+    ds = W.make(100, 20, 5, 90)
+    x, y, z, qx, qy = upload(T, ds)
+    bad = x.clone()
+    bad[7] = float("nan")
+    with pytest.raises(aidw.AidwError) as e:
+        aidw.run(bad, y, z, qx, qy, aidw.Params(k=5))
+    assert e.value.code == aidw.ENONFINITE
+    line = T.linspace(0, 1, 50, device="cuda")
+    zero = T.zeros(50, device="cuda")
+    with pytest.raises(aidw.AidwError) as e:
+        aidw.run(line, zero, zero, line[:5].contiguous(), zero[:5].contiguous(), aidw.Params(k=3))
+    assert e.value.code == aidw.EDEGENERATE
+    # collinear data with an explicit area is valid
+    qz = aidw.run(line, zero, line, line[:5].contiguous(), zero[:5].contiguous(), aidw.Params(k=3, area=1.0))
+    assert T.isfinite(qz).all()
+    os.environ["AIDW_FAULT"] = "alloc"
+    try:
+        with pytest.raises(aidw.AidwError) as e:
+            aidw.run(x, y, z, qx, qy, aidw.Params(k=5))
+        assert e.value.code == aidw.ENOMEM
+    finally:
+        del os.environ["AIDW_FAULT"]
+    assert T.isfinite(aidw.run(x, y, z, qx, qy, aidw.Params(k=5))).all()
+
+
+# ------------------------------------------------------------------ full sizes, sampled
+
+@pytest.mark.parametrize("name", ["uniform_1m", "clustered_256k"])
+def test_full_size_sampled(T, name):
+    aidw = aidw_mod()
+    ds = W.WORKLOADS[name]()
+    sel = W.sample_queries(ds.m, 512, ds.seed)
+    x, y, z, qx, qy = upload(T, ds)
+    p = aidw.Params(k=ds.k)
+    # kNN of every query (the kernels run() uses), checked on the sample
+    g = aidw.build_grid(x, y, qx, qy, p)
+    r, d1, ix = aidw.knn(g, qx, qy, ds.k, want_idx=True)
+    g.close()
+    ref_i, ref_d2 = O.knn(ds.x, ds.y, ds.qx[sel], ds.qy[sel], ds.k)
+    assert np.array_equal(ix.cpu().numpy()[sel], ref_i)
+    # the whole method in the launch configuration the benchmark times
+    qz, al, ro = aidw.run(x, y, z, qx, qy, p, want_alpha=True, want_robs=True)
+    T.cuda.synchronize()
+    assert T.equal(ro, r)
+    zall = qz.cpu().numpy()
+    assert np.all(np.isfinite(zall)) and zall.min() >= ds.z.min() and zall.max() <= ds.z.max()
+    a = al.cpu().numpy()
+    assert a.min() >= 1.0 and a.max() <= 5.0
+    ref = O.aidw(ds.x, ds.y, ds.z, ds.qx, ds.qy, k=ds.k, qsel=sel)
+    e = zerr(zall[sel], ref)
+    assert e.max() <= Z_TOL, "max z error %.3e" % e.max()
+    assert np.allclose(a[sel], ref["alpha"], atol=2e-6)
