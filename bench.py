@@ -1,0 +1,199 @@
+#!/usr/bin/env python3
+"""Benchmark: interpolated points/s of the whole AIDW method on one MI355X.
+
+A step is one aidw_run over the workload (grid build, query binning, kNN with
+Eq. 3, Eq. 4-6 and the weighted mean of Eq. 1 over all data points, and the
+coincident-query fix-up) with inputs already resident in HBM.  The default
+workload is n = m = 2^20 uniform points, k = 10 (synthetic, seeded).
+
+Printed: one JSON line with the metric, the pair kernel's roofline fraction
+(its duration measured with HIP events on the run's stream), the plain FP64
+CPU oracle timed on a bounded sample of the same workload on this host, and
+the z error of the timed run on that sample.
+
+    python bench.py [--steps K] [--warmup W] [--workload uniform_1m] [--cpu-sample S] [--no-cpu-baseline]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "interpolated points/s at n=m=1M (plain vs learned-R) at stated z error"
+
+# Roofline of the pair kernels, from the chip's unit counts and clock:
+#   256 CUs at 2.4 GHz; FP32 VALU issues 128 lanes / clk / CU (157.3 TFLOP/s = 256 * 2.4e9 * 128 * 2);
+#   transcendentals (v_log_f32, v_exp_f32, v_rsq_f32) issue 32 lanes / clk / CU and do not overlap
+#   with other VALU work (both measured on the chip).
+# Minimum work of one pair (query j, data point i):
+#   general alpha: 7 VALU (2 sub, mul + fma for d^2, mul for the exponent, fma + add for the sums)
+#                  + 2 transcendentals (log2, exp2);
+#   alpha == integer p: 6 VALU (d^2 and the sums) + the multiplies of the shortest addition chain
+#                  for r^p + 1 transcendental (rsq).
+# The peak for a workload is the harmonic mix over its queries' classes.
+CUS, CLOCK = 256, 2.4e9
+VALU_PER_CLK_CU, TRANS_PER_CLK_CU = 128, 32
+CHAIN_MULS = {1: 0, 2: 1, 3: 2, 4: 2, 5: 3, 6: 3, 7: 4, 8: 3}
+
+
+def pair_peak(valu, trans):
+    return CUS * CLOCK / (valu / VALU_PER_CLK_CU + trans / TRANS_PER_CLK_CU)
+
+
+PEAK_GENERAL = pair_peak(7, 2)
+
+
+def class_mix_peak(alpha, levels):
+    """Peak pairs/s for the queries' alpha values (integer levels take the one-transcendental form)."""
+    a = np.asarray(alpha, np.float64)
+    inv = np.full(a.shape, 1.0 / PEAK_GENERAL)
+    for p in sorted(set(int(v) for v in levels if float(v).is_integer() and 1 <= v <= 8)):
+        inv[a == p] = 1.0 / pair_peak(6 + CHAIN_MULS[p], 1)
+    return 1.0 / inv.mean(), {("alpha=%d" % p): float(np.mean(a == p)) for p in range(1, 9) if np.any(a == p)}
+
+
+def measured_traffic(workload):
+    """HBM bytes per launch of the dominant pair kernel, from the committed rocprofv3 counter summary
+    (FETCH_SIZE and WRITE_SIZE scaled by a copy-kernel calibration); None if the pair-kernel source has
+    changed since the counters were taken, or no summary exists for this workload."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "k_interp_%s_counters.md" % workload)
+    src = os.path.join(ROOT, "paper_1601_05904_amd", "csrc", "interp.hip")
+    if not os.path.exists(path):
+        return None
+    fields = {}
+    with open(path) as f:
+        for line in f:
+            if ":" in line and not line.startswith(("|", "#", "`")):
+                k, v = line.split(":", 1)
+                fields[k.strip()] = v.strip()
+    with open(src, "rb") as f:
+        h = hashlib.sha256(f.read()).hexdigest()[:16]
+    if fields.get("interp_source_sha256_16") != h or "traffic_bytes_per_launch" not in fields:
+        return None
+    return float(fields["traffic_bytes_per_launch"])
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="uniform_1m")
+    ap.add_argument("--cpu-sample", type=int, default=1024, help="queries of the CPU-baseline sample")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MB",
+                    help="only run a plain device copy of MB megabytes (reference for HBM traffic counters)")
+    return ap.parse_args()
+
+
+def copy_calibration(mb):
+    """A plain elementwise kernel of known traffic: reads and writes mb MB once per launch."""
+    import torch
+    a = torch.ones(mb * (1 << 20) // 4, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        torch.neg(a, out=b)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration_bytes_read": a.numel() * 4, "bytes_written": b.numel() * 4, "launches": 3}))
+
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on one GPU only: the method is measured on a single MI355X "
+              "(the query-sharded multi-GPU design is documented, not built); use --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_1601_05904_amd as aidw
+    from paper_1601_05904_amd import workloads as W
+
+    if args.copy_calibration:
+        copy_calibration(args.copy_calibration)
+        return
+    if not torch.cuda.is_available():
+        print("no GPU visible", file=sys.stderr)
+        sys.exit(1)
+    aidw.load(build_if_missing=True)
+    ds = W.WORKLOADS[args.workload]()
+    dev = torch.device("cuda", 0)
+    x, y, z, qx, qy = (torch.from_numpy(getattr(ds, k)).to(dev) for k in ("x", "y", "z", "qx", "qy"))
+    p = aidw.Params(k=ds.k, levels=ds.levels, r_min=ds.r_min, r_max=ds.r_max, occupancy=ds.occupancy)
+    qz = torch.empty(ds.m, dtype=torch.float32, device=dev)
+    stream = torch.cuda.current_stream()
+
+    aidw.set_timing(True)
+    for _ in range(args.warmup):
+        aidw.run(x, y, z, qx, qy, p, out=qz, stream=stream)
+    torch.cuda.synchronize()
+    stages = []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        aidw.run(x, y, z, qx, qy, p, out=qz, stream=stream)
+        stages.append(aidw.last_timing())
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    aidw.set_timing(False)
+
+    # alpha of every query (untimed run) decides the class mix of the roofline
+    _, alpha, _ = aidw.run(x, y, z, qx, qy, p, want_alpha=True, stream=stream)
+    peak, mix = class_mix_peak(alpha.cpu().numpy(), ds.levels)
+
+    ms = (t1 - t0) * 1e3 / args.steps
+    value = ds.m / (ms * 1e-3)
+    interp_ms = float(np.mean([s["interp_ms"] for s in stages]))
+    pairs = float(ds.n) * float(ds.m)
+    achieved = pairs / (interp_ms * 1e-3)
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "points/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic (seeded; coordinates on a 2^-20 lattice, z = sin 6x cos 6y + N(0, 0.01^2))",
+        "config": {"workload": args.workload, "n": ds.n, "m": ds.m, "k": ds.k, "distribution": ds.meta["kind"],
+                   "levels": list(ds.levels), "r_min": ds.r_min, "r_max": ds.r_max, "occupancy": ds.occupancy,
+                   "variant": "plain", "interp_q": stages[-1]["interp_q"], "interp_split": stages[-1]["interp_split"]},
+        "stages_ms": {k: float(np.mean([s[k] for s in stages])) for k in ("grid_ms", "knn_ms", "interp_ms",
+                                                                          "finish_ms")},
+        "roofline": {"bound": "alu", "kernel": "k_interp", "achieved": achieved / 1e9, "peak": peak / 1e9,
+                     "unit": "Gpair/s", "frac": achieved / peak, "traffic": measured_traffic(args.workload),
+                     "per_unit": "pair: general alpha 7 VALU + 2 transcendental; integer alpha p 6 VALU + chain(p) "
+                                 "multiplies + 1 transcendental", "class_mix": mix,
+                     "peak_general_form": PEAK_GENERAL / 1e9, "units_per_launch": pairs},
+    }
+
+    if not args.no_cpu_baseline:
+        import oracle
+        sel = W.sample_queries(ds.m, args.cpu_sample, ds.seed)
+        tc0 = time.perf_counter()
+        ref = oracle.aidw(ds.x, ds.y, ds.z, ds.qx, ds.qy, k=ds.k, levels=ds.levels, r_min=ds.r_min,
+                          r_max=ds.r_max, occupancy=ds.occupancy, qsel=sel)
+        tc1 = time.perf_counter()
+        out["cpu_baseline"] = {"value": len(sel) / (tc1 - tc0), "unit": "points/s", "cores": oracle.num_threads(),
+                               "kind": "oracle",
+                               "sample": "%d of the %d queries (every data point), FP64, %.1f s wall" % (
+                                   len(sel), ds.m, tc1 - tc0)}
+        zg = qz.cpu().numpy()[sel].astype(np.float64)
+        e = np.abs(zg - ref["z"]) / np.maximum(np.abs(ref["z"]), ref["s"])
+        out["z_error"] = {"metric": "|z - z64| / max(|z64|, sum w|z| / sum w)", "max": float(e.max()),
+                          "p999": float(np.quantile(e, 0.999)), "median": float(np.median(e)),
+                          "sample": len(sel)}
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

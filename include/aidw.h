@@ -216,8 +216,11 @@ aidw_status aidw_last_timing(aidw_timing* out);
 
 /* Overrides the pair kernel's launch shape for later calls on the calling
  * thread: q = queries per lane (1, 2, 4 or 8), split = data-axis splits
- * (>= 1).  0 for either restores the built-in choice. */
-aidw_status aidw_set_interp_config(int32_t q, int32_t split);
+ * (>= 1); 0 for either restores the built-in choice.  integer_powers = 0
+ * evaluates every query with the general w = 2^(-(alpha/2) log2 t); 1 or -1
+ * (the default) lets queries whose alpha equals an integer level p in 1..8
+ * use w = rsq(t)^p (one transcendental instead of two). */
+aidw_status aidw_set_interp_config(int32_t q, int32_t split, int32_t integer_powers);
 
 /* Static text for a status code. */
 const char* aidw_status_string(aidw_status st);

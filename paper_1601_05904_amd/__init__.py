@@ -117,7 +117,7 @@ def load(build_if_missing: bool = True):
     L.aidw_run.argtypes = [_VP, _VP, _VP, i64, _VP, _VP, i64, P(_Params), _VP, _VP, _VP, _VP]
     L.aidw_set_timing.argtypes = [ctypes.c_int]
     L.aidw_last_timing.argtypes = [P(_Timing)]
-    L.aidw_set_interp_config.argtypes = [i32, i32]
+    L.aidw_set_interp_config.argtypes = [i32, i32, i32]
     L.aidw_status_string.argtypes = [ctypes.c_int]
     L.aidw_status_string.restype = ctypes.c_char_p
     L.aidw_last_error_detail.argtypes = []
@@ -265,8 +265,10 @@ def last_timing() -> dict:
     return {f: getattr(t, f) for f, _ in _Timing._fields_}
 
 
-def set_interp_config(q: int = 0, split: int = 0):
-    _check(load().aidw_set_interp_config(int(q), int(split)))
+def set_interp_config(q: int = 0, split: int = 0, integer_powers: int = -1):
+    """Pair-kernel launch shape for later calls on this thread (0 = built-in choice);
+    integer_powers = 0 forces the general exp2/log2 weight for every query."""
+    _check(load().aidw_set_interp_config(int(q), int(split), int(integer_powers)))
 
 
 def version() -> str:

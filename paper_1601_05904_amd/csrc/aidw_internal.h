@@ -64,9 +64,20 @@ struct AlphaParams {
   double levels[5];
 };
 
+// Eq. 4-6 per query -> alpha_f [m] (and alpha_out if non-null); class keys [m] (p in 1..8 when
+// alpha == p exactly, else 0) and the identity permutation vals [m], ready for a stable sort by key.
+hipError_t launch_alpha_class(const float* r_obs, int m, const AlphaParams& ap, float* alpha_f, float* alpha_out,
+                              uint32_t* keys, uint32_t* vals, hipStream_t s);
+// Pair kernels over the queries in class order (perm, sorted keys skeys); fast_mask bit p
+// requests the integer-power kernel for class p (the general kernel covers every other block).
+// x, y, z are the padded copies made by launch_pad_copy.
 hipError_t launch_interp(const float* x, const float* y, const float* z, int n, const float* qx, const float* qy,
-                         const float* r_obs, const float* d1sq, int m, const AlphaParams& ap, int q, int split,
-                         float* qz, double2* partial, float* alpha_out, hipStream_t s);
+                         const float* alpha_f, const float* d1sq, const uint32_t* perm, const uint32_t* skeys, int m,
+                         uint32_t fast_mask, int q, int split, float* qz, double2* partial, hipStream_t s);
+// Zero-padded copies of x, y, z for the pair kernels, which may prefetch one chunk past n.
+int interp_padded_len(int n);
+hipError_t launch_pad_copy(const float* x, const float* y, const float* z, int n, float* xp, float* yp, float* zp,
+                           hipStream_t s);
 hipError_t launch_combine(const double2* partial, int m, int split, float* qz, hipStream_t s);
 hipError_t launch_coincident_list(const float* d1sq, int m, uint32_t* count, uint32_t* list, hipStream_t s);
 hipError_t launch_fixup_grid(const uint32_t* count, const uint32_t* list, const float* qx, const float* qy,

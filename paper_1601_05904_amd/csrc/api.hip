@@ -28,7 +28,7 @@ namespace {
 
 thread_local std::string g_detail;
 thread_local int g_timing = 0;
-thread_local int g_cfg_q = 0, g_cfg_split = 0;
+thread_local int g_cfg_q = 0, g_cfg_split = 0, g_cfg_intpow = 1;
 
 struct Timing {
   hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
@@ -225,16 +225,18 @@ aidw_status knn_impl(const aidw_grid* g, const float* qx, const float* qy, int64
 }
 
 void choose_interp_config(int64_t n, int64_t m, int* q, int* split) {
-  // Aim for >= 4 wavefronts per SIMD (256 CUs x 4 SIMDs) with 4 queries per lane;
-  // split the data axis when there are too few queries, keeping >= 2048 points per split.
-  int qq = g_cfg_q ? g_cfg_q : 4;
-  int64_t waves = (m + 64LL * qq - 1) / (64LL * qq);
+  // One query per lane (the most wavefronts per SIMD: the pair loop is latency-bound on the
+  // transcendental unit, and occupancy hides it better than in-lane ILP).  The data axis is
+  // split so that each split streams about 32K points (~400 KB, resident in an XCD's L2 while
+  // the blocks of that split run), and so that small query sets still fill the chip
+  // (>= 4096 wavefronts), keeping >= 64 points per split.
+  const int qq = g_cfg_q ? g_cfg_q : 1;
+  const int64_t waves = (m + 64LL * qq - 1) / (64LL * qq);
   int sp = 1;
   if (g_cfg_split) {
     sp = g_cfg_split;
   } else {
-    const int64_t target = 4096;
-    while (waves * sp < target && (n / (sp * 2)) >= 2048 && sp < 1024) sp *= 2;
+    while (sp < 1024 && n / (sp * 2) >= 64 && ((n / sp) > 32768 || waves * sp < 4096)) sp *= 2;
   }
   if (sp > n) sp = (int)n;
   *q = qq;
@@ -256,17 +258,34 @@ aidw_status interp_impl(const float* x, const float* y, const float* z, int64_t 
   choose_interp_config(n, m, &q, &split);
   if (used_q) *used_q = q;
   if (used_split) *used_split = split;
+  // integer levels get their own pair kernel (alpha == p: w = rsq(t)^p)
+  uint32_t fast_mask = 0;
+  if (g_cfg_intpow)
+    for (int i = 0; i < 5; ++i) {
+      const double a = p->alpha[i];
+      if (a >= 1.0 && a <= 8.0 && a == floor(a)) fast_mask |= 1u << (int)a;
+    }
   Temps t(s);
   double2* partial = nullptr;
-  uint32_t *count, *list;
+  uint32_t *count, *list, *keys, *perm, *tk, *tv, *hist, *scan;
+  float *alpha_f, *xp, *yp, *zp;
+  const int npad = interp_padded_len((int)n);
   hipError_t e;
   if (split > 1 && (e = t.get(&partial, (size_t)split * m)) != hipSuccess) return hip_fail(e, "allocating partials");
-  if ((e = t.get(&count, 1)) != hipSuccess || (e = t.get(&list, m)) != hipSuccess)
-    return hip_fail(e, "allocating coincidence list");
+  if ((e = t.get(&count, 1)) != hipSuccess || (e = t.get(&list, m)) != hipSuccess ||
+      (e = t.get(&alpha_f, m)) != hipSuccess || (e = t.get(&keys, m)) != hipSuccess ||
+      (e = t.get(&perm, m)) != hipSuccess || (e = t.get(&tk, m)) != hipSuccess || (e = t.get(&tv, m)) != hipSuccess ||
+      (e = t.get(&hist, radix_hist_words((int)m))) != hipSuccess ||
+      (e = t.get(&scan, radix_scan_tmp_words((int)m))) != hipSuccess || (e = t.get(&xp, npad)) != hipSuccess ||
+      (e = t.get(&yp, npad)) != hipSuccess || (e = t.get(&zp, npad)) != hipSuccess)
+    return hip_fail(e, "allocating interpolation buffers");
+  HIP_TRY(launch_pad_copy(x, y, z, (int)n, xp, yp, zp, s), "padding copy");
   HIP_TRY(hipMemsetAsync(count, 0, sizeof(uint32_t), s), "clearing coincidence count");
   HIP_TRY(launch_coincident_list(d1sq, (int)m, count, list, s), "coincidence list kernel");
+  HIP_TRY(launch_alpha_class(r_obs, (int)m, ap, alpha_f, alpha_out, keys, perm, s), "alpha kernel");
+  if (fast_mask) HIP_TRY(radix_sort_pairs(keys, perm, tk, tv, (int)m, 4, hist, scan, s), "class sort");
   if (ev_begin) HIP_TRY(hipEventRecord(ev_begin, s), "event");
-  HIP_TRY(launch_interp(x, y, z, (int)n, qx, qy, r_obs, d1sq, (int)m, ap, q, split, qz, partial, alpha_out, s),
+  HIP_TRY(launch_interp(xp, yp, zp, (int)n, qx, qy, alpha_f, d1sq, perm, keys, (int)m, fast_mask, q, split, qz, partial, s),
           "interpolation kernel");
   if (ev_end) HIP_TRY(hipEventRecord(ev_end, s), "event");
   if (split > 1) HIP_TRY(launch_combine(partial, (int)m, split, qz, s), "combine kernel");
@@ -461,11 +480,13 @@ aidw_status aidw_last_timing(aidw_timing* out) {
   return AIDW_OK;
 }
 
-aidw_status aidw_set_interp_config(int32_t q, int32_t split) {
+aidw_status aidw_set_interp_config(int32_t q, int32_t split, int32_t integer_powers) {
   if (!(q == 0 || q == 1 || q == 2 || q == 4 || q == 8)) return fail(AIDW_EINVAL, "q must be 0, 1, 2, 4 or 8");
   if (split < 0) return fail(AIDW_EINVAL, "split must be >= 0");
+  if (integer_powers < -1 || integer_powers > 1) return fail(AIDW_EINVAL, "integer_powers must be -1, 0 or 1");
   g_cfg_q = q;
   g_cfg_split = split;
+  g_cfg_intpow = integer_powers != 0;
   return AIDW_OK;
 }
 

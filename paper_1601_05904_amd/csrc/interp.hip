@@ -19,6 +19,16 @@
 // two-sum pairs; the final num / den is formed in float64.  Splitting the data
 // axis (blockIdx.y) gives more wavefronts when m is small; the splits' float64
 // partials are then combined in split order by a second kernel.
+//
+// Integer powers.  With the usual levels most queries have alpha saturated at
+// a level (mu <= 0.1 or >= 0.9, Eq. 6), and when that level is an integer p the
+// weight is w = (d1 / d)^p = r^p with r = rsq(t): one transcendental and a few
+// multiplies instead of log2 + exp2.  A prologue kernel evaluates Eq. 4-6 per
+// query and keys each query by its class (p in 1..8 when alpha == p exactly,
+// else 0); a stable sort by key groups the classes, and one launch per class
+// takes the blocks whose queries all share that class, the general kernel the
+// rest.  Which path a query takes depends only on the inputs, so results stay
+// deterministic.
 #include <float.h>
 
 #include "aidw_internal.h"
@@ -28,8 +38,12 @@ namespace aidw {
 namespace {
 
 constexpr int kThreads = 256;
-constexpr int kChunk = 8;    // data points per scalar fetch
+#ifndef AIDW_CHUNK
+#define AIDW_CHUNK 8
+#endif
+constexpr int kChunk = AIDW_CHUNK;  // data points per scalar fetch
 constexpr int kTile = 256;   // data points per float32 partial before the two-sum fold
+constexpr int kMaxIntPow = 8;  // integer alpha classes with a dedicated kernel
 
 // Eq. 5 as printed: 0 below R_min, 1 above R_max, else 0.5 - 0.5 cos(pi / R_max (R - R_min)).
 __device__ inline double fuzzy_mu(double R, double rmin, double rmax) {
@@ -62,7 +76,21 @@ __device__ inline void two_sum_fold(float& hi, float& lo, float v) {
   lo += err;
 }
 
-template <int Q>
+// w = r^P by repeated squaring (P known at compile time).
+template <int P>
+__device__ inline float ipow(float r) {
+  if constexpr (P == 1) {
+    return r;
+  } else if constexpr (P % 2 == 0) {
+    const float h = ipow<P / 2>(r);
+    return h * h;
+  } else {
+    return ipow<P - 1>(r) * r;
+  }
+}
+
+// POW = 0: general alpha, w = 2^(nh log2 t); POW = p > 0: alpha == p, w = rsq(t)^p.
+template <int Q, int POW>
 struct Lane {
   float qx[Q], qy[Q], nh[Q], sc[Q];
   Acc acc[Q];
@@ -74,7 +102,11 @@ struct Lane {
       const float dy = qy[j] - y;
       const float d2 = __builtin_fmaf(dx, dx, dy * dy);
       const float t = d2 * sc[j];
-      const float w = __builtin_amdgcn_exp2f(__builtin_amdgcn_logf(t) * nh[j]);
+      float w;
+      if constexpr (POW == 0)
+        w = __builtin_amdgcn_exp2f(__builtin_amdgcn_logf(t) * nh[j]);
+      else
+        w = ipow<POW>(__builtin_amdgcn_rsqf(t));
       acc[j].num_t = __builtin_fmaf(w, z, acc[j].num_t);
       acc[j].den_t += w;
     }
@@ -90,27 +122,57 @@ struct Lane {
   }
 };
 
-template <int Q>
+// Eq. 4-6 per query (float64), the query's class key and the identity permutation.
+__global__ __launch_bounds__(256) void k_alpha_class(const float* __restrict__ r_obs, int m, AlphaParams ap,
+                                                     float* __restrict__ alpha_f, float* __restrict__ alpha_out,
+                                                     uint32_t* __restrict__ keys, uint32_t* __restrict__ vals) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= m) return;
+  const double R = (double)r_obs[q] / ap.r_exp;                                  // Eq. 4
+  const double alpha = level_alpha(fuzzy_mu(R, ap.r_min, ap.r_max), ap.levels);  // Eq. 5, 6
+  const float af = (float)alpha;
+  alpha_f[q] = af;
+  if (alpha_out) alpha_out[q] = af;
+  uint32_t key = 0;
+  if (alpha >= 1.0 && alpha <= (double)kMaxIntPow && alpha == floor(alpha)) key = (uint32_t)alpha;
+  keys[q] = key;
+  vals[q] = (uint32_t)q;
+}
+
+// Queries are taken in class order: slot (block, j, thread) -> position -> query perm[position].
+// A class launch (POW > 0) takes only blocks whose queries all have key POW; the general launch
+// (POW == 0) skips the blocks that a class launch takes (fast_mask bit set for that key).
+template <int Q, int POW>
 __global__ __launch_bounds__(kThreads) void k_interp(const float* __restrict__ x, const float* __restrict__ y,
                                                      const float* __restrict__ z, int n, int chunk,
                                                      const float* __restrict__ qx, const float* __restrict__ qy,
-                                                     const float* __restrict__ r_obs, const float* __restrict__ d1sq,
-                                                     int m, AlphaParams ap, float* __restrict__ qz,
-                                                     double2* __restrict__ partial, float* __restrict__ alpha_out) {
-  Lane<Q> L;
-  const int qbase = blockIdx.x * kThreads * Q + threadIdx.x;
+                                                     const float* __restrict__ alpha_f,
+                                                     const float* __restrict__ d1sq,
+                                                     const uint32_t* __restrict__ perm,
+                                                     const uint32_t* __restrict__ skeys, int m, uint32_t fast_mask,
+                                                     float* __restrict__ qz, double2* __restrict__ partial) {
+  const int pos0 = blockIdx.x * kThreads * Q;
+  const int posl = min(m, pos0 + kThreads * Q) - 1;
+  const uint32_t k0 = skeys[pos0], kl = skeys[posl];
+  if constexpr (POW > 0) {
+    if (k0 != (uint32_t)POW || kl != (uint32_t)POW) return;
+  } else {
+    if (k0 == kl && ((fast_mask >> k0) & 1u)) return;
+  }
+  Lane<Q, POW> L;
   const int split = blockIdx.y;
+  uint32_t qid[Q];
 #pragma unroll
   for (int j = 0; j < Q; ++j) {
-    const int q = qbase + j * kThreads;
+    const int pos = pos0 + j * kThreads + threadIdx.x;
     float fx = 0.0f, fy = 0.0f, nh = 0.0f, sc = 1.0f;
-    if (q < m) {
+    qid[j] = 0xffffffffu;
+    if (pos < m) {
+      const uint32_t q = perm[pos];
+      qid[j] = q;
       fx = qx[q];
       fy = qy[q];
-      const double R = (double)r_obs[q] / ap.r_exp;                          // Eq. 4
-      const double alpha = level_alpha(fuzzy_mu(R, ap.r_min, ap.r_max), ap.levels);  // Eq. 5, 6
-      if (alpha_out && split == 0) alpha_out[q] = (float)alpha;
-      nh = (float)(-0.5 * alpha);
+      nh = -0.5f * alpha_f[q];
       const float d1 = d1sq[q];
       sc = d1 > 0.0f ? (float)(1.0 / (double)d1) : 1.0f;  // d1 == 0: coincident query, fixed up later
     }
@@ -123,46 +185,68 @@ __global__ __launch_bounds__(kThreads) void k_interp(const float* __restrict__ x
 
   const int lo = split * chunk;
   const int hi = min(n, lo + chunk);
-  int p = lo;
-  for (; p + kTile <= hi; p += kTile) {
-    for (int c = 0; c < kTile; c += kChunk) {
-      float xs[kChunk], ys[kChunk], zs[kChunk];
-#pragma unroll
-      for (int i = 0; i < kChunk; ++i) {
-        xs[i] = x[p + c + i];
-        ys[i] = y[p + c + i];
-        zs[i] = z[p + c + i];
-      }
-#pragma unroll
-      for (int i = 0; i < kChunk; ++i) L.pair(xs[i], ys[i], zs[i]);
-    }
-    L.fold();
-  }
-  for (; p + kChunk <= hi; p += kChunk) {
-    float xs[kChunk], ys[kChunk], zs[kChunk];
+  const int nfull = hi > lo ? (hi - lo) / kChunk : 0;
+  constexpr int kFoldMask = kTile / kChunk - 1;
+  // Double-buffered: each iteration fetches the next chunk while it evaluates the
+  // current one, and the compiler is left free to place the fetch (pinning it to
+  // the top of the loop bunches the scalar work and measured slower).  x, y, z are
+  // padded copies with >= kChunk points past the last full chunk, so the final
+  // prefetch stays in bounds.
+  if (nfull > 0) {
+    float cx[kChunk], cy[kChunk], cz[kChunk];
 #pragma unroll
     for (int i = 0; i < kChunk; ++i) {
-      xs[i] = x[p + i];
-      ys[i] = y[p + i];
-      zs[i] = z[p + i];
+      cx[i] = x[lo + i];
+      cy[i] = y[lo + i];
+      cz[i] = z[lo + i];
     }
+    for (int ci = 0; ci < nfull; ++ci) {
+      const int pn = lo + (ci + 1) * kChunk;
+      float nx[kChunk], ny[kChunk], nz[kChunk];
 #pragma unroll
-    for (int i = 0; i < kChunk; ++i) L.pair(xs[i], ys[i], zs[i]);
+      for (int i = 0; i < kChunk; ++i) {
+        nx[i] = x[pn + i];
+        ny[i] = y[pn + i];
+        nz[i] = z[pn + i];
+      }
+
+#pragma unroll
+      for (int i = 0; i < kChunk; ++i) L.pair(cx[i], cy[i], cz[i]);
+      if (((ci + 1) & kFoldMask) == 0) L.fold();
+#pragma unroll
+      for (int i = 0; i < kChunk; ++i) {
+        cx[i] = nx[i];
+        cy[i] = ny[i];
+        cz[i] = nz[i];
+      }
+    }
   }
-  for (; p < hi; ++p) L.pair(x[p], y[p], z[p]);
+  for (int p = lo + nfull * kChunk; p < hi; ++p) L.pair(x[p], y[p], z[p]);
   L.fold();
 
 #pragma unroll
   for (int j = 0; j < Q; ++j) {
-    const int q = qbase + j * kThreads;
-    if (q >= m) continue;
+    if (qid[j] == 0xffffffffu) continue;
     const double num = (double)L.acc[j].num_h + (double)L.acc[j].num_l;
     const double den = (double)L.acc[j].den_h + (double)L.acc[j].den_l;
     if (gridDim.y == 1)
-      qz[q] = (float)(num / den);
+      qz[qid[j]] = (float)(num / den);
     else
-      partial[(size_t)split * m + q] = make_double2(num, den);
+      partial[(size_t)split * m + qid[j]] = make_double2(num, den);
   }
+}
+
+// Copies the data into zero-padded arrays of interp_padded_len(n) points.
+__global__ __launch_bounds__(256) void k_pad_copy(const float* __restrict__ x, const float* __restrict__ y,
+                                                  const float* __restrict__ z, int n, int npad,
+                                                  float* __restrict__ xp, float* __restrict__ yp,
+                                                  float* __restrict__ zp) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= npad) return;
+  const bool in = i < n;
+  xp[i] = in ? x[i] : 0.0f;
+  yp[i] = in ? y[i] : 0.0f;
+  zp[i] = in ? z[i] : 0.0f;
 }
 
 __global__ __launch_bounds__(256) void k_combine(const double2* __restrict__ partial, int m, int split,
@@ -260,34 +344,65 @@ __global__ __launch_bounds__(256) void k_fixup_scan(const uint32_t* __restrict__
 
 }  // namespace
 
+hipError_t launch_alpha_class(const float* r_obs, int m, const AlphaParams& ap, float* alpha_f, float* alpha_out,
+                              uint32_t* keys, uint32_t* vals, hipStream_t s) {
+  if (m <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_alpha_class, dim3((m + 255) / 256), dim3(256), 0, s, r_obs, m, ap, alpha_f, alpha_out, keys,
+                     vals);
+  return hipGetLastError();
+}
+
+namespace {
+
+template <int Q, int POW>
+void launch_one(dim3 grid, hipStream_t s, const float* x, const float* y, const float* z, int n, int chunk,
+                const float* qx, const float* qy, const float* alpha_f, const float* d1sq, const uint32_t* perm,
+                const uint32_t* skeys, int m, uint32_t mask, float* qz, double2* partial) {
+  hipLaunchKernelGGL((k_interp<Q, POW>), grid, dim3(kThreads), 0, s, x, y, z, n, chunk, qx, qy, alpha_f, d1sq, perm,
+                     skeys, m, mask, qz, partial);
+}
+
+template <int Q>
+hipError_t launch_q(dim3 grid, hipStream_t s, const float* x, const float* y, const float* z, int n, int chunk,
+                    const float* qx, const float* qy, const float* alpha_f, const float* d1sq, const uint32_t* perm,
+                    const uint32_t* skeys, int m, uint32_t mask, float* qz, double2* partial) {
+  launch_one<Q, 0>(grid, s, x, y, z, n, chunk, qx, qy, alpha_f, d1sq, perm, skeys, m, mask, qz, partial);
+  if (mask & (1u << 1)) launch_one<Q, 1>(grid, s, x, y, z, n, chunk, qx, qy, alpha_f, d1sq, perm, skeys, m, mask, qz, partial);
+  if (mask & (1u << 2)) launch_one<Q, 2>(grid, s, x, y, z, n, chunk, qx, qy, alpha_f, d1sq, perm, skeys, m, mask, qz, partial);
+  if (mask & (1u << 3)) launch_one<Q, 3>(grid, s, x, y, z, n, chunk, qx, qy, alpha_f, d1sq, perm, skeys, m, mask, qz, partial);
+  if (mask & (1u << 4)) launch_one<Q, 4>(grid, s, x, y, z, n, chunk, qx, qy, alpha_f, d1sq, perm, skeys, m, mask, qz, partial);
+  if (mask & (1u << 5)) launch_one<Q, 5>(grid, s, x, y, z, n, chunk, qx, qy, alpha_f, d1sq, perm, skeys, m, mask, qz, partial);
+  if (mask & (1u << 6)) launch_one<Q, 6>(grid, s, x, y, z, n, chunk, qx, qy, alpha_f, d1sq, perm, skeys, m, mask, qz, partial);
+  if (mask & (1u << 7)) launch_one<Q, 7>(grid, s, x, y, z, n, chunk, qx, qy, alpha_f, d1sq, perm, skeys, m, mask, qz, partial);
+  if (mask & (1u << 8)) launch_one<Q, 8>(grid, s, x, y, z, n, chunk, qx, qy, alpha_f, d1sq, perm, skeys, m, mask, qz, partial);
+  return hipGetLastError();
+}
+
+}  // namespace
+
 hipError_t launch_interp(const float* x, const float* y, const float* z, int n, const float* qx, const float* qy,
-                         const float* r_obs, const float* d1sq, int m, const AlphaParams& ap, int q, int split,
-                         float* qz, double2* partial, float* alpha_out, hipStream_t s) {
+                         const float* alpha_f, const float* d1sq, const uint32_t* perm, const uint32_t* skeys, int m,
+                         uint32_t fast_mask, int q, int split, float* qz, double2* partial, hipStream_t s) {
   if (m <= 0) return hipSuccess;
   int chunk = (n + split - 1) / split;
   chunk = (chunk + kChunk - 1) / kChunk * kChunk;
-  const dim3 block(kThreads);
   const dim3 grid((m + kThreads * q - 1) / (kThreads * q), split);
+  fast_mask &= ((1u << (kMaxIntPow + 1)) - 2u);
   switch (q) {
-    case 1:
-      hipLaunchKernelGGL(k_interp<1>, grid, block, 0, s, x, y, z, n, chunk, qx, qy, r_obs, d1sq, m, ap, qz, partial,
-                         alpha_out);
-      break;
-    case 2:
-      hipLaunchKernelGGL(k_interp<2>, grid, block, 0, s, x, y, z, n, chunk, qx, qy, r_obs, d1sq, m, ap, qz, partial,
-                         alpha_out);
-      break;
-    case 4:
-      hipLaunchKernelGGL(k_interp<4>, grid, block, 0, s, x, y, z, n, chunk, qx, qy, r_obs, d1sq, m, ap, qz, partial,
-                         alpha_out);
-      break;
-    case 8:
-      hipLaunchKernelGGL(k_interp<8>, grid, block, 0, s, x, y, z, n, chunk, qx, qy, r_obs, d1sq, m, ap, qz, partial,
-                         alpha_out);
-      break;
-    default:
-      return hipErrorInvalidValue;
+    case 1: return launch_q<1>(grid, s, x, y, z, n, chunk, qx, qy, alpha_f, d1sq, perm, skeys, m, fast_mask, qz, partial);
+    case 2: return launch_q<2>(grid, s, x, y, z, n, chunk, qx, qy, alpha_f, d1sq, perm, skeys, m, fast_mask, qz, partial);
+    case 4: return launch_q<4>(grid, s, x, y, z, n, chunk, qx, qy, alpha_f, d1sq, perm, skeys, m, fast_mask, qz, partial);
+    case 8: return launch_q<8>(grid, s, x, y, z, n, chunk, qx, qy, alpha_f, d1sq, perm, skeys, m, fast_mask, qz, partial);
+    default: return hipErrorInvalidValue;
   }
+}
+
+int interp_padded_len(int n) { return (n + kChunk - 1) / kChunk * kChunk + kChunk; }
+
+hipError_t launch_pad_copy(const float* x, const float* y, const float* z, int n, float* xp, float* yp, float* zp,
+                           hipStream_t s) {
+  const int npad = interp_padded_len(n);
+  hipLaunchKernelGGL(k_pad_copy, dim3((npad + 255) / 256), dim3(256), 0, s, x, y, z, n, npad, xp, yp, zp);
   return hipGetLastError();
 }
 

@@ -74,8 +74,9 @@ def test_other_entry_points_validate(L):
     assert L.aidw_interpolate(FAKE, FAKE, FAKE, 10, FAKE, FAKE, 5, None, FAKE, _p(), None, FAKE, None,
                               None) == aidw.EINVAL
     assert L.aidw_grid_describe(None, None) == aidw.EINVAL
-    assert L.aidw_set_interp_config(3, 0) == aidw.EINVAL
-    assert L.aidw_set_interp_config(0, 0) == aidw.OK
+    assert L.aidw_set_interp_config(3, 0, -1) == aidw.EINVAL
+    assert L.aidw_set_interp_config(0, 0, 2) == aidw.EINVAL
+    assert L.aidw_set_interp_config(0, 0, -1) == aidw.OK
     t = aidw._Timing()
     assert L.aidw_last_timing(ctypes.byref(t)) == aidw.EINVAL
     L.aidw_grid_destroy(None)

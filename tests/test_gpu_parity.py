@@ -168,7 +168,7 @@ def _run_case(T, ds, params=None, qsel=None):
     assert e.max() <= Z_TOL, "max z error %.3e" % e.max()
     assert np.allclose(ro.cpu().numpy()[sel], ref["r_obs"], rtol=1.2e-7, atol=0)
     assert np.allclose(al.cpu().numpy()[sel], ref["alpha"], rtol=0, atol=2e-6)
-    return qz, e
+    return qz, e, ref
 
 
 def test_run_uniform_4k(T):
@@ -186,14 +186,34 @@ def test_run_other_levels_and_rmin(T):
 
 
 @pytest.mark.parametrize("q,split", [(1, 1), (2, 3), (4, 1), (4, 7), (8, 1), (8, 16)])
-def test_run_launch_shapes(T, q, split):
+@pytest.mark.parametrize("intpow", [1, 0])
+def test_run_launch_shapes(T, q, split, intpow):
     aidw = aidw_mod()
     ds = W.make(4099, 2053, 10, 63)  # ragged: n not a multiple of the chunk or tile, m not of the block
-    aidw.set_interp_config(q, split)
+    aidw.set_interp_config(q, split, intpow)
     try:
         _run_case(T, ds)
     finally:
-        aidw.set_interp_config(0, 0)
+        aidw.set_interp_config(0, 0, -1)
+
+
+@pytest.mark.parametrize("levels", [(1.0, 2.0, 3.0, 4.0, 5.0), (2.0, 2.5, 3.0, 3.5, 4.0), (1.5, 2.0, 2.5, 3.0, 3.5),
+                                    (3.0, 4.0, 5.0, 6.0, 8.0), (0.75, 1.0, 1.5, 2.0, 7.0)])
+def test_integer_power_classes(T, levels):
+    # alpha saturates at alpha_1 (low R) and alpha_5 (high R); integer levels take the rsq^p kernels.
+    # A clustered set gives both low-R queries (inside clusters) and high-R ones (background).
+    aidw = aidw_mod()
+    ds = W.make(6000, 5000, 10, 64, "mixture", 6)
+    p = aidw.Params(k=10, levels=levels, r_min=0.0, r_max=2.0)
+    qz_fast, e_fast, ref = _run_case(T, ds, p)
+    aidw.set_interp_config(0, 0, 0)
+    try:
+        qz_gen, e_gen, _ = _run_case(T, ds, p)
+    finally:
+        aidw.set_interp_config(0, 0, -1)
+    # both paths evaluate the same definition; in the error metric they agree far inside the tolerance
+    d = np.abs(qz_fast.cpu().numpy().astype(np.float64) - qz_gen.cpu().numpy()) / np.maximum(np.abs(ref["z"]), ref["s"])
+    assert d.max() < 2e-6
 
 
 def test_run_deterministic(T):
@@ -212,7 +232,7 @@ def test_coincident_queries(T):
     ds.x[11], ds.y[11] = ds.x[20], ds.y[20]
     for j, i in enumerate([20, 5, 1000, 2999, 10]):
         ds.qx[j], ds.qy[j] = ds.x[i], ds.y[i]
-    qz, _ = _run_case(T, ds)
+    qz, _, _ = _run_case(T, ds)
     got = qz.cpu().numpy()
     assert got[0] == np.float32((np.float64(ds.z[10]) + ds.z[11] + ds.z[20]) / 3)
     assert got[1] == ds.z[5] and got[2] == ds.z[1000] and got[3] == ds.z[2999]
