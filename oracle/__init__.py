@@ -67,6 +67,8 @@ def lib():
                                   f64p, ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                   ctypes.c_double, f64p, f64p, f64p, f64p, f64p, ctypes.c_void_p, ctypes.c_void_p,
                                   f64p]
+        L.oracle_features.argtypes = [f32p, f32p, i64, f32p, f32p, i64, ctypes.c_float, ctypes.c_float,
+                                      ctypes.c_float, ctypes.c_int32, ctypes.c_int32, f32p]
         _lib = L
     return _lib
 
@@ -167,6 +169,16 @@ def idw(x, y, z, qx, qy, alpha_q, return_scale=False):
     s = np.zeros(m)
     lib().oracle_idw(x, y, z, x.size, qx, qy, m, a, zq, _ptr(s))
     return (zq, s) if return_scale else zq
+
+
+def features(x, y, qx, qy, minx, miny, inv_cw, ncol, nrow):
+    """Learned-R inputs [m, 27]: 5 x 5 cell counts around the query's cell relative to the mean
+    occupancy, and the in-cell offsets (see aidw_oracle.c)."""
+    x, y, qx, qy = _f32(x), _f32(y), _f32(qx), _f32(qy)
+    out = np.zeros((qx.size, 27), np.float32)
+    lib().oracle_features(x, y, x.size, qx, qy, qx.size, np.float32(minx), np.float32(miny), np.float32(inv_cw),
+                          int(ncol), int(nrow), out)
+    return out
 
 
 def aidw(x, y, z, qx, qy, k=10, levels=(1.0, 2.0, 3.0, 4.0, 5.0), r_min=0.0, r_max=2.0, area=0.0,

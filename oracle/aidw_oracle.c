@@ -19,6 +19,7 @@
  *   oracle_alpha                                          pinned (knot values, closed form of Eq. 5-6 for alpha = 1..5)
  *   oracle_idw                                            pinned (coincidence, constant field, hull, symmetric closed forms, hand-derived worked examples)
  *   oracle_aidw                                           composition of the above
+ *   oracle_features                                       pinned (counts of a constructed grid, window clipping, offsets)
  */
 #include <math.h>
 #include <stdint.h>
@@ -303,4 +304,50 @@ int oracle_aidw(const float* x, const float* y, const float* z, int64_t n, const
   if (knn_d2) memcpy(knn_d2, kd, sizeof(double) * (size_t)msel * (size_t)k);
   free(sx); free(sy); free(ki); free(kd); free(ro); free(al);
   return ORACLE_OK;
+}
+
+/*
+ * Learned-R input features of each query (the surrogate that predicts R of Eq. 4
+ * from the grid's occupancy instead of a kNN search):
+ *   feat[0..24]  number of data points in each cell of the 5 x 5 block of cells
+ *                centred on the query's cell (row offset -2..2 outer, column
+ *                offset -2..2 inner; 0 for cells outside the grid), times
+ *                inv_occ = nCells / n (i.e. relative to the mean occupancy);
+ *   feat[25..26] the query's offset inside its cell along x and y, in [0, 1),
+ *                from the same single-precision binning as the data points.
+ * Counts come from a histogram of oracle_cell_index over the data.
+ */
+void oracle_features(const float* x, const float* y, int64_t n, const float* qx, const float* qy, int64_t m,
+                     float minX, float minY, float inv_cw, int32_t ncol, int32_t nrow, float* feat) {
+  int64_t ncells = (int64_t)ncol * nrow;
+  int32_t* cell = (int32_t*)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+  int64_t* count = (int64_t*)calloc((size_t)ncells, sizeof(int64_t));
+  if (!cell || !count) {
+    free(cell);
+    free(count);
+    return;
+  }
+  oracle_cell_index(x, y, n, minX, minY, inv_cw, ncol, nrow, cell);
+  for (int64_t i = 0; i < n; ++i) count[cell[i]] += 1;
+  double inv_occ = (double)ncells / (double)n;
+  for (int64_t j = 0; j < m; ++j) {
+    float tx = (qx[j] - minX) * inv_cw;
+    float ty = (qy[j] - minY) * inv_cw;
+    int32_t c0 = tx < 0.0f ? 0 : (int32_t)tx;
+    int32_t r0 = ty < 0.0f ? 0 : (int32_t)ty;
+    if (c0 > ncol - 1) c0 = ncol - 1;
+    if (r0 > nrow - 1) r0 = nrow - 1;
+    float* f = feat + j * 27;
+    for (int dr = -2; dr <= 2; ++dr) {
+      for (int dc = -2; dc <= 2; ++dc) {
+        int32_t r = r0 + dr, c = c0 + dc;
+        int64_t cnt = (r >= 0 && r < nrow && c >= 0 && c < ncol) ? count[(int64_t)r * ncol + c] : 0;
+        f[(dr + 2) * 5 + (dc + 2)] = (float)((double)cnt * inv_occ);
+      }
+    }
+    f[25] = tx - (float)c0;
+    f[26] = ty - (float)r0;
+  }
+  free(cell);
+  free(count);
 }
