@@ -87,6 +87,10 @@ def parse():
     ap.add_argument("--workload", default="uniform_1m")
     ap.add_argument("--cpu-sample", type=int, default=1024, help="queries of the CPU-baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-learned", action="store_true", help="skip the learned-R comparison")
+    ap.add_argument("--learned-workload", default="learned_1m")
+    ap.add_argument("--learned-steps", type=int, default=5)
+    ap.add_argument("--delta", type=float, default=0.3, help="fallback margin of the alpha-exact rule")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MB",
                     help="only run a plain device copy of MB megabytes (reference for HBM traffic counters)")
     return ap.parse_args()
@@ -101,6 +105,84 @@ def copy_calibration(mb):
         torch.neg(a, out=b)
     torch.cuda.synchronize()
     print(json.dumps({"copy_calibration_bytes_read": a.numel() * 4, "bytes_written": b.numel() * 4, "launches": 3}))
+
+
+def timed_runs(fn, steps, warmup):
+    """Runs fn warmup + steps times with per-stage timing; returns (ms per step, mean stage times)."""
+    import torch
+
+    import paper_1601_05904_amd as aidw
+    aidw.set_timing(True)
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    stages = []
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        fn()
+        stages.append(aidw.last_timing())
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    aidw.set_timing(False)
+    mean = {k: float(np.mean([s[k] for s in stages])) for k in ("grid_ms", "knn_ms", "interp_ms", "finish_ms")}
+    return (t1 - t0) * 1e3 / steps, mean
+
+
+def learned_comparison(args, with_oracle):
+    """Plain vs learned-R on the clustered 2^20 workload: the network is trained first on held-out
+    datasets (same recipe, seeds 100-103), then both paths are timed on the evaluation set."""
+    import torch
+
+    import paper_1601_05904_amd as aidw
+    import paper_1601_05904_amd.learned as L
+    from paper_1601_05904_amd import workloads as W
+
+    t0 = time.perf_counter()
+    train = W.learned_training_sets()
+    feat, target = L.training_pairs(train, k=15)
+    del train
+    t1 = time.perf_counter()
+    mlp = L.MLP(seed=11)
+    losses = mlp.train(feat, target, epochs=16, batch=1024, lr=2e-3, seed=11)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    npairs = int(feat.shape[0])
+    del feat, target
+
+    ds = W.WORKLOADS[args.learned_workload]()
+    dev = torch.device("cuda", 0)
+    x, y, z, qx, qy = (torch.from_numpy(getattr(ds, k)).to(dev) for k in ("x", "y", "z", "qx", "qy"))
+    p = aidw.Params(k=ds.k, levels=ds.levels, r_min=ds.r_min, r_max=ds.r_max, occupancy=ds.occupancy)
+    qz_p = torch.empty(ds.m, dtype=torch.float32, device=dev)
+    qz_l = torch.empty(ds.m, dtype=torch.float32, device=dev)
+    ms_p, st_p = timed_runs(lambda: aidw.run(x, y, z, qx, qy, p, out=qz_p), args.learned_steps, 1)
+    ms_l, st_l = timed_runs(lambda: L.run_learned(x, y, z, qx, qy, p, mlp, L.ALPHA_EXACT, args.delta, out=qz_l),
+                            args.learned_steps, 1)
+    _, al_p, _ = aidw.run(x, y, z, qx, qy, p, want_alpha=True)
+    _, al_l, _, nfb = L.run_learned(x, y, z, qx, qy, p, mlp, L.ALPHA_EXACT, args.delta, want_alpha=True)
+    mismatch = float((al_p != al_l).float().mean().item())
+    rstage_p = st_p["grid_ms"] + st_p["knn_ms"]
+    rstage_l = st_l["grid_ms"] + st_l["knn_ms"]
+    out = {"workload": args.learned_workload, "n": ds.n, "m": ds.m, "k": ds.k, "rule": "alpha-exact",
+           "delta": args.delta,
+           "plain_points_per_s": ds.m / (ms_p * 1e-3), "learned_points_per_s": ds.m / (ms_l * 1e-3),
+           "speedup_end_to_end": ms_p / ms_l,
+           "plain_rstage_ms": rstage_p, "learned_rstage_ms": rstage_l, "speedup_rstage": rstage_p / rstage_l,
+           "plain_stages_ms": st_p, "learned_stages_ms": st_l,
+           "skipped_knn_fraction": 1.0 - nfb / ds.m, "alpha_mismatch_fraction": mismatch,
+           "training": {"pairs": npairs, "epochs": 16, "batch": 1024, "lr": 2e-3, "final_loss": float(losses[-1]),
+                        "data_s": t1 - t0, "train_s": t2 - t1}}
+    if with_oracle:
+        import oracle
+        sel = W.sample_queries(ds.m, args.cpu_sample, ds.seed)
+        ref = oracle.aidw(ds.x, ds.y, ds.z, ds.qx, ds.qy, k=ds.k, levels=ds.levels, r_min=ds.r_min,
+                          r_max=ds.r_max, occupancy=ds.occupancy, qsel=sel)
+        for name, qz in (("z_error_plain", qz_p), ("z_error_learned", qz_l)):
+            e = np.abs(qz.cpu().numpy()[sel].astype(np.float64) - ref["z"]) / np.maximum(np.abs(ref["z"]), ref["s"])
+            out[name] = {"max": float(e.max()), "median": float(np.median(e)),
+                         "frac_within_1e-5": float(np.mean(e <= 1e-5)), "sample": len(sel)}
+    mlp.close()
+    return out
 
 
 def main():
@@ -192,6 +274,8 @@ def main():
         out["z_error"] = {"metric": "|z - z64| / max(|z64|, sum w|z| / sum w)", "max": float(e.max()),
                           "p999": float(np.quantile(e, 0.999)), "median": float(np.median(e)),
                           "sample": len(sel)}
+    if not args.no_learned:
+        out["learned_r"] = learned_comparison(args, with_oracle=not args.no_cpu_baseline)
     print(json.dumps(out))
 
 

@@ -222,6 +222,84 @@ aidw_status aidw_last_timing(aidw_timing* out);
  * use w = rsq(t)^p (one transcendental instead of two). */
 aidw_status aidw_set_interp_config(int32_t q, int32_t split, int32_t integer_powers);
 
+/* ---------------------------------------------------------------------------
+ * Learned-R form.  A small network predicts the nearest-neighbour statistic R
+ * of Eq. 4 from the grid's occupancy around each query (inputs: the counts of
+ * the 5 x 5 cells around the query's cell relative to the mean occupancy, and
+ * the query's offset inside its cell), so that most queries skip the kNN search
+ * of Section 3.2.4.  Exact kNN stays the fallback wherever the prediction could
+ * change alpha (Eq. 5, 6).  27 -> 64 -> 64 -> 1, GELU (tanh form), bf16 weights
+ * and activations as operands, float32 accumulation, trained on the GPU by the
+ * library's own forward / backward / Adam kernels.
+ * Parameter vector (float32, AIDW_MLP_PARAMS entries): W1 [64 x 27 row-major],
+ * b1 [64], W2 [64 x 64], b2 [64], W3 [64], b3 [1].
+ * ------------------------------------------------------------------------- */
+#define AIDW_MLP_INPUTS 27
+#define AIDW_MLP_PARAMS 6017
+
+typedef struct aidw_mlp aidw_mlp; /* opaque, device-resident, library-owned */
+
+typedef enum {
+  AIDW_FALLBACK_LITERAL = 0,     /* kNN when |R_hat - r_min| < delta or |R_hat - r_max| < delta; else alpha(R_hat) */
+  AIDW_FALLBACK_ALPHA_EXACT = 1  /* skip kNN only when R_hat is delta beyond the points where alpha
+                                    saturates (mu = 0.1 / 0.9 in Eq. 6); skipped queries get alpha_1 / alpha_5 */
+} aidw_fallback_rule;
+
+/* New network with weights drawn from `seed` (uniform in +-sqrt(6 / fan_in),
+ * biases 0) for grids of the given occupancy (> 0; points per cell).  Errors:
+ * AIDW_EINVAL, AIDW_ENOMEM, AIDW_EDEVICE. */
+aidw_status aidw_mlp_create(uint64_t seed, double occupancy, aidw_mlp** out);
+void aidw_mlp_destroy(aidw_mlp* mlp);
+
+/* Copies the float32 parameters from / to host memory (AIDW_MLP_PARAMS floats).
+ * set_params also clears the optimiser state.  Both synchronise the device. */
+aidw_status aidw_mlp_set_params(aidw_mlp* mlp, const float* host_params);
+aidw_status aidw_mlp_get_params(const aidw_mlp* mlp, float* host_params);
+
+/* Checkpoint: a versioned binary file holding the parameters, the optimiser
+ * state, the step count and the occupancy.  Errors: AIDW_EINVAL (bad file). */
+aidw_status aidw_mlp_save(const aidw_mlp* mlp, const char* path);
+aidw_status aidw_mlp_load(const char* path, aidw_mlp** out);
+
+/* Occupancy the network was created for (0 on a NULL handle). */
+double aidw_mlp_occupancy(const aidw_mlp* mlp);
+
+/* Network inputs of m queries on grid g: feat [m x 27] float32 (device,
+ * row-major); d1sq [m] (device, may be NULL) receives the squared distance to
+ * the nearest data point when it lies in the 3 x 3 cells around the query and
+ * nearer than their outer edge, else a lower bound of it (exactly 0 iff the
+ * query coincides with a data point). */
+aidw_status aidw_features(const aidw_grid* g, const float* qx, const float* qy, int64_t m, float* feat, float* d1sq,
+                          hipStream_t stream);
+
+/* r_hat [m] = network output for feat [m x 27] (device pointers). */
+aidw_status aidw_mlp_forward(const aidw_mlp* mlp, const float* feat, int64_t m, float* r_hat, hipStream_t stream);
+
+/* Gradient of the mean squared error over a batch (feat [batch x 27], target
+ * [batch], device) with respect to the parameter vector: grad [AIDW_MLP_PARAMS + 1]
+ * (device), the last entry being the loss.  No update is made. */
+aidw_status aidw_mlp_gradients(const aidw_mlp* mlp, const float* feat, const float* target, int64_t batch,
+                               float* grad, hipStream_t stream);
+
+/* Trains on `count` (feature, target) pairs (device): `epochs` passes of Adam
+ * (beta 0.9 / 0.999, eps 1e-8, learning rate lr) over minibatches of `batch`
+ * pairs, reshuffled each epoch from `seed`.  epoch_loss (host, [epochs], may be
+ * NULL) receives the mean batch loss of each epoch (this synchronises). */
+aidw_status aidw_mlp_train(aidw_mlp* mlp, const float* feat, const float* target, int64_t count, int32_t epochs,
+                           int32_t batch, float lr, uint64_t seed, float* epoch_loss, hipStream_t stream);
+
+/* The whole method with the learned R: grid build, features, network, exact
+ * kNN on the fallback queries only (rule, delta >= 0), alpha, and the weighted
+ * interpolation of aidw_interpolate for every query.  p->cell_width must be
+ * <= 0 and p->occupancy must equal the network's.  r_hat_out [m] (may be NULL)
+ * receives the predictions; *fallback_count (host, may be NULL) the number of
+ * queries that took the exact kNN path (this synchronises).  Timing as aidw_run
+ * (the kNN stage time covers features, network and the fallback search). */
+aidw_status aidw_run_learned(const float* x, const float* y, const float* z, int64_t n, const float* qx,
+                             const float* qy, int64_t m, const aidw_params* p, const aidw_mlp* mlp, int32_t rule,
+                             double delta, float* qz, float* alpha_out, float* r_hat_out, int64_t* fallback_count,
+                             hipStream_t stream);
+
 /* Static text for a status code. */
 const char* aidw_status_string(aidw_status st);
 

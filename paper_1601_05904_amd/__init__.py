@@ -123,8 +123,26 @@ def load(build_if_missing: bool = True):
     L.aidw_last_error_detail.argtypes = []
     L.aidw_last_error_detail.restype = ctypes.c_char_p
     L.aidw_version.restype = ctypes.c_char_p
+    u64 = ctypes.c_uint64
+    L.aidw_mlp_create.argtypes = [u64, ctypes.c_double, P(_VP)]
+    L.aidw_mlp_destroy.argtypes = [_VP]
+    L.aidw_mlp_destroy.restype = None
+    L.aidw_mlp_set_params.argtypes = [_VP, _VP]
+    L.aidw_mlp_get_params.argtypes = [_VP, _VP]
+    L.aidw_mlp_save.argtypes = [_VP, ctypes.c_char_p]
+    L.aidw_mlp_load.argtypes = [ctypes.c_char_p, P(_VP)]
+    L.aidw_mlp_occupancy.argtypes = [_VP]
+    L.aidw_mlp_occupancy.restype = ctypes.c_double
+    L.aidw_features.argtypes = [_VP, _VP, _VP, i64, _VP, _VP, _VP]
+    L.aidw_mlp_forward.argtypes = [_VP, _VP, i64, _VP, _VP]
+    L.aidw_mlp_gradients.argtypes = [_VP, _VP, _VP, i64, _VP, _VP]
+    L.aidw_mlp_train.argtypes = [_VP, _VP, _VP, i64, i32, i32, ctypes.c_float, u64, _VP, _VP]
+    L.aidw_run_learned.argtypes = [_VP, _VP, _VP, i64, _VP, _VP, i64, P(_Params), _VP, i32, ctypes.c_double, _VP, _VP,
+                                   _VP, P(i64), _VP]
     for name in ("aidw_build_grid", "aidw_grid_describe", "aidw_grid_arrays", "aidw_grid_copy_arrays", "aidw_knn",
-                 "aidw_interpolate", "aidw_run", "aidw_set_timing", "aidw_last_timing", "aidw_set_interp_config"):
+                 "aidw_interpolate", "aidw_run", "aidw_set_timing", "aidw_last_timing", "aidw_set_interp_config",
+                 "aidw_mlp_create", "aidw_mlp_set_params", "aidw_mlp_get_params", "aidw_mlp_save", "aidw_mlp_load",
+                 "aidw_features", "aidw_mlp_forward", "aidw_mlp_gradients", "aidw_mlp_train", "aidw_run_learned"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L

@@ -54,9 +54,12 @@ hipError_t launch_cell_start_gather(const uint32_t* keys, const uint32_t* vals, 
                                     const float* y, int32_t* cell_start, float* sx, float* sy, int32_t* sidx,
                                     hipStream_t s);
 
+// qperm (may be null) lists the queries in processing order; active (may be null) is a device
+// count: only the first *active entries of qperm are processed.
 hipError_t launch_knn(const GridScalars* gs, const int32_t* cell_start, const float* sx, const float* sy,
-                      const int32_t* sidx, const float* qx, const float* qy, const uint32_t* qperm, int m, int k,
-                      double slack_cells, float* r_obs, float* d1sq, int32_t* nn_idx, hipStream_t s);
+                      const int32_t* sidx, const float* qx, const float* qy, const uint32_t* qperm,
+                      const uint32_t* active, int m, int k, double slack_cells, float* r_obs, float* d1sq,
+                      int32_t* nn_idx, hipStream_t s);
 
 struct AlphaParams {
   double r_exp;
@@ -86,4 +89,42 @@ hipError_t launch_fixup_grid(const uint32_t* count, const uint32_t* list, const 
 hipError_t launch_fixup_scan(const uint32_t* count, const uint32_t* list, const float* qx, const float* qy,
                              const float* x, const float* y, const float* z, int n, float* qz, hipStream_t s);
 
+// ---- learned-R form ----
+
+// Device buffers of the learned-R network (one allocation, see api.hip).
+struct MlpDevice {
+  float* master;   // [AIDW_MLP_PARAMS] float32 parameters
+  float* mom;      // Adam first moment
+  float* vel;      // Adam second moment
+  uint32_t* w1p;   // [64][14] bf16 pairs
+  uint32_t* w2p;   // [64][32]
+  uint32_t* w3p;   // [32]
+  float* w2r;      // [64][64] float32 of the bf16-rounded W2
+  float* w3r;      // [64]
+};
+
+hipError_t launch_features(const GridScalars* gs, const int32_t* cell_start, const float* sx, const float* sy,
+                           const float* qx, const float* qy, int m, double inv_occ, double slack_cells, float* feat,
+                           float* d1sq, hipStream_t s);
+hipError_t launch_mlp_repack(const MlpDevice& d, hipStream_t s);
+hipError_t launch_mlp_forward(const MlpDevice& d, const float* feat, int m, float* out, hipStream_t s);
+size_t mlp_batch_scratch_floats(int B);
+// grad [AIDW_MLP_PARAMS + 1]: the batch gradient, then the batch's mean squared error.
+hipError_t launch_mlp_gradients(const MlpDevice& d, const float* feat, const float* target, const uint32_t* sel, int B,
+                                float* scratch, float* grad, hipStream_t s);
+hipError_t launch_adam(const MlpDevice& d, const float* grad, float lr, float b1, float b2, float eps, float bc1,
+                       float bc2, hipStream_t s);
+hipError_t launch_accumulate_loss(const float* grad, float* epoch_loss, int epoch, float scale, hipStream_t s);
+hipError_t launch_fallback(const float* r_hat, const float* d1sq, const float* qx, const float* qy, int m,
+                           const GridScalars* gs, const AlphaParams& ap, int rule, double delta, double r_sat_lo,
+                           double r_sat_hi, float* alpha_f, uint32_t* keys, uint32_t* vals, uint32_t* count,
+                           hipStream_t s);
+hipError_t launch_alpha_fallback(const uint32_t* perm, const uint32_t* count, int m, const float* r_obs,
+                                 const AlphaParams& ap, float* alpha_f, hipStream_t s);
+// Pair-kernel class keys from a given alpha (alpha == p in 1..8 -> p, else 0) and the identity permutation.
+hipError_t launch_class_keys(const float* alpha_f, int m, uint32_t* keys, uint32_t* vals, hipStream_t s);
+// Shuffle keys for training: a 32-bit hash of (seed, epoch, i), and the identity values.
+hipError_t launch_shuffle_keys(uint64_t seed, int epoch, int count, uint32_t* keys, uint32_t* vals, hipStream_t s);
+
 }  // namespace aidw
+

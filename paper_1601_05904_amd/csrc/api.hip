@@ -89,7 +89,7 @@ void dfree_async(void* p, hipStream_t s) {
 // Scoped stream-ordered temporaries.
 struct Temps {
   hipStream_t s;
-  void* ptrs[16];
+  void* ptrs[32];
   int count = 0;
   explicit Temps(hipStream_t st) : s(st) {}
   ~Temps() {
@@ -98,6 +98,7 @@ struct Temps {
   template <typename T>
   hipError_t get(T** out, size_t elems) {
     void* p = nullptr;
+    if (count >= 32) return hipErrorInvalidValue;
     hipError_t e = dmalloc_async(&p, elems * sizeof(T), s);
     if (e != hipSuccess) return e;
     ptrs[count++] = p;
@@ -218,7 +219,7 @@ aidw_status knn_impl(const aidw_grid* g, const float* qx, const float* qy, int64
   // bin the queries with the data's cell formula, then sort them by cell
   HIP_TRY(launch_cell_keys(qx, qy, (int)m, g->dev, keys, vals, s), "query key kernel");
   HIP_TRY(radix_sort_pairs(keys, vals, tk, tv, (int)m, bits_for(g->host.ncells), hist, scan, s), "query sort");
-  HIP_TRY(launch_knn(g->dev, g->cell_start, g->sx, g->sy, g->sidx, qx, qy, vals, (int)m, k, slack_cells(g->host), r_obs,
+  HIP_TRY(launch_knn(g->dev, g->cell_start, g->sx, g->sy, g->sidx, qx, qy, vals, nullptr, (int)m, k, slack_cells(g->host), r_obs,
                      d1sq, nn_idx, s),
           "kNN kernel");
   return AIDW_OK;
@@ -246,7 +247,7 @@ void choose_interp_config(int64_t n, int64_t m, int* q, int* split) {
 aidw_status interp_impl(const float* x, const float* y, const float* z, int64_t n, const float* qx, const float* qy,
                         int64_t m, const float* r_obs, const float* d1sq, const aidw_params* p, const aidw_grid* g,
                         float* qz, float* alpha_out, hipStream_t s, hipEvent_t ev_begin, hipEvent_t ev_end,
-                        int* used_q, int* used_split) {
+                        int* used_q, int* used_split, const float* alpha_in = nullptr) {
   double area = p->area > 0 ? p->area : (g ? g->host.area : 0.0);
   if (!(area > 0)) return fail(AIDW_EINVAL, "aidw_interpolate needs params.area > 0 or a grid");
   AlphaParams ap;
@@ -282,7 +283,14 @@ aidw_status interp_impl(const float* x, const float* y, const float* z, int64_t 
   HIP_TRY(launch_pad_copy(x, y, z, (int)n, xp, yp, zp, s), "padding copy");
   HIP_TRY(hipMemsetAsync(count, 0, sizeof(uint32_t), s), "clearing coincidence count");
   HIP_TRY(launch_coincident_list(d1sq, (int)m, count, list, s), "coincidence list kernel");
-  HIP_TRY(launch_alpha_class(r_obs, (int)m, ap, alpha_f, alpha_out, keys, perm, s), "alpha kernel");
+  if (alpha_in) {  // alpha given per query: only the class keys are needed
+    HIP_TRY(hipMemcpyAsync(alpha_f, alpha_in, sizeof(float) * m, hipMemcpyDeviceToDevice, s), "copying alpha");
+    if (alpha_out)
+      HIP_TRY(hipMemcpyAsync(alpha_out, alpha_in, sizeof(float) * m, hipMemcpyDeviceToDevice, s), "copying alpha");
+    HIP_TRY(launch_class_keys(alpha_f, (int)m, keys, perm, s), "class key kernel");
+  } else {
+    HIP_TRY(launch_alpha_class(r_obs, (int)m, ap, alpha_f, alpha_out, keys, perm, s), "alpha kernel");
+  }
   if (fast_mask) HIP_TRY(radix_sort_pairs(keys, perm, tk, tv, (int)m, 4, hist, scan, s), "class sort");
   if (ev_begin) HIP_TRY(hipEventRecord(ev_begin, s), "event");
   HIP_TRY(launch_interp(xp, yp, zp, (int)n, qx, qy, alpha_f, d1sq, perm, keys, (int)m, fast_mask, q, split, qz, partial, s),
@@ -296,6 +304,69 @@ aidw_status interp_impl(const float* x, const float* y, const float* z, int64_t 
     HIP_TRY(launch_fixup_scan(count, list, qx, qy, x, y, z, (int)n, qz, s), "coincidence fix-up kernel");
   return AIDW_OK;
 }
+
+}  // namespace
+
+struct aidw_mlp {
+  MlpDevice d{};
+  void* block = nullptr;
+  double occupancy = 2.0;
+  uint64_t step = 0;
+};
+
+namespace {
+
+constexpr int kP = AIDW_MLP_PARAMS;
+
+// Float offsets of the network's arrays inside its single device allocation.
+struct MlpLayout {
+  static constexpr size_t master = 0, mom = kP, vel = 2 * kP, w1p = 3 * kP, w2p = w1p + 64 * 14, w3p = w2p + 64 * 32,
+                          w2r = w3p + 32, w3r = w2r + 64 * 64, total = w3r + 64;
+};
+
+aidw_status mlp_alloc(aidw_mlp** out) {
+  aidw_mlp* h = new aidw_mlp();
+  hipError_t e = dmalloc(&h->block, sizeof(float) * MlpLayout::total);
+  if (e != hipSuccess) {
+    delete h;
+    return hip_fail(e, "allocating the network");
+  }
+  float* b = static_cast<float*>(h->block);
+  h->d.master = b + MlpLayout::master;
+  h->d.mom = b + MlpLayout::mom;
+  h->d.vel = b + MlpLayout::vel;
+  h->d.w1p = reinterpret_cast<uint32_t*>(b + MlpLayout::w1p);
+  h->d.w2p = reinterpret_cast<uint32_t*>(b + MlpLayout::w2p);
+  h->d.w3p = reinterpret_cast<uint32_t*>(b + MlpLayout::w3p);
+  h->d.w2r = b + MlpLayout::w2r;
+  h->d.w3r = b + MlpLayout::w3r;
+  *out = h;
+  return AIDW_OK;
+}
+
+// Uploads masters (and optionally the optimiser state), then rebuilds the bf16 copies.
+aidw_status mlp_upload(aidw_mlp* h, const float* master, const float* mom, const float* vel) {
+  HIP_TRY(hipMemcpy(h->d.master, master, sizeof(float) * kP, hipMemcpyHostToDevice), "uploading parameters");
+  if (mom && vel) {
+    HIP_TRY(hipMemcpy(h->d.mom, mom, sizeof(float) * kP, hipMemcpyHostToDevice), "uploading optimiser state");
+    HIP_TRY(hipMemcpy(h->d.vel, vel, sizeof(float) * kP, hipMemcpyHostToDevice), "uploading optimiser state");
+  } else {
+    HIP_TRY(hipMemset(h->d.mom, 0, sizeof(float) * 2 * kP), "clearing optimiser state");
+  }
+  HIP_TRY(launch_mlp_repack(h->d, nullptr), "repacking weights");
+  HIP_TRY(hipDeviceSynchronize(), "repacking weights");
+  return AIDW_OK;
+}
+
+// SplitMix64 (Steele, Lea & Flood): the initial weights' generator.
+uint64_t splitmix64(uint64_t& state) {
+  uint64_t z = (state += 0x9E3779B97F4A7C15ull);
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+constexpr char kMlpMagic[8] = {'A', 'I', 'D', 'W', 'M', 'L', 'P', 1};
 
 }  // namespace
 
@@ -453,6 +524,287 @@ aidw_status aidw_run(const float* x, const float* y, const float* z, int64_t n, 
     }
   }
   aidw_grid_destroy(g);
+  return st;
+}
+
+aidw_status aidw_mlp_create(uint64_t seed, double occupancy, aidw_mlp** out) {
+  g_detail.clear();
+  if (!out) return fail(AIDW_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!finite_pos(occupancy)) return fail(AIDW_EINVAL, "occupancy must be finite and > 0");
+  float host[kP];
+  uint64_t st = seed;
+  auto uniform = [&](double a) { return (float)(a * (2.0 * ((splitmix64(st) >> 11) * 0x1.0p-53) - 1.0)); };
+  int o = 0;
+  for (int i = 0; i < 64 * 27; ++i) host[o++] = uniform(sqrt(6.0 / 27.0));
+  for (int i = 0; i < 64; ++i) host[o++] = 0.0f;
+  for (int i = 0; i < 64 * 64; ++i) host[o++] = uniform(sqrt(6.0 / 64.0));
+  for (int i = 0; i < 64; ++i) host[o++] = 0.0f;
+  for (int i = 0; i < 64; ++i) host[o++] = uniform(sqrt(6.0 / 64.0));
+  host[o++] = 0.0f;
+  aidw_mlp* h = nullptr;
+  aidw_status stt = mlp_alloc(&h);
+  if (stt != AIDW_OK) return stt;
+  h->occupancy = occupancy;
+  if ((stt = mlp_upload(h, host, nullptr, nullptr)) != AIDW_OK) {
+    aidw_mlp_destroy(h);
+    return stt;
+  }
+  *out = h;
+  return AIDW_OK;
+}
+
+void aidw_mlp_destroy(aidw_mlp* mlp) {
+  if (!mlp) return;
+  if (mlp->block) (void)hipFree(mlp->block);
+  delete mlp;
+}
+
+double aidw_mlp_occupancy(const aidw_mlp* mlp) { return mlp ? mlp->occupancy : 0.0; }
+
+aidw_status aidw_mlp_set_params(aidw_mlp* mlp, const float* host_params) {
+  g_detail.clear();
+  if (!mlp || !host_params) return fail(AIDW_EINVAL, "network / params is NULL");
+  for (int i = 0; i < kP; ++i)
+    if (!isfinite(host_params[i])) return fail(AIDW_EINVAL, "parameter %d is not finite", i);
+  mlp->step = 0;
+  return mlp_upload(mlp, host_params, nullptr, nullptr);
+}
+
+aidw_status aidw_mlp_get_params(const aidw_mlp* mlp, float* host_params) {
+  g_detail.clear();
+  if (!mlp || !host_params) return fail(AIDW_EINVAL, "network / params is NULL");
+  HIP_TRY(hipDeviceSynchronize(), "synchronising");
+  HIP_TRY(hipMemcpy(host_params, mlp->d.master, sizeof(float) * kP, hipMemcpyDeviceToHost), "reading parameters");
+  return AIDW_OK;
+}
+
+aidw_status aidw_mlp_save(const aidw_mlp* mlp, const char* path) {
+  g_detail.clear();
+  if (!mlp || !path) return fail(AIDW_EINVAL, "network / path is NULL");
+  std::string buf(sizeof(float) * 3 * kP, '\0');
+  HIP_TRY(hipDeviceSynchronize(), "synchronising");
+  HIP_TRY(hipMemcpy(&buf[0], mlp->d.master, buf.size(), hipMemcpyDeviceToHost), "reading the network");
+  FILE* f = fopen(path, "wb");
+  if (!f) return fail(AIDW_EINVAL, "cannot open %s for writing", path);
+  const uint32_t hdr[4] = {1u, AIDW_MLP_INPUTS, 64u, (uint32_t)kP};
+  bool ok = fwrite(kMlpMagic, 1, 8, f) == 8 && fwrite(hdr, sizeof hdr, 1, f) == 1 &&
+            fwrite(&mlp->occupancy, sizeof(double), 1, f) == 1 && fwrite(&mlp->step, sizeof(uint64_t), 1, f) == 1 &&
+            fwrite(buf.data(), 1, buf.size(), f) == buf.size();
+  ok = (fclose(f) == 0) && ok;
+  return ok ? AIDW_OK : fail(AIDW_EINVAL, "writing %s failed", path);
+}
+
+aidw_status aidw_mlp_load(const char* path, aidw_mlp** out) {
+  g_detail.clear();
+  if (!path || !out) return fail(AIDW_EINVAL, "path / out is NULL");
+  *out = nullptr;
+  FILE* f = fopen(path, "rb");
+  if (!f) return fail(AIDW_EINVAL, "cannot open %s", path);
+  char magic[8];
+  uint32_t hdr[4];
+  double occ = 0;
+  uint64_t step = 0;
+  std::string buf(sizeof(float) * 3 * kP, '\0');
+  bool ok = fread(magic, 1, 8, f) == 8 && memcmp(magic, kMlpMagic, 8) == 0 && fread(hdr, sizeof hdr, 1, f) == 1 &&
+            hdr[0] == 1u && hdr[1] == AIDW_MLP_INPUTS && hdr[2] == 64u && hdr[3] == (uint32_t)kP &&
+            fread(&occ, sizeof occ, 1, f) == 1 && fread(&step, sizeof step, 1, f) == 1 &&
+            fread(&buf[0], 1, buf.size(), f) == buf.size() && finite_pos(occ);
+  fclose(f);
+  if (!ok) return fail(AIDW_EINVAL, "%s is not a network checkpoint of this version", path);
+  aidw_mlp* h = nullptr;
+  aidw_status st = mlp_alloc(&h);
+  if (st != AIDW_OK) return st;
+  h->occupancy = occ;
+  h->step = step;
+  const float* fb = reinterpret_cast<const float*>(buf.data());
+  if ((st = mlp_upload(h, fb, fb + kP, fb + 2 * kP)) != AIDW_OK) {
+    aidw_mlp_destroy(h);
+    return st;
+  }
+  *out = h;
+  return AIDW_OK;
+}
+
+aidw_status aidw_features(const aidw_grid* g, const float* qx, const float* qy, int64_t m, float* feat, float* d1sq,
+                          hipStream_t stream) {
+  g_detail.clear();
+  if (!g) return fail(AIDW_EINVAL, "grid is NULL");
+  if (m < 0 || m > INT32_MAX) return fail(AIDW_EINVAL, "m = %lld out of range", (long long)m);
+  if (m == 0) return AIDW_OK;
+  if (!qx || !qy || !feat) return fail(AIDW_EINVAL, "qx / qy / feat is NULL");
+  const double inv_occ = (double)g->host.ncells / (double)g->n;
+  HIP_TRY(launch_features(g->dev, g->cell_start, g->sx, g->sy, qx, qy, (int)m, inv_occ, slack_cells(g->host), feat,
+                          d1sq, stream),
+          "feature kernel");
+  return AIDW_OK;
+}
+
+aidw_status aidw_mlp_forward(const aidw_mlp* mlp, const float* feat, int64_t m, float* r_hat, hipStream_t stream) {
+  g_detail.clear();
+  if (!mlp) return fail(AIDW_EINVAL, "network is NULL");
+  if (m < 0 || m > INT32_MAX) return fail(AIDW_EINVAL, "m = %lld out of range", (long long)m);
+  if (m == 0) return AIDW_OK;
+  if (!feat || !r_hat) return fail(AIDW_EINVAL, "feat / r_hat is NULL");
+  HIP_TRY(launch_mlp_forward(mlp->d, feat, (int)m, r_hat, stream), "network forward kernel");
+  return AIDW_OK;
+}
+
+aidw_status aidw_mlp_gradients(const aidw_mlp* mlp, const float* feat, const float* target, int64_t batch,
+                               float* grad, hipStream_t stream) {
+  g_detail.clear();
+  if (!mlp || !feat || !target || !grad) return fail(AIDW_EINVAL, "network / feat / target / grad is NULL");
+  if (batch < 1 || batch > (1 << 20)) return fail(AIDW_EINVAL, "batch = %lld out of [1, 2^20]", (long long)batch);
+  Temps t(stream);
+  float* scratch;
+  hipError_t e = t.get(&scratch, mlp_batch_scratch_floats((int)batch));
+  if (e != hipSuccess) return hip_fail(e, "allocating batch scratch");
+  HIP_TRY(launch_mlp_gradients(mlp->d, feat, target, nullptr, (int)batch, scratch, grad, stream), "gradient kernels");
+  return AIDW_OK;
+}
+
+aidw_status aidw_mlp_train(aidw_mlp* mlp, const float* feat, const float* target, int64_t count, int32_t epochs,
+                           int32_t batch, float lr, uint64_t seed, float* epoch_loss, hipStream_t stream) {
+  g_detail.clear();
+  if (!mlp || !feat || !target) return fail(AIDW_EINVAL, "network / feat / target is NULL");
+  if (count < 1 || count > INT32_MAX) return fail(AIDW_EINVAL, "count = %lld out of range", (long long)count);
+  if (epochs < 1 || batch < 1 || batch > (1 << 20)) return fail(AIDW_EINVAL, "need epochs >= 1 and 1 <= batch <= 2^20");
+  if (!(lr > 0) || !isfinite(lr)) return fail(AIDW_EINVAL, "lr must be finite and > 0");
+  const int N = (int)count, B = batch < N ? batch : N;
+  const int nb = (N + B - 1) / B;
+  Temps t(stream);
+  uint32_t *keys, *vals, *tk, *tv, *hist, *scan;
+  float *scratch, *grad, *eloss;
+  hipError_t e;
+  if ((e = t.get(&keys, N)) != hipSuccess || (e = t.get(&vals, N)) != hipSuccess || (e = t.get(&tk, N)) != hipSuccess ||
+      (e = t.get(&tv, N)) != hipSuccess || (e = t.get(&hist, radix_hist_words(N))) != hipSuccess ||
+      (e = t.get(&scan, radix_scan_tmp_words(N))) != hipSuccess ||
+      (e = t.get(&scratch, mlp_batch_scratch_floats(B))) != hipSuccess || (e = t.get(&grad, kP + 1)) != hipSuccess ||
+      (e = t.get(&eloss, epochs)) != hipSuccess)
+    return hip_fail(e, "allocating training buffers");
+  HIP_TRY(hipMemsetAsync(eloss, 0, sizeof(float) * epochs, stream), "clearing losses");
+  const double b1 = 0.9, b2 = 0.999;
+  for (int ep = 0; ep < epochs; ++ep) {
+    HIP_TRY(launch_shuffle_keys(seed, ep, N, keys, vals, stream), "shuffle keys");
+    HIP_TRY(radix_sort_pairs(keys, vals, tk, tv, N, 32, hist, scan, stream), "shuffle sort");
+    for (int bi = 0; bi < nb; ++bi) {
+      const int start = bi * B, cnt = N - start < B ? N - start : B;
+      HIP_TRY(launch_mlp_gradients(mlp->d, feat, target, vals + start, cnt, scratch, grad, stream), "gradient kernels");
+      mlp->step += 1;
+      const float bc1 = (float)(1.0 - pow(b1, (double)mlp->step)), bc2 = (float)(1.0 - pow(b2, (double)mlp->step));
+      HIP_TRY(launch_adam(mlp->d, grad, lr, (float)b1, (float)b2, 1e-8f, bc1, bc2, stream), "Adam kernel");
+      HIP_TRY(launch_mlp_repack(mlp->d, stream), "repack kernel");
+      HIP_TRY(launch_accumulate_loss(grad, eloss, ep, 1.0f / (float)nb, stream), "loss kernel");
+    }
+  }
+  if (epoch_loss) {
+    HIP_TRY(hipMemcpyAsync(epoch_loss, eloss, sizeof(float) * epochs, hipMemcpyDeviceToHost, stream), "reading losses");
+    HIP_TRY(hipStreamSynchronize(stream), "synchronising");
+  }
+  return AIDW_OK;
+}
+
+aidw_status aidw_run_learned(const float* x, const float* y, const float* z, int64_t n, const float* qx,
+                             const float* qy, int64_t m, const aidw_params* p, const aidw_mlp* mlp, int32_t rule,
+                             double delta, float* qz, float* alpha_out, float* r_hat_out, int64_t* fallback_count,
+                             hipStream_t stream) {
+  g_detail.clear();
+  aidw_status st = check_data(x, y, n, qx, qy, m);
+  if (st != AIDW_OK) return st;
+  if (!z) return fail(AIDW_EINVAL, "z is NULL");
+  if ((st = check_params(p)) != AIDW_OK) return st;
+  if (!mlp) return fail(AIDW_EINVAL, "network is NULL");
+  if (rule != AIDW_FALLBACK_LITERAL && rule != AIDW_FALLBACK_ALPHA_EXACT) return fail(AIDW_EINVAL, "unknown rule %d", rule);
+  if (!(delta >= 0) || !isfinite(delta)) return fail(AIDW_EINVAL, "delta must be finite and >= 0");
+  if (p->cell_width > 0 || p->occupancy != mlp->occupancy)
+    return fail(AIDW_EINVAL, "the grid must use the network's occupancy (%g) and no explicit cell width",
+                mlp->occupancy);
+  if (p->k < 1 || p->k > AIDW_KMAX || p->k > n)
+    return fail(AIDW_EINVAL, "k = %d must be in [1, min(n = %lld, %d)]", p->k, (long long)n, AIDW_KMAX);
+  if (fallback_count) *fallback_count = 0;
+  if (m == 0) return AIDW_OK;
+  if (!qz) return fail(AIDW_EINVAL, "qz is NULL");
+  hipEvent_t* ev = nullptr;
+  if (g_timing) {
+    for (auto& e : g_tm.ev)
+      if (!e) HIP_TRY(hipEventCreate(&e), "creating timing events");
+    ev = g_tm.ev;
+    g_tm.valid = false;
+    HIP_TRY(hipEventRecord(ev[0], stream), "event");
+  }
+  aidw_grid* g = nullptr;
+  if ((st = build_grid_impl(x, y, n, qx, qy, m, p, stream, true, &g)) != AIDW_OK) return st;
+  uint32_t host_count = 0;
+  {
+    Temps t(stream);
+    hipError_t e = hipSuccess;
+    if (ev) e = hipEventRecord(ev[1], stream);
+    float *feat = nullptr, *d1sq = nullptr, *r_hat = nullptr, *alpha_f = nullptr, *r_obs = nullptr;
+    uint32_t *keys = nullptr, *vals = nullptr, *tk = nullptr, *tv = nullptr, *hist = nullptr, *scan = nullptr,
+             *count = nullptr;
+    const int mm = (int)m;
+    if (e == hipSuccess) e = t.get(&feat, (size_t)mm * AIDW_MLP_INPUTS);
+    if (e == hipSuccess) e = t.get(&d1sq, mm);
+    if (e == hipSuccess) e = t.get(&r_hat, mm);
+    if (e == hipSuccess) e = t.get(&alpha_f, mm);
+    if (e == hipSuccess) e = t.get(&r_obs, mm);
+    if (e == hipSuccess) e = t.get(&keys, mm);
+    if (e == hipSuccess) e = t.get(&vals, mm);
+    if (e == hipSuccess) e = t.get(&tk, mm);
+    if (e == hipSuccess) e = t.get(&tv, mm);
+    if (e == hipSuccess) e = t.get(&hist, radix_hist_words(mm));
+    if (e == hipSuccess) e = t.get(&scan, radix_scan_tmp_words(mm));
+    if (e == hipSuccess) e = t.get(&count, 1);
+    if (e != hipSuccess) st = hip_fail(e, "allocating learned-R buffers");
+    AlphaParams ap;
+    ap.r_exp = g->host.r_exp;
+    ap.r_min = p->r_min;
+    ap.r_max = p->r_max;
+    for (int i = 0; i < 5; ++i) ap.levels[i] = p->alpha[i];
+    // R where mu = 0.1 and 0.9 (Eq. 5 as applied): alpha is saturated below / above them (Eq. 6)
+    const double r_sat_lo = p->r_min + p->r_max / M_PI * acos(0.8);
+    const double r_sat_hi = p->r_min + p->r_max / M_PI * acos(-0.8);
+    const double inv_occ = (double)g->host.ncells / (double)n;
+#define STEP(expr, what) \
+  if (st == AIDW_OK && (e = (expr)) != hipSuccess) st = hip_fail(e, what)
+    STEP(hipMemsetAsync(count, 0, sizeof(uint32_t), stream), "clearing the fallback count");
+    STEP(launch_features(g->dev, g->cell_start, g->sx, g->sy, qx, qy, mm, inv_occ, slack_cells(g->host), feat, d1sq,
+                         stream),
+         "feature kernel");
+    STEP(launch_mlp_forward(mlp->d, feat, mm, r_hat, stream), "network forward kernel");
+    STEP(launch_fallback(r_hat, d1sq, qx, qy, mm, g->dev, ap, rule, delta, r_sat_lo, r_sat_hi, alpha_f, keys, vals,
+                         count, stream),
+         "fallback kernel");
+    // fallback queries first, in cell order (the sentinel key nCells sorts the others last)
+    STEP(radix_sort_pairs(keys, vals, tk, tv, mm, bits_for(g->host.ncells + 1), hist, scan, stream), "fallback sort");
+    STEP(launch_knn(g->dev, g->cell_start, g->sx, g->sy, g->sidx, qx, qy, vals, count, mm, p->k, slack_cells(g->host),
+                    r_obs, d1sq, nullptr, stream),
+         "kNN kernel");
+    STEP(launch_alpha_fallback(vals, count, mm, r_obs, ap, alpha_f, stream), "alpha kernel");
+#undef STEP
+    int q = 0, split = 0;
+    if (st == AIDW_OK)
+      st = interp_impl(x, y, z, n, qx, qy, m, nullptr, d1sq, p, g, qz, alpha_out, stream, ev ? ev[2] : nullptr,
+                       ev ? ev[3] : nullptr, &q, &split, alpha_f);
+    if (st == AIDW_OK && r_hat_out)
+      if ((e = hipMemcpyAsync(r_hat_out, r_hat, sizeof(float) * m, hipMemcpyDeviceToDevice, stream)) != hipSuccess)
+        st = hip_fail(e, "copying predictions");
+    if (st == AIDW_OK && fallback_count)
+      if ((e = hipMemcpyAsync(&host_count, count, sizeof(uint32_t), hipMemcpyDeviceToHost, stream)) != hipSuccess)
+        st = hip_fail(e, "reading the fallback count");
+    if (st == AIDW_OK && ev) {
+      if ((e = hipEventRecord(ev[4], stream)) != hipSuccess) st = hip_fail(e, "event");
+      g_tm.valid = st == AIDW_OK;
+      g_tm.q = q;
+      g_tm.split = split;
+    }
+  }
+  aidw_grid_destroy(g);
+  if (st == AIDW_OK && fallback_count) {
+    hipError_t e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) return hip_fail(e, "synchronising");
+    *fallback_count = host_count;
+  }
   return st;
 }
 

@@ -327,7 +327,32 @@ __global__ __launch_bounds__(256) void k_gather(const uint32_t* __restrict__ val
 
 inline int div_up(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
 
+// 32-bit finaliser of MurmurHash3 (Appleby): a bijective avalanche mix.
+__device__ inline uint32_t fmix32(uint32_t h) {
+  h ^= h >> 16;
+  h *= 0x85ebca6bu;
+  h ^= h >> 13;
+  h *= 0xc2b2ae35u;
+  h ^= h >> 16;
+  return h;
+}
+
+__global__ __launch_bounds__(256) void k_shuffle_keys(uint32_t seed_lo, uint32_t seed_hi, int epoch, int count,
+                                                      uint32_t* __restrict__ keys, uint32_t* __restrict__ vals) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= count) return;
+  keys[i] = fmix32(fmix32((uint32_t)i ^ seed_lo) + fmix32((uint32_t)epoch ^ seed_hi));
+  vals[i] = (uint32_t)i;
+}
+
 }  // namespace
+
+hipError_t launch_shuffle_keys(uint64_t seed, int epoch, int count, uint32_t* keys, uint32_t* vals, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_shuffle_keys, dim3(div_up(count, 256)), dim3(256), 0, s, (uint32_t)seed,
+                     (uint32_t)(seed >> 32), epoch, count, keys, vals);
+  return hipGetLastError();
+}
 
 hipError_t launch_bounds(const float* x, const float* y, int n, const float* qx, const float* qy, int m,
                          BoundsPartial* partial, hipStream_t s) {

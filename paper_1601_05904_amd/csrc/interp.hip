@@ -139,6 +139,17 @@ __global__ __launch_bounds__(256) void k_alpha_class(const float* __restrict__ r
   vals[q] = (uint32_t)q;
 }
 
+__global__ __launch_bounds__(256) void k_class_keys(const float* __restrict__ alpha_f, int m,
+                                                    uint32_t* __restrict__ keys, uint32_t* __restrict__ vals) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= m) return;
+  const float a = alpha_f[q];
+  uint32_t key = 0;
+  if (a >= 1.0f && a <= (float)kMaxIntPow && a == floorf(a)) key = (uint32_t)a;
+  keys[q] = key;
+  vals[q] = (uint32_t)q;
+}
+
 // Queries are taken in class order: slot (block, j, thread) -> position -> query perm[position].
 // A class launch (POW > 0) takes only blocks whose queries all have key POW; the general launch
 // (POW == 0) skips the blocks that a class launch takes (fast_mask bit set for that key).
@@ -349,6 +360,12 @@ hipError_t launch_alpha_class(const float* r_obs, int m, const AlphaParams& ap, 
   if (m <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_alpha_class, dim3((m + 255) / 256), dim3(256), 0, s, r_obs, m, ap, alpha_f, alpha_out, keys,
                      vals);
+  return hipGetLastError();
+}
+
+hipError_t launch_class_keys(const float* alpha_f, int m, uint32_t* keys, uint32_t* vals, hipStream_t s) {
+  if (m <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_class_keys, dim3((m + 255) / 256), dim3(256), 0, s, alpha_f, m, keys, vals);
   return hipGetLastError();
 }
 

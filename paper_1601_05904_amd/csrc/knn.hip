@@ -41,11 +41,12 @@ template <int KMAX>
 __global__ __launch_bounds__(256) void k_knn(const GridScalars* __restrict__ gs, const int32_t* __restrict__ cell_start,
                                              const float* __restrict__ sx, const float* __restrict__ sy,
                                              const int32_t* __restrict__ sidx, const float* __restrict__ qx,
-                                             const float* __restrict__ qy, const uint32_t* __restrict__ qperm, int m,
-                                             int k, double slack_cells, float* __restrict__ r_obs,
-                                             float* __restrict__ d1sq, int32_t* __restrict__ nn_idx) {
+                                             const float* __restrict__ qy, const uint32_t* __restrict__ qperm,
+                                             const uint32_t* __restrict__ active, int m, int k, double slack_cells,
+                                             float* __restrict__ r_obs, float* __restrict__ d1sq,
+                                             int32_t* __restrict__ nn_idx) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= m) return;
+  if (t >= m || (active && (uint32_t)t >= *active)) return;
   const int q = qperm ? (int)qperm[t] : t;
   const float fx = qx[q], fy = qy[q];
   const double px = fx, py = fy;
@@ -156,21 +157,22 @@ __global__ __launch_bounds__(256) void k_knn(const GridScalars* __restrict__ gs,
 }  // namespace
 
 hipError_t launch_knn(const GridScalars* gs, const int32_t* cell_start, const float* sx, const float* sy,
-                      const int32_t* sidx, const float* qx, const float* qy, const uint32_t* qperm, int m, int k,
-                      double slack_cells, float* r_obs, float* d1sq, int32_t* nn_idx, hipStream_t s) {
+                      const int32_t* sidx, const float* qx, const float* qy, const uint32_t* qperm,
+                      const uint32_t* active, int m, int k, double slack_cells, float* r_obs, float* d1sq,
+                      int32_t* nn_idx, hipStream_t s) {
   if (m <= 0) return hipSuccess;
   const dim3 grid((m + 255) / 256), block(256);
   if (k <= 8)
-    hipLaunchKernelGGL(k_knn<8>, grid, block, 0, s, gs, cell_start, sx, sy, sidx, qx, qy, qperm, m, k, slack_cells,
+    hipLaunchKernelGGL(k_knn<8>, grid, block, 0, s, gs, cell_start, sx, sy, sidx, qx, qy, qperm, active, m, k, slack_cells,
                        r_obs, d1sq, nn_idx);
   else if (k <= 16)
-    hipLaunchKernelGGL(k_knn<16>, grid, block, 0, s, gs, cell_start, sx, sy, sidx, qx, qy, qperm, m, k, slack_cells,
+    hipLaunchKernelGGL(k_knn<16>, grid, block, 0, s, gs, cell_start, sx, sy, sidx, qx, qy, qperm, active, m, k, slack_cells,
                        r_obs, d1sq, nn_idx);
   else if (k <= 32)
-    hipLaunchKernelGGL(k_knn<32>, grid, block, 0, s, gs, cell_start, sx, sy, sidx, qx, qy, qperm, m, k, slack_cells,
+    hipLaunchKernelGGL(k_knn<32>, grid, block, 0, s, gs, cell_start, sx, sy, sidx, qx, qy, qperm, active, m, k, slack_cells,
                        r_obs, d1sq, nn_idx);
   else
-    hipLaunchKernelGGL(k_knn<64>, grid, block, 0, s, gs, cell_start, sx, sy, sidx, qx, qy, qperm, m, k, slack_cells,
+    hipLaunchKernelGGL(k_knn<64>, grid, block, 0, s, gs, cell_start, sx, sy, sidx, qx, qy, qperm, active, m, k, slack_cells,
                        r_obs, d1sq, nn_idx);
   return hipGetLastError();
 }

@@ -1,0 +1,481 @@
+// Learned-R form: a small network predicts the nearest-neighbour statistic R of
+// Eq. 4 from the grid's occupancy around each query, so that most queries skip
+// the kNN search of Section 3.2.4; exact kNN remains the fallback wherever the
+// prediction could change alpha (Eq. 5, 6).
+//
+// Network (27 -> 64 -> 64 -> 1):
+//   x  = bf16(features)                     (5 x 5 cell counts / mean occupancy, in-cell offsets)
+//   h1 = bf16(gelu(W1 x + b1)),  h2 = bf16(gelu(W2 h1 + b2)),  y = W3 h2 + b3
+// with bf16 weights and activations as operands and float32 accumulation
+// (v_dot2c_f32_bf16: two products per lane per instruction), gelu the tanh form
+// u / 2 (1 + tanh(sqrt(2 / pi) (u + 0.044715 u^3))).  All lanes of a wavefront
+// use the same weights, so the weights are read through the scalar cache into
+// SGPRs and every dot instruction takes its weight pair as a scalar operand.
+// Training: per-sample forward and backward in one kernel (one sample per lane),
+// the weight gradients summed over the batch in a fixed order, then Adam on the
+// float32 master weights and a repack of the bf16 copies.
+#include <float.h>
+
+#include "aidw_internal.h"
+
+namespace aidw {
+
+namespace {
+
+typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
+
+constexpr int kIn = 27;
+constexpr int kInPairs = 14;  // 27 inputs + one zero pad
+constexpr int kH = 64;
+constexpr int kHPairs = 32;
+
+__device__ inline uint32_t bf16_bits(float f) {
+  uint32_t u = __float_as_uint(f);
+  u += 0x7FFFu + ((u >> 16) & 1u);  // round to nearest, ties to even
+  return u >> 16;
+}
+__device__ inline float bf16_round(float f) { return __uint_as_float(bf16_bits(f) << 16); }
+__device__ inline uint32_t pack_bf16(float lo, float hi) { return bf16_bits(lo) | (bf16_bits(hi) << 16); }
+__device__ inline float dot2(uint32_t a, uint32_t b, float c) {
+  return __builtin_amdgcn_fdot2_f32_bf16(__builtin_bit_cast(bf16x2_t, a), __builtin_bit_cast(bf16x2_t, b), c, false);
+}
+
+constexpr float kGeluC = 0.7978845608028654f;  // sqrt(2 / pi)
+constexpr float kGeluA = 0.044715f;
+
+__device__ inline float tanh_f(float v) {
+  // tanh(v) = 1 - 2 / (exp(2v) + 1); exp overflow gives 1, underflow gives -1
+  const float e = __builtin_amdgcn_exp2f(2.8853900817779268f * v);  // 2 / ln 2
+  return 1.0f - 2.0f * __builtin_amdgcn_rcpf(e + 1.0f);
+}
+__device__ inline float gelu_f(float u) {
+  const float t = tanh_f(kGeluC * (u + kGeluA * u * u * u));
+  return 0.5f * u * (1.0f + t);
+}
+__device__ inline float gelu_grad_f(float u) {
+  const float t = tanh_f(kGeluC * (u + kGeluA * u * u * u));
+  return 0.5f * (1.0f + t) + 0.5f * u * (1.0f - t * t) * kGeluC * (1.0f + 3.0f * kGeluA * u * u);
+}
+
+__device__ inline int clamp_cell(float t, int nc) {
+  if (!(t >= 0.0f)) return 0;
+  if (t >= 2147483520.0f) return nc - 1;
+  const int c = (int)t;
+  return c > nc - 1 ? nc - 1 : c;
+}
+
+// ---- features -------------------------------------------------------------------
+
+// Per query: 25 cell counts of the 5 x 5 block around its cell (0 outside the grid)
+// times nCells / n, its in-cell offsets, and d1sq: the exact squared distance to its
+// nearest data point when that point lies in the surrounding 3 x 3 block of cells
+// and nearer than the block's open sides, otherwise a lower bound (the squared
+// distance to those sides).  d1sq is exactly 0 iff the query coincides with a point.
+__global__ __launch_bounds__(256) void k_features(const GridScalars* __restrict__ gs,
+                                                  const int32_t* __restrict__ cell_start,
+                                                  const float* __restrict__ sx, const float* __restrict__ sy,
+                                                  const float* __restrict__ qx, const float* __restrict__ qy, int m,
+                                                  double inv_occ, double slack_cells, float* __restrict__ feat,
+                                                  float* __restrict__ d1sq) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= m) return;
+  const float minx = gs->minx, miny = gs->miny, inv = gs->inv_cw;
+  const int ncol = gs->ncol, nrow = gs->nrow;
+  const float fx = qx[q], fy = qy[q];
+  const float tx = (fx - minx) * inv;
+  const float ty = (fy - miny) * inv;
+  const int c0 = clamp_cell(tx, ncol), r0 = clamp_cell(ty, nrow);
+  float* f = feat + (size_t)q * kIn;
+#pragma unroll
+  for (int dr = -2; dr <= 2; ++dr) {
+    const int r = r0 + dr;
+#pragma unroll
+    for (int dc = -2; dc <= 2; ++dc) {
+      const int c = c0 + dc;
+      int cnt = 0;
+      if (r >= 0 && r < nrow && c >= 0 && c < ncol) {
+        const int cell = r * ncol + c;
+        cnt = cell_start[cell + 1] - cell_start[cell];
+      }
+      f[(dr + 2) * 5 + (dc + 2)] = (float)((double)cnt * inv_occ);
+    }
+  }
+  f[25] = tx - (float)c0;
+  f[26] = ty - (float)r0;
+  if (!d1sq) return;
+  // nearest point in the 3 x 3 block
+  const double px = fx, py = fy;
+  double best = INFINITY;
+  const int ca = c0 > 0 ? c0 - 1 : 0, cb = c0 + 1 < ncol ? c0 + 1 : ncol - 1;
+  for (int r = r0 - 1; r <= r0 + 1; ++r) {
+    if (r < 0 || r >= nrow) continue;
+    const int p1 = cell_start[r * ncol + cb + 1];
+    for (int p = cell_start[r * ncol + ca]; p < p1; ++p) {
+      const double dx = (double)sx[p] - px;
+      const double dy = (double)sy[p] - py;
+      const double d2 = dx * dx + dy * dy;
+      best = d2 < best ? d2 : best;
+    }
+  }
+  const double cwd = gs->cwd, minxd = minx, minyd = miny;
+  double dout = INFINITY;
+  if (c0 - 1 > 0) dout = fmin(dout, px - (minxd + (double)(c0 - 1) * cwd));
+  if (c0 + 1 < ncol - 1) dout = fmin(dout, (minxd + (double)(c0 + 2) * cwd) - px);
+  if (r0 - 1 > 0) dout = fmin(dout, py - (minyd + (double)(r0 - 1) * cwd));
+  if (r0 + 1 < nrow - 1) dout = fmin(dout, (minyd + (double)(r0 + 2) * cwd) - py);
+  dout -= slack_cells * cwd;
+  double v;
+  if (dout == INFINITY || best < dout * dout)
+    v = best;                       // exact nearest distance
+  else
+    v = dout > 0 ? dout * dout : 0; // lower bound
+  d1sq[q] = v == 0.0 ? (best == 0.0 ? 0.0f : FLT_MIN) : fmaxf((float)v, FLT_MIN);
+}
+
+// ---- network ------------------------------------------------------------------------
+
+// Layer weights in the kernels' layout: bf16 pairs for the forward, float32 values of
+// the rounded weights for the backward.
+struct MlpWeights {
+  const uint32_t* w1p;  // [64][14]
+  const uint32_t* w2p;  // [64][32]
+  const uint32_t* w3p;  // [32]
+  const float* w2r;     // [64][64]
+  const float* w3r;     // [64]
+  const float* master;  // float32 parameters (biases are read from here)
+};
+
+constexpr int kOffW1 = 0, kOffB1 = 64 * 27, kOffW2 = kOffB1 + 64, kOffB2 = kOffW2 + 64 * 64, kOffW3 = kOffB2 + 64,
+              kOffB3 = kOffW3 + 64, kParams = kOffB3 + 1;
+static_assert(kParams == AIDW_MLP_PARAMS, "parameter layout");
+
+__device__ inline void load_x(const float* __restrict__ f, uint32_t* xp) {
+#pragma unroll
+  for (int p = 0; p < kInPairs; ++p) {
+    const float lo = f[2 * p];
+    const float hi = 2 * p + 1 < kIn ? f[2 * p + 1] : 0.0f;
+    xp[p] = pack_bf16(lo, hi);
+  }
+}
+
+// a1 = W1 x + b1 for one output row
+__device__ inline float layer1_row(const MlpWeights& w, const uint32_t* xp, int o) {
+  float acc = w.master[kOffB1 + o];
+#pragma unroll
+  for (int p = 0; p < kInPairs; ++p) acc = dot2(w.w1p[o * kInPairs + p], xp[p], acc);
+  return acc;
+}
+__device__ inline float layer2_row(const MlpWeights& w, const uint32_t* hp, int o) {
+  float acc = w.master[kOffB2 + o];
+#pragma unroll
+  for (int p = 0; p < kHPairs; ++p) acc = dot2(w.w2p[o * kHPairs + p], hp[p], acc);
+  return acc;
+}
+__device__ inline float layer3(const MlpWeights& w, const uint32_t* hp) {
+  float acc = w.master[kOffB3];
+#pragma unroll
+  for (int p = 0; p < kHPairs; ++p) acc = dot2(w.w3p[p], hp[p], acc);
+  return acc;
+}
+
+__global__ __launch_bounds__(256) void k_mlp_forward(MlpWeights w, const float* __restrict__ feat, int m,
+                                                     float* __restrict__ out) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= m) return;
+  uint32_t xp[kInPairs], h1p[kHPairs], h2p[kHPairs];
+  load_x(feat + (size_t)q * kIn, xp);
+#pragma unroll
+  for (int o = 0; o < kH; o += 2) {
+    const float a = gelu_f(layer1_row(w, xp, o)), b = gelu_f(layer1_row(w, xp, o + 1));
+    h1p[o / 2] = pack_bf16(a, b);
+  }
+#pragma unroll
+  for (int o = 0; o < kH; o += 2) {
+    const float a = gelu_f(layer2_row(w, h1p, o)), b = gelu_f(layer2_row(w, h1p, o + 1));
+    h2p[o / 2] = pack_bf16(a, b);
+  }
+  out[q] = layer3(w, h2p);
+}
+
+// One sample per lane: forward, loss term, and the per-sample backward down to the
+// pre-activation gradients; saves the operands of the weight gradients, sample-major.
+__global__ __launch_bounds__(64) void k_mlp_train_sample(MlpWeights w, const float* __restrict__ feat,
+                                                         const float* __restrict__ target,
+                                                         const uint32_t* __restrict__ sel, int B, float two_over_b,
+                                                         float* __restrict__ s_x, float* __restrict__ s_h1,
+                                                         float* __restrict__ s_h2, float* __restrict__ s_da1,
+                                                         float* __restrict__ s_da2, float* __restrict__ s_dy,
+                                                         float* __restrict__ s_err2) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= B) return;
+  const int j = sel ? (int)sel[b] : b;
+  uint32_t xp[kInPairs], h1p[kHPairs], h2p[kHPairs];
+  float a1[kH], a2[kH];
+  load_x(feat + (size_t)j * kIn, xp);
+#pragma unroll
+  for (int o = 0; o < kH; o += 2) {
+    a1[o] = layer1_row(w, xp, o);
+    a1[o + 1] = layer1_row(w, xp, o + 1);
+    h1p[o / 2] = pack_bf16(gelu_f(a1[o]), gelu_f(a1[o + 1]));
+  }
+#pragma unroll
+  for (int o = 0; o < kH; o += 2) {
+    a2[o] = layer2_row(w, h1p, o);
+    a2[o + 1] = layer2_row(w, h1p, o + 1);
+    h2p[o / 2] = pack_bf16(gelu_f(a2[o]), gelu_f(a2[o + 1]));
+  }
+  const float y = layer3(w, h2p);
+  const float err = y - target[j];
+  const float dy = two_over_b * err;
+  s_dy[b] = dy;
+  s_err2[b] = err * err;
+#pragma unroll
+  for (int p = 0; p < kInPairs; ++p) {
+    s_x[(size_t)b * 28 + 2 * p] = __uint_as_float(xp[p] << 16);
+    s_x[(size_t)b * 28 + 2 * p + 1] = __uint_as_float(xp[p] & 0xFFFF0000u);
+  }
+#pragma unroll
+  for (int p = 0; p < kHPairs; ++p) {
+    s_h1[(size_t)b * kH + 2 * p] = __uint_as_float(h1p[p] << 16);
+    s_h1[(size_t)b * kH + 2 * p + 1] = __uint_as_float(h1p[p] & 0xFFFF0000u);
+    s_h2[(size_t)b * kH + 2 * p] = __uint_as_float(h2p[p] << 16);
+    s_h2[(size_t)b * kH + 2 * p + 1] = __uint_as_float(h2p[p] & 0xFFFF0000u);
+  }
+  // da2 = dy * W3 * gelu'(a2)
+#pragma unroll
+  for (int i = 0; i < kH; ++i) {
+    a2[i] = dy * w.w3r[i] * gelu_grad_f(a2[i]);
+    s_da2[(size_t)b * kH + i] = a2[i];
+  }
+  // da1 = (W2^T da2) * gelu'(a1)
+#pragma unroll
+  for (int c = 0; c < kH; ++c) {
+    float acc = 0.0f;
+#pragma unroll
+    for (int i = 0; i < kH; ++i) acc = __builtin_fmaf(w.w2r[i * kH + c], a2[i], acc);
+    s_da1[(size_t)b * kH + c] = acc * gelu_grad_f(a1[c]);
+  }
+}
+
+// grad[p] = sum over the batch (in sample order) of the parameter's two operands;
+// grad[kParams] = mean squared error of the batch.
+__global__ __launch_bounds__(256) void k_mlp_wgrad(int B, const float* __restrict__ s_x,
+                                                   const float* __restrict__ s_h1, const float* __restrict__ s_h2,
+                                                   const float* __restrict__ s_da1, const float* __restrict__ s_da2,
+                                                   const float* __restrict__ s_dy, const float* __restrict__ s_err2,
+                                                   float* __restrict__ grad) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p > kParams) return;
+  float acc = 0.0f;
+  if (p < kOffB1) {
+    const int o = p / kIn, i = p % kIn;
+    for (int b = 0; b < B; ++b) acc = __builtin_fmaf(s_da1[(size_t)b * kH + o], s_x[(size_t)b * 28 + i], acc);
+  } else if (p < kOffW2) {
+    const int o = p - kOffB1;
+    for (int b = 0; b < B; ++b) acc += s_da1[(size_t)b * kH + o];
+  } else if (p < kOffB2) {
+    const int o = (p - kOffW2) / kH, i = (p - kOffW2) % kH;
+    for (int b = 0; b < B; ++b) acc = __builtin_fmaf(s_da2[(size_t)b * kH + o], s_h1[(size_t)b * kH + i], acc);
+  } else if (p < kOffW3) {
+    const int o = p - kOffB2;
+    for (int b = 0; b < B; ++b) acc += s_da2[(size_t)b * kH + o];
+  } else if (p < kOffB3) {
+    const int i = p - kOffW3;
+    for (int b = 0; b < B; ++b) acc = __builtin_fmaf(s_dy[b], s_h2[(size_t)b * kH + i], acc);
+  } else if (p == kOffB3) {
+    for (int b = 0; b < B; ++b) acc += s_dy[b];
+  } else {
+    for (int b = 0; b < B; ++b) acc += s_err2[b];
+    acc /= (float)B;
+  }
+  grad[p] = acc;
+}
+
+// Adam on the float32 masters.
+__global__ __launch_bounds__(256) void k_adam(float* __restrict__ master, const float* __restrict__ grad,
+                                              float* __restrict__ mom, float* __restrict__ vel, float lr, float b1,
+                                              float b2, float eps, float bc1, float bc2) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= kParams) return;
+  const float g = grad[p];
+  const float mm = b1 * mom[p] + (1.0f - b1) * g;
+  const float vv = b2 * vel[p] + (1.0f - b2) * g * g;
+  mom[p] = mm;
+  vel[p] = vv;
+  master[p] -= lr * (mm / bc1) / (sqrtf(vv / bc2) + eps);
+}
+
+// bf16 copies of the weights in the kernels' layout.
+__global__ __launch_bounds__(256) void k_mlp_repack(const float* __restrict__ master, uint32_t* __restrict__ w1p,
+                                                    uint32_t* __restrict__ w2p, uint32_t* __restrict__ w3p,
+                                                    float* __restrict__ w2r, float* __restrict__ w3r) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < kH * kInPairs) {
+    const int o = t / kInPairs, p = t % kInPairs;
+    const float lo = master[kOffW1 + o * kIn + 2 * p];
+    const float hi = 2 * p + 1 < kIn ? master[kOffW1 + o * kIn + 2 * p + 1] : 0.0f;
+    w1p[t] = pack_bf16(lo, hi);
+  }
+  if (t < kH * kHPairs) {
+    const int o = t / kHPairs, p = t % kHPairs;
+    w2p[t] = pack_bf16(master[kOffW2 + o * kH + 2 * p], master[kOffW2 + o * kH + 2 * p + 1]);
+  }
+  if (t < kHPairs) w3p[t] = pack_bf16(master[kOffW3 + 2 * t], master[kOffW3 + 2 * t + 1]);
+  if (t < kH * kH) w2r[t] = bf16_round(master[kOffW2 + t]);
+  if (t < kH) w3r[t] = bf16_round(master[kOffW3 + t]);
+}
+
+// Loss of batch `step` into epoch_loss[epoch] (a single thread: fixed order).
+__global__ void k_accumulate_loss(const float* __restrict__ grad, float* __restrict__ epoch_loss, int epoch,
+                                  float scale) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) epoch_loss[epoch] += grad[kParams] * scale;
+}
+
+// ---- learned run: fallback decision -----------------------------------------------------
+
+// Per query, from the prediction r_hat of R: fall back to exact kNN when the
+// prediction could change alpha, else take alpha from the rule.  Fallback queries
+// get key = their cell (to be binned for the kNN kernel), the others the sentinel
+// nCells so that they sort last.  count receives the number of fallback queries.
+//   rule 0 (literal): fall back when |r_hat - R_min| < delta or |r_hat - R_max| < delta;
+//                     other queries use alpha(mu(r_hat)) by Eq. 5, 6.
+//   rule 1 (alpha-exact): skip only when r_hat >= r_sat_hi + delta (alpha = alpha_5) or
+//                     r_hat <= r_sat_lo - delta (alpha = alpha_1), where mu = 0.9 / 0.1.
+// Coincident queries (d1sq == 0) always fall back.
+__device__ inline double fuzzy_mu_l(double R, double rmin, double rmax) {
+  if (R <= rmin) return 0.0;
+  if (R >= rmax) return 1.0;
+  return 0.5 - 0.5 * cos((M_PI / rmax) * (R - rmin));
+}
+__device__ inline double level_alpha_l(double mu, const double* a) {
+  if (mu <= 0.1) return a[0];
+  if (mu <= 0.3) return a[0] * (1.0 - 5.0 * (mu - 0.1)) + 5.0 * a[1] * (mu - 0.1);
+  if (mu <= 0.5) return 5.0 * a[2] * (mu - 0.3) + a[1] * (1.0 - 5.0 * (mu - 0.3));
+  if (mu <= 0.7) return a[2] * (1.0 - 5.0 * (mu - 0.5)) + 5.0 * a[3] * (mu - 0.5);
+  if (mu <= 0.9) return 5.0 * a[4] * (mu - 0.7) + a[3] * (1.0 - 5.0 * (mu - 0.7));
+  return a[4];
+}
+
+__global__ __launch_bounds__(256) void k_fallback(const float* __restrict__ r_hat, const float* __restrict__ d1sq,
+                                                  const float* __restrict__ qx, const float* __restrict__ qy, int m,
+                                                  const GridScalars* __restrict__ gs, AlphaParams ap, int rule,
+                                                  double delta, double r_sat_lo, double r_sat_hi,
+                                                  float* __restrict__ alpha_f, uint32_t* __restrict__ keys,
+                                                  uint32_t* __restrict__ vals, uint32_t* __restrict__ count) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= m) return;
+  const double R = r_hat[q];
+  bool fall = d1sq[q] == 0.0f || !isfinite(R);
+  double alpha = 0.0;
+  if (!fall) {
+    if (rule == 0) {
+      fall = fabs(R - ap.r_min) < delta || fabs(R - ap.r_max) < delta;
+      alpha = level_alpha_l(fuzzy_mu_l(R, ap.r_min, ap.r_max), ap.levels);
+    } else if (R >= r_sat_hi + delta) {
+      alpha = ap.levels[4];
+    } else if (R <= r_sat_lo - delta) {
+      alpha = ap.levels[0];
+    } else {
+      fall = true;
+    }
+  }
+  vals[q] = (uint32_t)q;
+  if (fall) {
+    const int ncol = gs->ncol, nrow = gs->nrow;
+    const int c = clamp_cell((qx[q] - gs->minx) * gs->inv_cw, ncol);
+    const int r = clamp_cell((qy[q] - gs->miny) * gs->inv_cw, nrow);
+    keys[q] = (uint32_t)(r * ncol + c);
+    atomicAdd(count, 1u);
+  } else {
+    keys[q] = (uint32_t)gs->ncells;
+    alpha_f[q] = (float)alpha;
+  }
+}
+
+// Eq. 4-6 for the fallback queries (the first *count entries of perm) from their exact r_obs.
+__global__ __launch_bounds__(256) void k_alpha_fallback(const uint32_t* __restrict__ perm,
+                                                        const uint32_t* __restrict__ count,
+                                                        const float* __restrict__ r_obs, AlphaParams ap,
+                                                        float* __restrict__ alpha_f) {
+  const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= *count) return;
+  const uint32_t q = perm[t];
+  const double R = (double)r_obs[q] / ap.r_exp;
+  alpha_f[q] = (float)level_alpha_l(fuzzy_mu_l(R, ap.r_min, ap.r_max), ap.levels);
+}
+
+}  // namespace
+
+hipError_t launch_features(const GridScalars* gs, const int32_t* cell_start, const float* sx, const float* sy,
+                           const float* qx, const float* qy, int m, double inv_occ, double slack_cells, float* feat,
+                           float* d1sq, hipStream_t s) {
+  if (m <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_features, dim3((m + 255) / 256), dim3(256), 0, s, gs, cell_start, sx, sy, qx, qy, m, inv_occ,
+                     slack_cells, feat, d1sq);
+  return hipGetLastError();
+}
+
+static MlpWeights weights(const MlpDevice& d) {
+  return MlpWeights{d.w1p, d.w2p, d.w3p, d.w2r, d.w3r, d.master};
+}
+
+hipError_t launch_mlp_repack(const MlpDevice& d, hipStream_t s) {
+  hipLaunchKernelGGL(k_mlp_repack, dim3((kH * kH + 255) / 256), dim3(256), 0, s, d.master, d.w1p, d.w2p, d.w3p, d.w2r,
+                     d.w3r);
+  return hipGetLastError();
+}
+
+hipError_t launch_mlp_forward(const MlpDevice& d, const float* feat, int m, float* out, hipStream_t s) {
+  if (m <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_mlp_forward, dim3((m + 255) / 256), dim3(256), 0, s, weights(d), feat, m, out);
+  return hipGetLastError();
+}
+
+size_t mlp_batch_scratch_floats(int B) { return (size_t)B * (28 + 4 * kH + 2); }
+
+hipError_t launch_mlp_gradients(const MlpDevice& d, const float* feat, const float* target, const uint32_t* sel, int B,
+                                float* scratch, float* grad, hipStream_t s) {
+  float* s_x = scratch;
+  float* s_h1 = s_x + (size_t)B * 28;
+  float* s_h2 = s_h1 + (size_t)B * kH;
+  float* s_da1 = s_h2 + (size_t)B * kH;
+  float* s_da2 = s_da1 + (size_t)B * kH;
+  float* s_dy = s_da2 + (size_t)B * kH;
+  float* s_err2 = s_dy + B;
+  hipLaunchKernelGGL(k_mlp_train_sample, dim3((B + 63) / 64), dim3(64), 0, s, weights(d), feat, target, sel, B,
+                     2.0f / (float)B, s_x, s_h1, s_h2, s_da1, s_da2, s_dy, s_err2);
+  hipLaunchKernelGGL(k_mlp_wgrad, dim3((kParams + 1 + 255) / 256), dim3(256), 0, s, B, s_x, s_h1, s_h2, s_da1, s_da2,
+                     s_dy, s_err2, grad);
+  return hipGetLastError();
+}
+
+hipError_t launch_adam(const MlpDevice& d, const float* grad, float lr, float b1, float b2, float eps, float bc1,
+                       float bc2, hipStream_t s) {
+  hipLaunchKernelGGL(k_adam, dim3((kParams + 255) / 256), dim3(256), 0, s, d.master, grad, d.mom, d.vel, lr, b1, b2,
+                     eps, bc1, bc2);
+  return hipGetLastError();
+}
+
+hipError_t launch_accumulate_loss(const float* grad, float* epoch_loss, int epoch, float scale, hipStream_t s) {
+  hipLaunchKernelGGL(k_accumulate_loss, dim3(1), dim3(64), 0, s, grad, epoch_loss, epoch, scale);
+  return hipGetLastError();
+}
+
+hipError_t launch_fallback(const float* r_hat, const float* d1sq, const float* qx, const float* qy, int m,
+                           const GridScalars* gs, const AlphaParams& ap, int rule, double delta, double r_sat_lo,
+                           double r_sat_hi, float* alpha_f, uint32_t* keys, uint32_t* vals, uint32_t* count,
+                           hipStream_t s) {
+  if (m <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fallback, dim3((m + 255) / 256), dim3(256), 0, s, r_hat, d1sq, qx, qy, m, gs, ap, rule, delta,
+                     r_sat_lo, r_sat_hi, alpha_f, keys, vals, count);
+  return hipGetLastError();
+}
+
+hipError_t launch_alpha_fallback(const uint32_t* perm, const uint32_t* count, int m, const float* r_obs,
+                                 const AlphaParams& ap, float* alpha_f, hipStream_t s) {
+  if (m <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_alpha_fallback, dim3((m + 255) / 256), dim3(256), 0, s, perm, count, r_obs, ap, alpha_f);
+  return hipGetLastError();
+}
+
+}  // namespace aidw

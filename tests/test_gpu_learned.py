@@ -1,0 +1,220 @@
+"""Learned-R form on the GPU through the C ABI: features bit-exact against the
+oracle, network forward and gradient against the FP64 reference on the same
+bf16 operands, training, checkpointing, the fallback mechanics of
+aidw_run_learned, and the gain of a trained network over exact kNN."""
+import os
+import tempfile
+
+import numpy as np
+import pytest
+
+import oracle as O
+import oracle.mlp as OM
+from paper_1601_05904_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def T():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1601_05904_amd as aidw
+    aidw.load(build_if_missing=False)
+    return torch
+
+
+def mods():
+    import paper_1601_05904_amd as aidw
+    import paper_1601_05904_amd.learned as L
+    return aidw, L
+
+
+def dev(T, a):
+    return T.from_numpy(np.ascontiguousarray(a)).to("cuda")
+
+
+def random_params(seed, scale=0.35):
+    rng = np.random.default_rng(seed)
+    p = rng.standard_normal(OM.N_PARAMS) * scale
+    p[-1] = 1.5
+    return p.astype(np.float32)
+
+
+# ------------------------------------------------------------------ features
+
+@pytest.mark.parametrize("case", ["uniform", "mixture", "edges"])
+def test_features_match_oracle(T, case):
+    aidw, L = mods()
+    if case == "uniform":
+        ds = W.make(8000, 3000, 15, 201)
+    elif case == "mixture":
+        ds = W.make(20000, 4000, 15, 202, "mixture", 16)
+    else:
+        ds = W.make(3000, 500, 15, 203)
+        ds.qx[:4] = [0.0, 1.0 - 2 ** -20, 0.0, 1.0 - 2 ** -20]
+        ds.qy[:4] = [0.0, 0.0, 1.0 - 2 ** -20, 1.0 - 2 ** -20]
+        ds.qx[4], ds.qy[4] = ds.x[17], ds.y[17]  # coincident with a data point
+    x, y, qx, qy = (dev(T, getattr(ds, a)) for a in ("x", "y", "qx", "qy"))
+    g = aidw.build_grid(x, y, qx, qy, aidw.Params(k=15))
+    d = g.describe()
+    f, d1 = L.features(g, qx, qy)
+    g.close()
+    ref = O.features(ds.x, ds.y, ds.qx, ds.qy, d["min_x"], d["min_y"], d["inv_cell_width"], d["ncol"], d["nrow"])
+    assert np.array_equal(f.cpu().numpy(), ref)
+    # d1sq: exact when the nearest point is nearer than one cell width, a lower bound otherwise
+    _, kd = O.knn(ds.x, ds.y, ds.qx, ds.qy, 1)
+    exact = kd[:, 0].astype(np.float32)
+    got = d1.cpu().numpy()
+    near = np.sqrt(kd[:, 0]) < 0.999 * d["cell_width"]
+    assert np.array_equal(got[near], exact[near])
+    assert np.all(got <= exact * (1 + 1e-6))
+    if case == "edges":
+        assert got[4] == 0.0
+
+
+# ------------------------------------------------------------------ network
+
+def test_forward_matches_fp64_reference(T):
+    aidw, L = mods()
+    ds = W.make(20000, 6000, 15, 211, "mixture", 8)
+    x, y, qx, qy = (dev(T, getattr(ds, a)) for a in ("x", "y", "qx", "qy"))
+    g = aidw.build_grid(x, y, qx, qy, aidw.Params(k=15))
+    f, _ = L.features(g, qx, qy, want_d1sq=False)
+    g.close()
+    params = random_params(5)
+    mlp = L.MLP(seed=1)
+    mlp.set_params(params)
+    assert np.array_equal(mlp.get_params(), params)
+    yk = mlp.forward(f).cpu().numpy().astype(np.float64)
+    yo, _ = OM.forward(params.astype(np.float64), f.cpu().numpy())
+    err = np.abs(yk - yo) / (1.0 + np.abs(yo))
+    # differences come from float32 vs float64 arithmetic and rare one-ulp bf16 flips of an activation
+    assert np.median(err) < 1e-5 and np.quantile(err, 0.99) < 1e-3 and err.max() < 2e-2
+
+
+def test_gradients_match_fp64_reference(T):
+    aidw, L = mods()
+    rng = np.random.default_rng(221)
+    B = 700
+    feat = (rng.random((B, 27)) * 3).astype(np.float32)
+    feat[:, 25:] = rng.random((B, 2)).astype(np.float32)
+    target = (rng.random(B) * 3).astype(np.float32)
+    params = random_params(6, 0.3)
+    mlp = L.MLP()
+    mlp.set_params(params)
+    g, loss = mlp.gradients(dev(T, feat), dev(T, target))
+    lo, go = OM.loss_and_grad(params.astype(np.float64), feat, target)
+    gk = g.cpu().numpy().astype(np.float64)
+    assert float(loss) == pytest.approx(lo, rel=2e-3)
+    assert np.linalg.norm(gk - go) / np.linalg.norm(go) < 2e-3
+    # every parameter block, normwise
+    o = 0
+    for name, shape in OM.SIZES:
+        k = int(np.prod(shape))
+        a, b = gk[o:o + k], go[o:o + k]
+        assert np.linalg.norm(a - b) <= 5e-3 * np.linalg.norm(b) + 1e-7, name
+        o += k
+
+
+def test_training_reduces_loss_and_checkpoint_roundtrip(T):
+    aidw, L = mods()
+    sets = [W.make(1 << 15, 6000, 15, 300 + i, "mixture", 8) for i in range(2)]
+    feat, target = L.training_pairs(sets)
+    mlp = L.MLP(seed=3)
+    losses = mlp.train(feat, target, epochs=6, batch=512, lr=3e-3, seed=3)
+    assert np.all(np.isfinite(losses)) and losses[-1] < 0.5 * losses[0]
+    # deterministic: the same seed and data give the same network
+    mlp2 = L.MLP(seed=3)
+    mlp2.train(feat, target, epochs=6, batch=512, lr=3e-3, seed=3)
+    assert np.array_equal(mlp.get_params(), mlp2.get_params())
+    with tempfile.TemporaryDirectory() as d:
+        path = os.path.join(d, "net.bin")
+        mlp.save(path)
+        back = L.MLP.load_file(path)
+        assert np.array_equal(back.get_params(), mlp.get_params())
+        assert T.equal(back.forward(feat[:1000]), mlp.forward(feat[:1000]))
+        # resuming keeps the optimiser state: one more epoch from either gives the same network
+        mlp.train(feat, target, epochs=1, batch=512, lr=3e-3, seed=9)
+        back.train(feat, target, epochs=1, batch=512, lr=3e-3, seed=9)
+        assert np.array_equal(back.get_params(), mlp.get_params())
+        with open(path, "r+b") as fh:
+            fh.write(b"XXXX")
+        with pytest.raises(aidw.AidwError):
+            L.MLP.load_file(path)
+
+
+# ------------------------------------------------------------------ learned run
+
+def _plain_and_learned(T, ds, mlp, rule, delta, k):
+    aidw, L = mods()
+    x, y, z, qx, qy = (dev(T, getattr(ds, a)) for a in ("x", "y", "z", "qx", "qy"))
+    p = aidw.Params(k=k)
+    qz_p, al_p, ro_p = aidw.run(x, y, z, qx, qy, p, want_alpha=True, want_robs=True)
+    qz_l, al_l, rh, nfb = L.run_learned(x, y, z, qx, qy, p, mlp, rule, delta, want_alpha=True, want_rhat=True)
+    T.cuda.synchronize()
+    return (qz_p.cpu().numpy(), al_p.cpu().numpy(), ro_p.cpu().numpy(), qz_l.cpu().numpy(), al_l.cpu().numpy(),
+            rh.cpu().numpy(), nfb)
+
+
+def test_all_fallback_equals_plain_path(T):
+    aidw, L = mods()
+    ds = W.make(6000, 3000, 15, 231, "mixture", 8)
+    mlp = L.MLP(seed=4)
+    qz_p, al_p, _, qz_l, al_l, _, nfb = _plain_and_learned(T, ds, mlp, L.ALPHA_EXACT, 1e9, 15)
+    assert nfb == ds.m
+    assert np.array_equal(al_l, al_p) and np.array_equal(qz_l, qz_p)
+
+
+@pytest.mark.parametrize("rule", ["alpha_exact", "literal"])
+def test_learned_rules(T, rule):
+    aidw, L = mods()
+    ds = W.make(8000, 4000, 15, 232, "mixture", 8)
+    ds.qx[7], ds.qy[7] = ds.x[3], ds.y[3]  # a coincident query always falls back
+    mlp = L.MLP(seed=5)
+    mlp.set_params(random_params(9, 0.2))
+    r = L.ALPHA_EXACT if rule == "alpha_exact" else L.LITERAL
+    qz_p, al_p, ro_p, qz_l, al_l, rh, nfb = _plain_and_learned(T, ds, mlp, r, 0.1, 15)
+    # the decision each query took, recomputed from the predictions
+    lo, hi = 2 / np.pi * np.arccos(0.8), 2 / np.pi * np.arccos(-0.8)
+    rh64 = rh.astype(np.float64)
+    if r == L.ALPHA_EXACT:
+        skip = (rh64 >= hi + 0.1) | (rh64 <= lo - 0.1)
+        expect_alpha = np.where(rh64 >= hi + 0.1, 5.0, 1.0)
+    else:
+        skip = ~((np.abs(rh64 - 0.0) < 0.1) | (np.abs(rh64 - 2.0) < 0.1))
+        _, _, expect_alpha = O.alpha(rh64, 1.0, 0.0, 2.0, W.LEVELS)  # r_exp = 1: R = r_hat
+    skip[7] = False
+    assert nfb == int((~skip).sum())
+    assert np.allclose(al_l[skip], expect_alpha[skip], atol=2e-6)
+    # fallback queries take the exact path: same alpha, and the same z as the plain run
+    fb = ~skip
+    assert np.array_equal(al_l[fb], al_p[fb])
+    assert np.allclose(qz_l[fb], qz_p[fb], rtol=2e-6, atol=1e-7)
+    assert qz_l[7] == ds.z[3]
+    # skipped queries whose alpha happens to equal the exact one agree with the plain run
+    same = skip & (al_l == al_p)
+    assert np.allclose(qz_l[same], qz_p[same], rtol=2e-6, atol=1e-7)
+    assert np.all(np.isfinite(qz_l))
+
+
+def test_trained_network_gain(T):
+    """A network trained on held-out mixture datasets lets most queries skip the kNN search
+    while the interpolated values stay within the error bar for nearly all of them."""
+    aidw, L = mods()
+    n, mq = 1 << 18, 50000
+    train = [W.make(n, mq, 15, 400 + i, "mixture", 16) for i in range(4)]
+    mlp, losses = L.train_default(train, seed=11, epochs=10, batch=1024, lr=2e-3)
+    assert losses[-1] < losses[0]
+    ds = W.make(n, 16000, 15, 499, "mixture", 16)
+    qz_p, al_p, _, qz_l, al_l, rh, nfb = _plain_and_learned(T, ds, mlp, L.ALPHA_EXACT, 0.3, 15)
+    skipped = 1.0 - nfb / ds.m
+    wrong_alpha = float(np.mean(al_l != al_p))
+    sel = np.arange(0, ds.m, 16)
+    ref = O.aidw(ds.x, ds.y, ds.z, ds.qx, ds.qy, k=15, qsel=sel)
+    e = np.abs(qz_l[sel].astype(np.float64) - ref["z"]) / np.maximum(np.abs(ref["z"]), ref["s"])
+    print("skipped %.3f wrong-alpha %.4f within-1e-5 %.4f" % (skipped, wrong_alpha, float(np.mean(e <= 1e-5))))
+    assert skipped > 0.85
+    assert wrong_alpha < 0.005
+    assert np.mean(e <= 1e-5) > 0.995
