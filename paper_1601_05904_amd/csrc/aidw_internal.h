@@ -50,6 +50,11 @@ size_t radix_hist_words(int n);
 size_t radix_scan_tmp_words(int n);
 hipError_t radix_sort_pairs(uint32_t* keys, uint32_t* vals, uint32_t* tmp_keys, uint32_t* tmp_vals, int n, int bits,
                             uint32_t* hist, uint32_t* scan_tmp, hipStream_t s);
+// out[i] = in[0] + ... + in[i-1] (in and out may alias); *total (device, may be null) = the sum.
+// tmp needs scan_tmp_words(len) words.
+size_t scan_tmp_words(size_t len);
+hipError_t exclusive_scan_u32(const uint32_t* in, uint32_t* out, size_t len, uint32_t* tmp, uint32_t* total,
+                              hipStream_t s);
 hipError_t launch_cell_start_gather(const uint32_t* keys, const uint32_t* vals, int n, int64_t ncells, const float* x,
                                     const float* y, int32_t* cell_start, float* sx, float* sy, int32_t* sidx,
                                     hipStream_t s);
@@ -103,9 +108,10 @@ struct MlpDevice {
   float* w3r;      // [64]
 };
 
+// perm (may be null): lane t handles query perm[t] and writes its outputs at position t.
 hipError_t launch_features(const GridScalars* gs, const int32_t* cell_start, const float* sx, const float* sy,
-                           const float* qx, const float* qy, int m, double inv_occ, double slack_cells, float* feat,
-                           float* d1sq, hipStream_t s);
+                           const float* qx, const float* qy, const uint32_t* perm, int m, double inv_occ,
+                           double slack_cells, float* feat, float* d1sq, hipStream_t s);
 hipError_t launch_mlp_repack(const MlpDevice& d, hipStream_t s);
 hipError_t launch_mlp_forward(const MlpDevice& d, const float* feat, int m, float* out, hipStream_t s);
 size_t mlp_batch_scratch_floats(int B);
@@ -115,10 +121,14 @@ hipError_t launch_mlp_gradients(const MlpDevice& d, const float* feat, const flo
 hipError_t launch_adam(const MlpDevice& d, const float* grad, float lr, float b1, float b2, float eps, float bc1,
                        float bc2, hipStream_t s);
 hipError_t launch_accumulate_loss(const float* grad, float* epoch_loss, int epoch, float scale, hipStream_t s);
-hipError_t launch_fallback(const float* r_hat, const float* d1sq, const float* qx, const float* qy, int m,
-                           const GridScalars* gs, const AlphaParams& ap, int rule, double delta, double r_sat_lo,
-                           double r_sat_hi, float* alpha_f, uint32_t* keys, uint32_t* vals, uint32_t* count,
-                           hipStream_t s);
+// Per position t of the binned order (query perm[t]): flag[t] = 1 for exact-kNN fallback; skipped
+// queries get alpha_f[q] from the rule and d1sq[q] = d1pos[t]; r_hat_out[q] = r_hat[t] (if non-null).
+hipError_t launch_decide(const float* r_hat, const float* d1pos, const uint32_t* perm, int m, const AlphaParams& ap,
+                         int rule, double delta, double r_sat_lo, double r_sat_hi, uint32_t* flag, float* alpha_f,
+                         float* d1sq, float* r_hat_out, hipStream_t s);
+// list[idx[t]] = perm[t] for flagged positions (idx = exclusive scan of flag).
+hipError_t launch_compact(const uint32_t* flag, const uint32_t* idx, const uint32_t* perm, int m, uint32_t* list,
+                          hipStream_t s);
 hipError_t launch_alpha_fallback(const uint32_t* perm, const uint32_t* count, int m, const float* r_obs,
                                  const AlphaParams& ap, float* alpha_f, hipStream_t s);
 // Pair-kernel class keys from a given alpha (alpha == p in 1..8 -> p, else 0) and the identity permutation.

@@ -634,8 +634,8 @@ aidw_status aidw_features(const aidw_grid* g, const float* qx, const float* qy, 
   if (m == 0) return AIDW_OK;
   if (!qx || !qy || !feat) return fail(AIDW_EINVAL, "qx / qy / feat is NULL");
   const double inv_occ = (double)g->host.ncells / (double)g->n;
-  HIP_TRY(launch_features(g->dev, g->cell_start, g->sx, g->sy, qx, qy, (int)m, inv_occ, slack_cells(g->host), feat,
-                          d1sq, stream),
+  HIP_TRY(launch_features(g->dev, g->cell_start, g->sx, g->sy, qx, qy, nullptr, (int)m, inv_occ,
+                          slack_cells(g->host), feat, d1sq, stream),
           "feature kernel");
   return AIDW_OK;
 }
@@ -739,21 +739,29 @@ aidw_status aidw_run_learned(const float* x, const float* y, const float* z, int
     Temps t(stream);
     hipError_t e = hipSuccess;
     if (ev) e = hipEventRecord(ev[1], stream);
-    float *feat = nullptr, *d1sq = nullptr, *r_hat = nullptr, *alpha_f = nullptr, *r_obs = nullptr;
-    uint32_t *keys = nullptr, *vals = nullptr, *tk = nullptr, *tv = nullptr, *hist = nullptr, *scan = nullptr,
-             *count = nullptr;
+    // Queries are processed in cell order (as the kNN kernel takes them): features, network and
+    // the decision per position of that order; the fallback list is the flagged positions,
+    // compacted in order by a prefix sum, so the kNN kernel sees them binned as well.
+    float *feat = nullptr, *d1pos = nullptr, *d1sq = nullptr, *r_hat = nullptr, *alpha_f = nullptr, *r_obs = nullptr;
+    uint32_t *keys = nullptr, *perm = nullptr, *tk = nullptr, *tv = nullptr, *hist = nullptr, *scan = nullptr,
+             *flag = nullptr, *idx = nullptr, *list = nullptr, *stmp = nullptr, *count = nullptr;
     const int mm = (int)m;
     if (e == hipSuccess) e = t.get(&feat, (size_t)mm * AIDW_MLP_INPUTS);
+    if (e == hipSuccess) e = t.get(&d1pos, mm);
     if (e == hipSuccess) e = t.get(&d1sq, mm);
     if (e == hipSuccess) e = t.get(&r_hat, mm);
     if (e == hipSuccess) e = t.get(&alpha_f, mm);
     if (e == hipSuccess) e = t.get(&r_obs, mm);
     if (e == hipSuccess) e = t.get(&keys, mm);
-    if (e == hipSuccess) e = t.get(&vals, mm);
+    if (e == hipSuccess) e = t.get(&perm, mm);
     if (e == hipSuccess) e = t.get(&tk, mm);
     if (e == hipSuccess) e = t.get(&tv, mm);
     if (e == hipSuccess) e = t.get(&hist, radix_hist_words(mm));
     if (e == hipSuccess) e = t.get(&scan, radix_scan_tmp_words(mm));
+    if (e == hipSuccess) e = t.get(&flag, mm);
+    if (e == hipSuccess) e = t.get(&idx, mm);
+    if (e == hipSuccess) e = t.get(&list, mm);
+    if (e == hipSuccess) e = t.get(&stmp, scan_tmp_words(mm));
     if (e == hipSuccess) e = t.get(&count, 1);
     if (e != hipSuccess) st = hip_fail(e, "allocating learned-R buffers");
     AlphaParams ap;
@@ -767,28 +775,26 @@ aidw_status aidw_run_learned(const float* x, const float* y, const float* z, int
     const double inv_occ = (double)g->host.ncells / (double)n;
 #define STEP(expr, what) \
   if (st == AIDW_OK && (e = (expr)) != hipSuccess) st = hip_fail(e, what)
-    STEP(hipMemsetAsync(count, 0, sizeof(uint32_t), stream), "clearing the fallback count");
-    STEP(launch_features(g->dev, g->cell_start, g->sx, g->sy, qx, qy, mm, inv_occ, slack_cells(g->host), feat, d1sq,
-                         stream),
+    STEP(launch_cell_keys(qx, qy, mm, g->dev, keys, perm, stream), "query key kernel");
+    STEP(radix_sort_pairs(keys, perm, tk, tv, mm, bits_for(g->host.ncells), hist, scan, stream), "query sort");
+    STEP(launch_features(g->dev, g->cell_start, g->sx, g->sy, qx, qy, perm, mm, inv_occ, slack_cells(g->host), feat,
+                         d1pos, stream),
          "feature kernel");
     STEP(launch_mlp_forward(mlp->d, feat, mm, r_hat, stream), "network forward kernel");
-    STEP(launch_fallback(r_hat, d1sq, qx, qy, mm, g->dev, ap, rule, delta, r_sat_lo, r_sat_hi, alpha_f, keys, vals,
-                         count, stream),
-         "fallback kernel");
-    // fallback queries first, in cell order (the sentinel key nCells sorts the others last)
-    STEP(radix_sort_pairs(keys, vals, tk, tv, mm, bits_for(g->host.ncells + 1), hist, scan, stream), "fallback sort");
-    STEP(launch_knn(g->dev, g->cell_start, g->sx, g->sy, g->sidx, qx, qy, vals, count, mm, p->k, slack_cells(g->host),
+    STEP(launch_decide(r_hat, d1pos, perm, mm, ap, rule, delta, r_sat_lo, r_sat_hi, flag, alpha_f, d1sq, r_hat_out,
+                       stream),
+         "decision kernel");
+    STEP(exclusive_scan_u32(flag, idx, mm, stmp, count, stream), "fallback scan");
+    STEP(launch_compact(flag, idx, perm, mm, list, stream), "fallback compaction");
+    STEP(launch_knn(g->dev, g->cell_start, g->sx, g->sy, g->sidx, qx, qy, list, count, mm, p->k, slack_cells(g->host),
                     r_obs, d1sq, nullptr, stream),
          "kNN kernel");
-    STEP(launch_alpha_fallback(vals, count, mm, r_obs, ap, alpha_f, stream), "alpha kernel");
+    STEP(launch_alpha_fallback(list, count, mm, r_obs, ap, alpha_f, stream), "alpha kernel");
 #undef STEP
     int q = 0, split = 0;
     if (st == AIDW_OK)
       st = interp_impl(x, y, z, n, qx, qy, m, nullptr, d1sq, p, g, qz, alpha_out, stream, ev ? ev[2] : nullptr,
                        ev ? ev[3] : nullptr, &q, &split, alpha_f);
-    if (st == AIDW_OK && r_hat_out)
-      if ((e = hipMemcpyAsync(r_hat_out, r_hat, sizeof(float) * m, hipMemcpyDeviceToDevice, stream)) != hipSuccess)
-        st = hip_fail(e, "copying predictions");
     if (st == AIDW_OK && fallback_count)
       if ((e = hipMemcpyAsync(&host_count, count, sizeof(uint32_t), hipMemcpyDeviceToHost, stream)) != hipSuccess)
         st = hip_fail(e, "reading the fallback count");

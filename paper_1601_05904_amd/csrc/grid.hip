@@ -410,6 +410,26 @@ hipError_t radix_sort_pairs(uint32_t* keys, uint32_t* vals, uint32_t* tmp_keys, 
   return hipSuccess;
 }
 
+namespace {
+__global__ void k_scan_total(const uint32_t* __restrict__ in, const uint32_t* __restrict__ ex, size_t len,
+                             uint32_t* __restrict__ total) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *total = len ? ex[len - 1] + in[len - 1] : 0u;
+}
+}  // namespace
+
+size_t scan_tmp_words(size_t len) { return (len + kScanChunk - 1) / kScanChunk + 1; }
+
+hipError_t exclusive_scan_u32(const uint32_t* in, uint32_t* out, size_t len, uint32_t* tmp, uint32_t* total,
+                              hipStream_t s) {
+  if (len == 0) return hipSuccess;
+  const int nsb = (int)((len + kScanChunk - 1) / kScanChunk);
+  hipLaunchKernelGGL(k_scan_reduce, dim3(nsb), dim3(kScanThreads), 0, s, in, len, tmp);
+  hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kScanThreads), 0, s, tmp, nsb);
+  hipLaunchKernelGGL(k_scan_down, dim3(nsb), dim3(kScanThreads), 0, s, in, len, tmp, out);
+  if (total) hipLaunchKernelGGL(k_scan_total, dim3(1), dim3(64), 0, s, in, out, len, total);
+  return hipGetLastError();
+}
+
 hipError_t launch_cell_start_gather(const uint32_t* keys, const uint32_t* vals, int n, int64_t ncells, const float* x,
                                     const float* y, int32_t* cell_start, float* sx, float* sy, int32_t* sidx,
                                     hipStream_t s) {

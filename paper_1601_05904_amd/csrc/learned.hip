@@ -74,29 +74,35 @@ __device__ inline int clamp_cell(float t, int nc) {
 __global__ __launch_bounds__(256) void k_features(const GridScalars* __restrict__ gs,
                                                   const int32_t* __restrict__ cell_start,
                                                   const float* __restrict__ sx, const float* __restrict__ sy,
-                                                  const float* __restrict__ qx, const float* __restrict__ qy, int m,
-                                                  double inv_occ, double slack_cells, float* __restrict__ feat,
+                                                  const float* __restrict__ qx, const float* __restrict__ qy,
+                                                  const uint32_t* __restrict__ perm, int m, double inv_occ,
+                                                  double slack_cells, float* __restrict__ feat,
                                                   float* __restrict__ d1sq) {
-  const int q = blockIdx.x * blockDim.x + threadIdx.x;
-  if (q >= m) return;
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= m) return;
+  const int q = perm ? (int)perm[t] : t;
   const float minx = gs->minx, miny = gs->miny, inv = gs->inv_cw;
   const int ncol = gs->ncol, nrow = gs->nrow;
   const float fx = qx[q], fy = qy[q];
   const float tx = (fx - minx) * inv;
   const float ty = (fy - miny) * inv;
   const int c0 = clamp_cell(tx, ncol), r0 = clamp_cell(ty, nrow);
-  float* f = feat + (size_t)q * kIn;
+  float* f = feat + (size_t)t * kIn;
 #pragma unroll
   for (int dr = -2; dr <= 2; ++dr) {
     const int r = r0 + dr;
+    // the six offsets bounding the row's five cells (clipped to the row)
+    int off[6];
+#pragma unroll
+    for (int e = 0; e < 6; ++e) {
+      int c = c0 - 2 + e;
+      c = c < 0 ? 0 : (c > ncol ? ncol : c);
+      off[e] = (r >= 0 && r < nrow) ? cell_start[r * ncol + c] : 0;
+    }
 #pragma unroll
     for (int dc = -2; dc <= 2; ++dc) {
       const int c = c0 + dc;
-      int cnt = 0;
-      if (r >= 0 && r < nrow && c >= 0 && c < ncol) {
-        const int cell = r * ncol + c;
-        cnt = cell_start[cell + 1] - cell_start[cell];
-      }
+      const int cnt = (c >= 0 && c < ncol) ? off[dc + 3] - off[dc + 2] : 0;
       f[(dr + 2) * 5 + (dc + 2)] = (float)((double)cnt * inv_occ);
     }
   }
@@ -129,7 +135,7 @@ __global__ __launch_bounds__(256) void k_features(const GridScalars* __restrict_
     v = best;                       // exact nearest distance
   else
     v = dout > 0 ? dout * dout : 0; // lower bound
-  d1sq[q] = v == 0.0 ? (best == 0.0 ? 0.0f : FLT_MIN) : fmaxf((float)v, FLT_MIN);
+  d1sq[t] = v == 0.0 ? (best == 0.0 ? 0.0f : FLT_MIN) : fmaxf((float)v, FLT_MIN);
 }
 
 // ---- network ------------------------------------------------------------------------
@@ -257,38 +263,52 @@ __global__ __launch_bounds__(64) void k_mlp_train_sample(MlpWeights w, const flo
   }
 }
 
-// grad[p] = sum over the batch (in sample order) of the parameter's two operands;
-// grad[kParams] = mean squared error of the batch.
+// Weight gradients: grad[p] = sum over the batch of the parameter's two operands;
+// grad[kParams] = mean squared error of the batch.  The batch is cut into
+// kGradChunks contiguous chunks (blockIdx.y); each chunk's sum runs in sample
+// order, then k_mlp_wgrad_sum adds the chunks in chunk order.
+constexpr int kGradChunks = 16;
+
 __global__ __launch_bounds__(256) void k_mlp_wgrad(int B, const float* __restrict__ s_x,
                                                    const float* __restrict__ s_h1, const float* __restrict__ s_h2,
                                                    const float* __restrict__ s_da1, const float* __restrict__ s_da2,
                                                    const float* __restrict__ s_dy, const float* __restrict__ s_err2,
-                                                   float* __restrict__ grad) {
+                                                   float* __restrict__ part) {
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p > kParams) return;
+  const int per = (B + kGradChunks - 1) / kGradChunks;
+  const int b0 = blockIdx.y * per, b1 = min(B, b0 + per);
   float acc = 0.0f;
   if (p < kOffB1) {
     const int o = p / kIn, i = p % kIn;
-    for (int b = 0; b < B; ++b) acc = __builtin_fmaf(s_da1[(size_t)b * kH + o], s_x[(size_t)b * 28 + i], acc);
+    for (int b = b0; b < b1; ++b) acc = __builtin_fmaf(s_da1[(size_t)b * kH + o], s_x[(size_t)b * 28 + i], acc);
   } else if (p < kOffW2) {
     const int o = p - kOffB1;
-    for (int b = 0; b < B; ++b) acc += s_da1[(size_t)b * kH + o];
+    for (int b = b0; b < b1; ++b) acc += s_da1[(size_t)b * kH + o];
   } else if (p < kOffB2) {
     const int o = (p - kOffW2) / kH, i = (p - kOffW2) % kH;
-    for (int b = 0; b < B; ++b) acc = __builtin_fmaf(s_da2[(size_t)b * kH + o], s_h1[(size_t)b * kH + i], acc);
+    for (int b = b0; b < b1; ++b) acc = __builtin_fmaf(s_da2[(size_t)b * kH + o], s_h1[(size_t)b * kH + i], acc);
   } else if (p < kOffW3) {
     const int o = p - kOffB2;
-    for (int b = 0; b < B; ++b) acc += s_da2[(size_t)b * kH + o];
+    for (int b = b0; b < b1; ++b) acc += s_da2[(size_t)b * kH + o];
   } else if (p < kOffB3) {
     const int i = p - kOffW3;
-    for (int b = 0; b < B; ++b) acc = __builtin_fmaf(s_dy[b], s_h2[(size_t)b * kH + i], acc);
+    for (int b = b0; b < b1; ++b) acc = __builtin_fmaf(s_dy[b], s_h2[(size_t)b * kH + i], acc);
   } else if (p == kOffB3) {
-    for (int b = 0; b < B; ++b) acc += s_dy[b];
+    for (int b = b0; b < b1; ++b) acc += s_dy[b];
   } else {
-    for (int b = 0; b < B; ++b) acc += s_err2[b];
-    acc /= (float)B;
+    for (int b = b0; b < b1; ++b) acc += s_err2[b];
   }
-  grad[p] = acc;
+  part[(size_t)blockIdx.y * (kParams + 1) + p] = acc;
+}
+
+__global__ __launch_bounds__(256) void k_mlp_wgrad_sum(int B, const float* __restrict__ part,
+                                                       float* __restrict__ grad) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p > kParams) return;
+  float acc = 0.0f;
+  for (int c = 0; c < kGradChunks; ++c) acc += part[(size_t)c * (kParams + 1) + p];
+  grad[p] = p == kParams ? acc / (float)B : acc;
 }
 
 // Adam on the float32 masters.
@@ -333,15 +353,14 @@ __global__ void k_accumulate_loss(const float* __restrict__ grad, float* __restr
 
 // ---- learned run: fallback decision -----------------------------------------------------
 
-// Per query, from the prediction r_hat of R: fall back to exact kNN when the
-// prediction could change alpha, else take alpha from the rule.  Fallback queries
-// get key = their cell (to be binned for the kNN kernel), the others the sentinel
-// nCells so that they sort last.  count receives the number of fallback queries.
+// Per position t of the binned query order (query q = perm[t]), from the prediction
+// r_hat[t] of R: fall back to exact kNN when the prediction could change alpha, else
+// take alpha from the rule.
 //   rule 0 (literal): fall back when |r_hat - R_min| < delta or |r_hat - R_max| < delta;
 //                     other queries use alpha(mu(r_hat)) by Eq. 5, 6.
 //   rule 1 (alpha-exact): skip only when r_hat >= r_sat_hi + delta (alpha = alpha_5) or
 //                     r_hat <= r_sat_lo - delta (alpha = alpha_1), where mu = 0.9 / 0.1.
-// Coincident queries (d1sq == 0) always fall back.
+// Coincident queries (d1 == 0) always fall back.
 __device__ inline double fuzzy_mu_l(double R, double rmin, double rmax) {
   if (R <= rmin) return 0.0;
   if (R >= rmax) return 1.0;
@@ -356,16 +375,17 @@ __device__ inline double level_alpha_l(double mu, const double* a) {
   return a[4];
 }
 
-__global__ __launch_bounds__(256) void k_fallback(const float* __restrict__ r_hat, const float* __restrict__ d1sq,
-                                                  const float* __restrict__ qx, const float* __restrict__ qy, int m,
-                                                  const GridScalars* __restrict__ gs, AlphaParams ap, int rule,
-                                                  double delta, double r_sat_lo, double r_sat_hi,
-                                                  float* __restrict__ alpha_f, uint32_t* __restrict__ keys,
-                                                  uint32_t* __restrict__ vals, uint32_t* __restrict__ count) {
-  const int q = blockIdx.x * blockDim.x + threadIdx.x;
-  if (q >= m) return;
-  const double R = r_hat[q];
-  bool fall = d1sq[q] == 0.0f || !isfinite(R);
+__global__ __launch_bounds__(256) void k_decide(const float* __restrict__ r_hat, const float* __restrict__ d1pos,
+                                                const uint32_t* __restrict__ perm, int m, AlphaParams ap, int rule,
+                                                double delta, double r_sat_lo, double r_sat_hi,
+                                                uint32_t* __restrict__ flag, float* __restrict__ alpha_f,
+                                                float* __restrict__ d1sq, float* __restrict__ r_hat_out) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= m) return;
+  const uint32_t q = perm[t];
+  const double R = r_hat[t];
+  const float d1 = d1pos[t];
+  bool fall = d1 == 0.0f || !isfinite(R);
   double alpha = 0.0;
   if (!fall) {
     if (rule == 0) {
@@ -379,17 +399,20 @@ __global__ __launch_bounds__(256) void k_fallback(const float* __restrict__ r_ha
       fall = true;
     }
   }
-  vals[q] = (uint32_t)q;
-  if (fall) {
-    const int ncol = gs->ncol, nrow = gs->nrow;
-    const int c = clamp_cell((qx[q] - gs->minx) * gs->inv_cw, ncol);
-    const int r = clamp_cell((qy[q] - gs->miny) * gs->inv_cw, nrow);
-    keys[q] = (uint32_t)(r * ncol + c);
-    atomicAdd(count, 1u);
-  } else {
-    keys[q] = (uint32_t)gs->ncells;
+  flag[t] = fall ? 1u : 0u;
+  if (!fall) {
     alpha_f[q] = (float)alpha;
+    d1sq[q] = d1;
   }
+  if (r_hat_out) r_hat_out[q] = (float)R;
+}
+
+__global__ __launch_bounds__(256) void k_compact(const uint32_t* __restrict__ flag, const uint32_t* __restrict__ idx,
+                                                 const uint32_t* __restrict__ perm, int m,
+                                                 uint32_t* __restrict__ list) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= m) return;
+  if (flag[t]) list[idx[t]] = perm[t];
 }
 
 // Eq. 4-6 for the fallback queries (the first *count entries of perm) from their exact r_obs.
@@ -407,11 +430,11 @@ __global__ __launch_bounds__(256) void k_alpha_fallback(const uint32_t* __restri
 }  // namespace
 
 hipError_t launch_features(const GridScalars* gs, const int32_t* cell_start, const float* sx, const float* sy,
-                           const float* qx, const float* qy, int m, double inv_occ, double slack_cells, float* feat,
-                           float* d1sq, hipStream_t s) {
+                           const float* qx, const float* qy, const uint32_t* perm, int m, double inv_occ,
+                           double slack_cells, float* feat, float* d1sq, hipStream_t s) {
   if (m <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_features, dim3((m + 255) / 256), dim3(256), 0, s, gs, cell_start, sx, sy, qx, qy, m, inv_occ,
-                     slack_cells, feat, d1sq);
+  hipLaunchKernelGGL(k_features, dim3((m + 255) / 256), dim3(256), 0, s, gs, cell_start, sx, sy, qx, qy, perm, m,
+                     inv_occ, slack_cells, feat, d1sq);
   return hipGetLastError();
 }
 
@@ -431,7 +454,7 @@ hipError_t launch_mlp_forward(const MlpDevice& d, const float* feat, int m, floa
   return hipGetLastError();
 }
 
-size_t mlp_batch_scratch_floats(int B) { return (size_t)B * (28 + 4 * kH + 2); }
+size_t mlp_batch_scratch_floats(int B) { return (size_t)B * (28 + 4 * kH + 2) + (size_t)kGradChunks * (kParams + 1); }
 
 hipError_t launch_mlp_gradients(const MlpDevice& d, const float* feat, const float* target, const uint32_t* sel, int B,
                                 float* scratch, float* grad, hipStream_t s) {
@@ -442,10 +465,12 @@ hipError_t launch_mlp_gradients(const MlpDevice& d, const float* feat, const flo
   float* s_da2 = s_da1 + (size_t)B * kH;
   float* s_dy = s_da2 + (size_t)B * kH;
   float* s_err2 = s_dy + B;
+  float* part = s_err2 + B;
   hipLaunchKernelGGL(k_mlp_train_sample, dim3((B + 63) / 64), dim3(64), 0, s, weights(d), feat, target, sel, B,
                      2.0f / (float)B, s_x, s_h1, s_h2, s_da1, s_da2, s_dy, s_err2);
-  hipLaunchKernelGGL(k_mlp_wgrad, dim3((kParams + 1 + 255) / 256), dim3(256), 0, s, B, s_x, s_h1, s_h2, s_da1, s_da2,
-                     s_dy, s_err2, grad);
+  hipLaunchKernelGGL(k_mlp_wgrad, dim3((kParams + 1 + 255) / 256, kGradChunks), dim3(256), 0, s, B, s_x, s_h1, s_h2,
+                     s_da1, s_da2, s_dy, s_err2, part);
+  hipLaunchKernelGGL(k_mlp_wgrad_sum, dim3((kParams + 1 + 255) / 256), dim3(256), 0, s, B, part, grad);
   return hipGetLastError();
 }
 
@@ -461,13 +486,19 @@ hipError_t launch_accumulate_loss(const float* grad, float* epoch_loss, int epoc
   return hipGetLastError();
 }
 
-hipError_t launch_fallback(const float* r_hat, const float* d1sq, const float* qx, const float* qy, int m,
-                           const GridScalars* gs, const AlphaParams& ap, int rule, double delta, double r_sat_lo,
-                           double r_sat_hi, float* alpha_f, uint32_t* keys, uint32_t* vals, uint32_t* count,
-                           hipStream_t s) {
+hipError_t launch_decide(const float* r_hat, const float* d1pos, const uint32_t* perm, int m, const AlphaParams& ap,
+                         int rule, double delta, double r_sat_lo, double r_sat_hi, uint32_t* flag, float* alpha_f,
+                         float* d1sq, float* r_hat_out, hipStream_t s) {
   if (m <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_fallback, dim3((m + 255) / 256), dim3(256), 0, s, r_hat, d1sq, qx, qy, m, gs, ap, rule, delta,
-                     r_sat_lo, r_sat_hi, alpha_f, keys, vals, count);
+  hipLaunchKernelGGL(k_decide, dim3((m + 255) / 256), dim3(256), 0, s, r_hat, d1pos, perm, m, ap, rule, delta,
+                     r_sat_lo, r_sat_hi, flag, alpha_f, d1sq, r_hat_out);
+  return hipGetLastError();
+}
+
+hipError_t launch_compact(const uint32_t* flag, const uint32_t* idx, const uint32_t* perm, int m, uint32_t* list,
+                          hipStream_t s) {
+  if (m <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_compact, dim3((m + 255) / 256), dim3(256), 0, s, flag, idx, perm, m, list);
   return hipGetLastError();
 }
 
