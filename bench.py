@@ -91,6 +91,10 @@ def parse():
     ap.add_argument("--learned-workload", default="learned_1m")
     ap.add_argument("--learned-steps", type=int, default=5)
     ap.add_argument("--delta", type=float, default=0.3, help="fallback margin of the alpha-exact rule")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched-jobs measurement")
+    ap.add_argument("--batch-steps", type=int, default=10)
+    ap.add_argument("--batch-loop", action="store_true",
+                    help="also time the same jobs as one aidw_run per job (context for the batched form)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MB",
                     help="only run a plain device copy of MB megabytes (reference for HBM traffic counters)")
     return ap.parse_args()
@@ -185,6 +189,89 @@ def learned_comparison(args, with_oracle):
     return out
 
 
+def batch_measurement(args, with_oracle):
+    """The 256-job workload (n log-uniform in [1024, 65536], m = n, k from {8, 10, 15}, half uniform, half
+    8-cluster mixtures) as one plan in the autotuned launch shape, replayed as a HIP graph: aggregate
+    points/s over all jobs, the persistent pair kernel against its roofline, and sampled z errors."""
+    import torch
+
+    import paper_1601_05904_amd as aidw
+    import paper_1601_05904_amd.batch as B
+    from paper_1601_05904_amd import workloads as W
+
+    dss = W.batch_jobs()
+    dev = torch.device("cuda", 0)
+    jobs = [B.Job(*(torch.from_numpy(getattr(ds, k)).to(dev) for k in ("x", "y", "z", "qx", "qy")),
+                  params=aidw.Params(k=ds.k, levels=ds.levels, r_min=ds.r_min, r_max=ds.r_max,
+                                     occupancy=ds.occupancy)) for ds in dss]
+    torch.cuda.synchronize()
+    tt0 = time.perf_counter()
+    config = B.autotune(jobs)
+    tune_s = time.perf_counter() - tt0
+    config.use_graph = 1
+    plan = B.Plan(jobs, config, want_alpha=True)
+    info = plan.describe()
+    side = torch.cuda.Stream()
+    for _ in range(2):
+        plan.run(side)
+    side.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.batch_steps):
+        plan.run(side)
+    side.synchronize()
+    t1 = time.perf_counter()
+    assert plan.status(side) == [0] * len(dss)
+    ms = (t1 - t0) * 1e3 / args.batch_steps
+    # stage times from timed (direct) runs of the same plan
+    plan.set_timing(True)
+    stages = []
+    for _ in range(3):
+        plan.run(side)
+        stages.append(plan.last_timing())
+    plan.set_timing(False)
+    st = {k: float(np.mean([s_[k] for s_ in stages])) for k in stages[0]}
+    # roofline of the persistent pair kernel: every query's class weighted by its job's n
+    inv, pairs = 0.0, 0.0
+    for ds, a in zip(dss, plan.alpha):
+        al = a.cpu().numpy().astype(np.float64)
+        pk = np.full(al.shape, PEAK_GENERAL)
+        for p_ in sorted(set(int(v) for v in ds.levels if float(v).is_integer() and 1 <= v <= 8)):
+            pk[al == p_] = pair_peak(6 + CHAIN_MULS[p_], 1)
+        inv += float(ds.n) * float(np.sum(1.0 / pk))
+        pairs += float(ds.n) * float(ds.m)
+    peak = pairs / inv
+    achieved = pairs / (st["interp_ms"] * 1e-3)
+    out = {"workload": "batch_256", "jobs": len(dss), "total_queries": info["total_queries"],
+           "total_data": info["total_data"], "total_pairs": pairs, "value": info["total_queries"] / (ms * 1e-3),
+           "unit": "points/s", "ms_per_step": ms, "steps": args.batch_steps, "graph": True,
+           "config": info["config"], "work_items": info["work_items"], "workers": info["workers"],
+           "autotune_s": tune_s, "stages_ms": st,
+           "roofline": {"bound": "alu", "kernel": "k_b_interp", "achieved": achieved / 1e9, "peak": peak / 1e9,
+                        "unit": "Gpair/s", "frac": achieved / peak, "units_per_launch": pairs}}
+    if args.batch_loop:
+        aidw.set_interp_config(0, 0, -1)
+        outs = []
+        torch.cuda.synchronize()
+        l0 = time.perf_counter()
+        for jb in jobs:
+            outs.append(aidw.run(jb.x, jb.y, jb.z, jb.qx, jb.qy, jb.params))
+        torch.cuda.synchronize()
+        out["per_job_loop_ms"] = (time.perf_counter() - l0) * 1e3
+    if with_oracle:
+        import oracle
+        worst, count = 0.0, 0
+        for j, ds in enumerate(dss):
+            sel = W.sample_queries(ds.m, 4, 9000 + j)
+            ref = oracle.aidw(ds.x, ds.y, ds.z, ds.qx, ds.qy, k=ds.k, levels=ds.levels, r_min=ds.r_min,
+                              r_max=ds.r_max, occupancy=ds.occupancy, qsel=sel)
+            zg = plan.qz[j].cpu().numpy()[sel].astype(np.float64)
+            e = np.abs(zg - ref["z"]) / np.maximum(np.abs(ref["z"]), ref["s"])
+            worst, count = max(worst, float(e.max())), count + len(sel)
+        out["z_error"] = {"max": worst, "sample": "%d queries (4 per job)" % count}
+    plan.close()
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -276,6 +363,8 @@ def main():
                           "sample": len(sel)}
     if not args.no_learned:
         out["learned_r"] = learned_comparison(args, with_oracle=not args.no_cpu_baseline)
+    if not args.no_batch:
+        out["batch"] = batch_measurement(args, with_oracle=not args.no_cpu_baseline)
     print(json.dumps(out))
 
 

@@ -300,6 +300,138 @@ aidw_status aidw_run_learned(const float* x, const float* y, const float* z, int
                              double delta, float* qz, float* alpha_out, float* r_hat_out, int64_t* fallback_count,
                              hipStream_t stream);
 
+/* ---------------------------------------------------------------------------
+ * Batched form.  Many independent interpolation problems ("jobs") of uneven
+ * size run as one pipeline on one stream: each stage of the method (bounds and
+ * grid scalars, counting sort, query binning, kNN with Eq. 3, Eq. 4-6) is one
+ * launch over all jobs, and the pair evaluation of Eq. 1 is ONE persistent
+ * launch whose workgroups take work items (job, block of queries, range of
+ * data points) from a list ordered by decreasing cost until it is exhausted.
+ * Every item writes its own float64 partial sums and a last pass adds a
+ * query's partials in a fixed order, so results are bitwise reproducible.
+ * Each job's outputs are those aidw_run gives for the job alone (bitwise when
+ * aidw_run uses the same pair-kernel shape: q, and split = the job's number of
+ * data ranges, see split_points).
+ *
+ * A plan fixes the jobs (pointers and sizes) and the launch shape once: it
+ * checks everything on the host, allocates one device workspace and uploads
+ * the job table.  Running a plan reads the current contents of the jobs'
+ * input arrays, queues the whole pipeline and returns: it allocates nothing
+ * and never waits for the device, so it can be captured in a HIP graph (the
+ * plan does this itself with use_graph) and replayed.  In the batched form a
+ * job's grid has a cell budget fixed by n (about 2 n / occupancy cells); when
+ * the bounds would need more cells the cell side is widened, which changes
+ * only the search cost, never a result.
+ * ------------------------------------------------------------------------- */
+
+/* One job.  Inputs as for aidw_run (device pointers, caller-owned, valid while
+ * the plan is in use); params.k <= min(n, AIDW_KMAX); cell_width > 0 is a
+ * lower bound here (see above).  qz [m] receives the interpolated values;
+ * alpha_out [m] and r_obs_out [m] may be NULL.  m = 0 is allowed. */
+typedef struct {
+  const float* x;
+  const float* y;
+  const float* z;
+  int64_t n;
+  const float* qx;
+  const float* qy;
+  int64_t m;
+  aidw_params params;
+  float* qz;
+  float* alpha_out;
+  float* r_obs_out;
+} aidw_job;
+
+/* Launch shape of a plan (what the autotuner searches over).
+ *   q               queries per lane in the pair kernel: 1 or 2.
+ *   split_points    data points per work item, rounded up to a multiple of 8;
+ *                   0 = a job's whole data set (one range per query block).
+ *   workers_per_cu  persistent pair-kernel workgroups per compute unit, 1..32.
+ *   integer_powers  1: a block of queries whose alpha is the same integer p in
+ *                   1..8 uses w = rsq(t)^p; 0: every query the general form.
+ *   use_graph       1: the first aidw_batch_run captures the pipeline into a
+ *                   HIP graph (it needs a created stream, not the null stream)
+ *                   and every run launches that graph. */
+typedef struct {
+  int32_t q;
+  int32_t split_points;
+  int32_t workers_per_cu;
+  int32_t integer_powers;
+  int32_t use_graph;
+} aidw_batch_config;
+
+/* Defaults: q = 1, split_points = 0, workers_per_cu = 8, integer_powers = 1, use_graph = 0. */
+void aidw_batch_config_default(aidw_batch_config* c);
+
+/* Opaque plan (library-owned). */
+typedef struct aidw_batch aidw_batch;
+
+/* Checks the jobs and the config on the host, allocates the device workspace
+ * and uploads the job table (synchronous).  cfg may be NULL (defaults).
+ * Errors: AIDW_EINVAL (njobs < 1, a job's pointers, sizes, k or params, the
+ * config), AIDW_ECAPACITY (totals beyond int32 indexing), AIDW_ENOMEM,
+ * AIDW_EDEVICE.  On success *out owns the workspace until aidw_batch_destroy. */
+aidw_status aidw_batch_create(const aidw_job* jobs, int32_t njobs, const aidw_batch_config* cfg, aidw_batch** out);
+
+/* Queues the pipeline for all jobs on `stream` (or launches its graph).
+ * Asynchronous; overlapping runs of one plan race on its workspace.  A job
+ * whose input is non-finite or spans no area gets NaN outputs and its status
+ * is reported by aidw_batch_job_status; the other jobs are unaffected.
+ * Errors: AIDW_EINVAL (NULL plan; graph mode on the null stream), AIDW_EDEVICE. */
+aidw_status aidw_batch_run(aidw_batch* b, hipStream_t stream);
+
+/* Waits for `stream` and reports each job's status of the last run into
+ * status [njobs] (host array, may be NULL): AIDW_OK, AIDW_ENONFINITE or
+ * AIDW_EDEGENERATE.  Returns AIDW_OK if every job succeeded, else the status
+ * of the first job that failed. */
+aidw_status aidw_batch_job_status(aidw_batch* b, int32_t* status, hipStream_t stream);
+
+/* Sizes of a plan (host only). */
+typedef struct {
+  int32_t njobs;
+  int64_t total_data;       /* sum of n                              */
+  int64_t total_queries;    /* sum of m                              */
+  double total_pairs;       /* sum of n * m: pair evaluations of Eq. 1 */
+  int64_t total_cells;      /* sum of the jobs' cell budgets         */
+  int32_t work_items;       /* items of the persistent pair launch   */
+  int32_t workers;          /* its workgroups                        */
+  int32_t kmax;             /* register k-list length of the kNN kernel */
+  int64_t workspace_bytes;  /* device workspace                      */
+  aidw_batch_config config;
+} aidw_batch_desc;
+
+aidw_status aidw_batch_describe(const aidw_batch* b, aidw_batch_desc* out);
+
+/* Per-stage device times of a plan's runs, recorded with HIP events when
+ * enabled (a timed run is launched directly, not through the graph). */
+typedef struct {
+  float grid_ms;    /* gather, bounds, grid scalars, counting sort, CSR     */
+  float knn_ms;     /* query binning, kNN + Eq. 3, Eq. 4-6, class ordering  */
+  float interp_ms;  /* the persistent pair kernel of Eq. 1                  */
+  float finish_ms;  /* combine, coincident-query fix-up, outputs            */
+} aidw_batch_timing;
+
+aidw_status aidw_batch_set_timing(aidw_batch* b, int32_t enable);
+/* Waits for the last timed run of the plan and reports its stage times. */
+aidw_status aidw_batch_last_timing(aidw_batch* b, aidw_batch_timing* out);
+
+/* Frees the plan and its workspace (waits for the device).  NULL is a no-op. */
+void aidw_batch_destroy(aidw_batch* b);
+
+/* One-shot: create a plan (cfg may be NULL; use_graph is ignored), run it,
+ * report per-job status into status [njobs] (may be NULL) and destroy it.
+ * Synchronises the stream.  Returns as aidw_batch_job_status. */
+aidw_status aidw_run_batch(const aidw_job* jobs, int32_t njobs, const aidw_batch_config* cfg, int32_t* status,
+                           hipStream_t stream);
+
+/* Autotuner kernel: for each candidate config, builds a plan for the jobs, runs
+ * it once (warm-up, graph capture) and then `reps` times, and stores the mean
+ * device time per run in ms_out [ncandidates].  The jobs' outputs are written
+ * by every run.  Synchronises the stream.  Errors: those of aidw_batch_create
+ * and aidw_batch_run for the failing candidate. */
+aidw_status aidw_batch_tune(const aidw_job* jobs, int32_t njobs, const aidw_batch_config* candidates,
+                            int32_t ncandidates, int32_t reps, float* ms_out, hipStream_t stream);
+
 /* Static text for a status code. */
 const char* aidw_status_string(aidw_status st);
 

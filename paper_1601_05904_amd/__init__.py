@@ -57,6 +57,29 @@ class _Timing(ctypes.Structure):
                 ("finish_ms", ctypes.c_float), ("interp_q", ctypes.c_int32), ("interp_split", ctypes.c_int32)]
 
 
+class _BatchConfig(ctypes.Structure):
+    _fields_ = [("q", ctypes.c_int32), ("split_points", ctypes.c_int32), ("workers_per_cu", ctypes.c_int32),
+                ("integer_powers", ctypes.c_int32), ("use_graph", ctypes.c_int32)]
+
+
+class _Job(ctypes.Structure):
+    _fields_ = [("x", ctypes.c_void_p), ("y", ctypes.c_void_p), ("z", ctypes.c_void_p), ("n", ctypes.c_int64),
+                ("qx", ctypes.c_void_p), ("qy", ctypes.c_void_p), ("m", ctypes.c_int64), ("params", _Params),
+                ("qz", ctypes.c_void_p), ("alpha_out", ctypes.c_void_p), ("r_obs_out", ctypes.c_void_p)]
+
+
+class _BatchDesc(ctypes.Structure):
+    _fields_ = [("njobs", ctypes.c_int32), ("total_data", ctypes.c_int64), ("total_queries", ctypes.c_int64),
+                ("total_pairs", ctypes.c_double), ("total_cells", ctypes.c_int64), ("work_items", ctypes.c_int32),
+                ("workers", ctypes.c_int32), ("kmax", ctypes.c_int32), ("workspace_bytes", ctypes.c_int64),
+                ("config", _BatchConfig)]
+
+
+class _BatchTiming(ctypes.Structure):
+    _fields_ = [("grid_ms", ctypes.c_float), ("knn_ms", ctypes.c_float), ("interp_ms", ctypes.c_float),
+                ("finish_ms", ctypes.c_float)]
+
+
 @dataclass
 class Params:
     """aidw_params: k (Eq. 3), levels alpha_1..alpha_5 (Eq. 6), r_min / r_max (Eq. 5),
@@ -139,10 +162,24 @@ def load(build_if_missing: bool = True):
     L.aidw_mlp_train.argtypes = [_VP, _VP, _VP, i64, i32, i32, ctypes.c_float, u64, _VP, _VP]
     L.aidw_run_learned.argtypes = [_VP, _VP, _VP, i64, _VP, _VP, i64, P(_Params), _VP, i32, ctypes.c_double, _VP, _VP,
                                    _VP, P(i64), _VP]
+    L.aidw_batch_config_default.argtypes = [P(_BatchConfig)]
+    L.aidw_batch_config_default.restype = None
+    L.aidw_batch_create.argtypes = [P(_Job), i32, P(_BatchConfig), P(_VP)]
+    L.aidw_batch_run.argtypes = [_VP, _VP]
+    L.aidw_batch_job_status.argtypes = [_VP, P(i32), _VP]
+    L.aidw_batch_describe.argtypes = [_VP, P(_BatchDesc)]
+    L.aidw_batch_set_timing.argtypes = [_VP, i32]
+    L.aidw_batch_last_timing.argtypes = [_VP, P(_BatchTiming)]
+    L.aidw_batch_destroy.argtypes = [_VP]
+    L.aidw_batch_destroy.restype = None
+    L.aidw_run_batch.argtypes = [P(_Job), i32, P(_BatchConfig), P(i32), _VP]
+    L.aidw_batch_tune.argtypes = [P(_Job), i32, P(_BatchConfig), i32, i32, P(ctypes.c_float), _VP]
     for name in ("aidw_build_grid", "aidw_grid_describe", "aidw_grid_arrays", "aidw_grid_copy_arrays", "aidw_knn",
                  "aidw_interpolate", "aidw_run", "aidw_set_timing", "aidw_last_timing", "aidw_set_interp_config",
                  "aidw_mlp_create", "aidw_mlp_set_params", "aidw_mlp_get_params", "aidw_mlp_save", "aidw_mlp_load",
-                 "aidw_features", "aidw_mlp_forward", "aidw_mlp_gradients", "aidw_mlp_train", "aidw_run_learned"):
+                 "aidw_features", "aidw_mlp_forward", "aidw_mlp_gradients", "aidw_mlp_train", "aidw_run_learned",
+                 "aidw_batch_create", "aidw_batch_run", "aidw_batch_job_status", "aidw_batch_describe",
+                 "aidw_batch_set_timing", "aidw_batch_last_timing", "aidw_run_batch", "aidw_batch_tune"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L

@@ -28,6 +28,34 @@ struct BoundsPartial {
   int32_t pad[3];
 };
 
+// Slack, in cells, that covers the float32 binning error of a coordinate in a
+// grid of ncol x nrow cells: |fl(fl(x - minX) * inv) - (x - minX) * inv| <= (c + 1) * 2^-23
+// for column c, taken with a wide margin.
+__host__ __device__ inline double slack_cells(int32_t ncol, int32_t nrow) {
+  const double span = (double)(ncol > nrow ? ncol : nrow) + 1.0;
+  return span * 4.76837158203125e-07 /* 2^-21 */ + 1e-9;
+}
+inline double slack_cells(const GridScalars& g) { return slack_cells(g.ncol, g.nrow); }
+
+// ---- host helpers shared by the ABI sources (api.hip, batch.hip) ----
+
+// Records a message for aidw_last_error_detail on the calling thread and returns st.
+aidw_status fail(aidw_status st, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+// AIDW_ENOMEM for allocation failures, else AIDW_EDEVICE, with the HIP message.
+aidw_status hip_fail(hipError_t e, const char* what);
+// hipMalloc of at least one byte; honours the AIDW_FAULT=alloc test hook.
+hipError_t dmalloc(void** p, size_t bytes);
+// Checks the method parameters other than k (alpha levels, r_min / r_max, area, cell side).
+aidw_status check_params(const aidw_params* p);
+// Smallest b with 2^b >= ncells (at most 31).
+int bits_for(int64_t ncells);
+
+#define HIP_TRY(expr, what)                            \
+  do {                                                 \
+    hipError_t e_ = (expr);                            \
+    if (e_ != hipSuccess) return hip_fail(e_, what);   \
+  } while (0)
+
 constexpr int kBoundsBlocks = 512;
 constexpr int kBoundsThreads = 256;
 constexpr int kSortThreads = 256;

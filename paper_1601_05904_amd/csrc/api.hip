@@ -41,7 +41,10 @@ struct Timing {
 };
 thread_local Timing g_tm;
 
-aidw_status fail(aidw_status st, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+}  // namespace
+
+namespace aidw {
+
 aidw_status fail(aidw_status st, const char* fmt, ...) {
   char buf[512];
   va_list ap;
@@ -57,12 +60,6 @@ aidw_status hip_fail(hipError_t e, const char* what) {
     return fail(AIDW_ENOMEM, "%s: %s", what, hipGetErrorString(e));
   return fail(AIDW_EDEVICE, "%s: %s", what, hipGetErrorString(e));
 }
-
-#define HIP_TRY(expr, what)                      \
-  do {                                           \
-    hipError_t e_ = (expr);                      \
-    if (e_ != hipSuccess) return hip_fail(e_, what); \
-  } while (0)
 
 // Test hook: AIDW_FAULT=alloc makes every device allocation fail (host-forced ENOMEM).
 bool fault_alloc() {
@@ -128,12 +125,9 @@ int bits_for(int64_t ncells) {
   return b;
 }
 
-// Slack (in cells) that covers the float32 binning error of a coordinate in
-// column c: |fl(fl(x - minX) * inv) - (x - minX) * inv| <= (c + 1) * 2^-23.
-double slack_cells(const GridScalars& g) {
-  const double span = (double)(g.ncol > g.nrow ? g.ncol : g.nrow) + 1.0;
-  return span * ldexp(1.0, -21) + 1e-9;
-}
+}  // namespace aidw
+
+namespace {
 
 aidw_status build_grid_impl(const float* x, const float* y, int64_t n, const float* qx, const float* qy, int64_t m,
                             const aidw_params* p, hipStream_t s, bool async, aidw_grid** out) {

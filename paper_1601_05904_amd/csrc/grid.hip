@@ -8,23 +8,15 @@
 // cell_start[c], size = cell_start[c+1] - cell_start[c]) come from a binary
 // search over the sorted keys, which also covers empty cells.
 #include "aidw_internal.h"
+#include "grid_core.h"
 
 namespace aidw {
 
 namespace {
 
-__device__ inline float wave_min(float v) {
-  for (int o = 32; o > 0; o >>= 1) v = fminf(v, __shfl_xor(v, o, 64));
-  return v;
-}
-__device__ inline float wave_max(float v) {
-  for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
-  return v;
-}
-__device__ inline int wave_or(int v) {
-  for (int o = 32; o > 0; o >>= 1) v |= __shfl_xor(v, o, 64);
-  return v;
-}
+using gridc::wave_max;
+using gridc::wave_min;
+using gridc::wave_or;
 
 // Per-block min / max of x and y over the data points followed by the queries
 // (Section 4.1.1: the grid encloses both sets), plus a non-finite flag.
@@ -72,79 +64,13 @@ __global__ __launch_bounds__(kBoundsThreads) void k_bounds(const float* __restri
   }
 }
 
-// Reduces the partials and derives the grid scalars (Eq. 2, Section 4.1.1), in
-// float64: A = bounding-box area unless given, r_exp = 1 / (2 sqrt(n / A)),
-// cell side = given or sqrt(occ * A / n), nCol = (int)((W + cw) / cw), nRow likewise.
+// Reduces the partials and derives the grid scalars (Eq. 2, Section 4.1.1).
 __global__ __launch_bounds__(256) void k_finalize(const BoundsPartial* __restrict__ partial, int nparts, int64_t n,
                                                   double area_in, double cw_in, double occ,
                                                   GridScalars* __restrict__ out) {
-  float mnx = INFINITY, mny = INFINITY, mxx = -INFINITY, mxy = -INFINITY;
-  int bad = 0;
-  for (int i = threadIdx.x; i < nparts; i += blockDim.x) {
-    mnx = fminf(mnx, partial[i].minx);
-    mny = fminf(mny, partial[i].miny);
-    mxx = fmaxf(mxx, partial[i].maxx);
-    mxy = fmaxf(mxy, partial[i].maxy);
-    bad |= partial[i].nonfinite;
-  }
-  mnx = wave_min(mnx);
-  mny = wave_min(mny);
-  mxx = wave_max(mxx);
-  mxy = wave_max(mxy);
-  bad = wave_or(bad);
-  __shared__ BoundsPartial s[4];
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  if (lane == 0) s[wave] = BoundsPartial{mnx, mny, mxx, mxy, bad, {0, 0, 0}};
-  __syncthreads();
+  const BoundsPartial r = gridc::block_reduce_bounds(partial, 0, nparts);
   if (threadIdx.x != 0) return;
-  for (int w = 1; w < 4; ++w) {
-    s[0].minx = fminf(s[0].minx, s[w].minx);
-    s[0].miny = fminf(s[0].miny, s[w].miny);
-    s[0].maxx = fmaxf(s[0].maxx, s[w].maxx);
-    s[0].maxy = fmaxf(s[0].maxy, s[w].maxy);
-    s[0].nonfinite |= s[w].nonfinite;
-  }
-  GridScalars g{};
-  g.minx = s[0].minx;
-  g.miny = s[0].miny;
-  g.maxx = s[0].maxx;
-  g.maxy = s[0].maxy;
-  g.status = AIDW_OK;
-  if (s[0].nonfinite) {
-    g.status = AIDW_ENONFINITE;
-    *out = g;
-    return;
-  }
-  const double W = (double)g.maxx - (double)g.minx;
-  const double H = (double)g.maxy - (double)g.miny;
-  const double area = area_in > 0 ? area_in : W * H;
-  if (!(area > 0) || !isfinite(area)) {
-    g.status = AIDW_EDEGENERATE;
-    *out = g;
-    return;
-  }
-  g.area = area;
-  g.r_exp = 1.0 / (2.0 * sqrt((double)n / area));
-  const double cw = cw_in > 0 ? cw_in : sqrt(occ * area / (double)n);
-  const double fc = (W + cw) / cw;
-  const double fr = (H + cw) / cw;
-  if (!(cw > 0) || !(fc < (double)AIDW_MAX_CELLS) || !(fr < (double)AIDW_MAX_CELLS)) {
-    g.status = AIDW_ECAPACITY;
-    *out = g;
-    return;
-  }
-  g.ncol = (int32_t)fc;
-  g.nrow = (int32_t)fr;
-  g.ncells = (int64_t)g.ncol * g.nrow;
-  if (g.ncells > AIDW_MAX_CELLS) {
-    g.status = AIDW_ECAPACITY;
-    *out = g;
-    return;
-  }
-  g.cw = cw;
-  g.inv_cw = (float)(1.0 / cw);
-  g.cwd = 1.0 / (double)g.inv_cw;
-  *out = g;
+  *out = gridc::grid_scalars(r.minx, r.miny, r.maxx, r.maxy, r.nonfinite != 0, n, area_in, cw_in, occ, 0);
 }
 
 // Section 4.1.2: cell of each data point, (x - minX) * inv_cw in float32 truncated,

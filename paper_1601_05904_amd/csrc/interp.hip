@@ -32,95 +32,20 @@
 #include <float.h>
 
 #include "aidw_internal.h"
+#include "knn_core.h"
+#include "pair_core.h"
 
 namespace aidw {
 
 namespace {
 
-constexpr int kThreads = 256;
-#ifndef AIDW_CHUNK
-#define AIDW_CHUNK 8
-#endif
-constexpr int kChunk = AIDW_CHUNK;  // data points per scalar fetch
-constexpr int kTile = 256;   // data points per float32 partial before the two-sum fold
-constexpr int kMaxIntPow = 8;  // integer alpha classes with a dedicated kernel
-
-// Eq. 5 as printed: 0 below R_min, 1 above R_max, else 0.5 - 0.5 cos(pi / R_max (R - R_min)).
-__device__ inline double fuzzy_mu(double R, double rmin, double rmax) {
-  if (R <= rmin) return 0.0;
-  if (R >= rmax) return 1.0;
-  return 0.5 - 0.5 * cos((M_PI / rmax) * (R - rmin));
-}
-
-// Eq. 6: piecewise-linear between the levels at mu = 0.1, 0.3, 0.5, 0.7, 0.9, constant outside.
-__device__ inline double level_alpha(double mu, const double* a) {
-  if (mu <= 0.1) return a[0];
-  if (mu <= 0.3) return a[0] * (1.0 - 5.0 * (mu - 0.1)) + 5.0 * a[1] * (mu - 0.1);
-  if (mu <= 0.5) return 5.0 * a[2] * (mu - 0.3) + a[1] * (1.0 - 5.0 * (mu - 0.3));
-  if (mu <= 0.7) return a[2] * (1.0 - 5.0 * (mu - 0.5)) + 5.0 * a[3] * (mu - 0.5);
-  if (mu <= 0.9) return 5.0 * a[4] * (mu - 0.7) + a[3] * (1.0 - 5.0 * (mu - 0.7));
-  return a[4];
-}
-
-struct Acc {
-  float num_t, den_t;   // current tile
-  float num_h, num_l;   // folded: two-sum hi / lo
-  float den_h, den_l;
-};
-
-__device__ inline void two_sum_fold(float& hi, float& lo, float v) {
-  const float s = hi + v;
-  const float bp = s - hi;
-  const float err = (hi - (s - bp)) + (v - bp);
-  hi = s;
-  lo += err;
-}
-
-// w = r^P by repeated squaring (P known at compile time).
-template <int P>
-__device__ inline float ipow(float r) {
-  if constexpr (P == 1) {
-    return r;
-  } else if constexpr (P % 2 == 0) {
-    const float h = ipow<P / 2>(r);
-    return h * h;
-  } else {
-    return ipow<P - 1>(r) * r;
-  }
-}
-
-// POW = 0: general alpha, w = 2^(nh log2 t); POW = p > 0: alpha == p, w = rsq(t)^p.
-template <int Q, int POW>
-struct Lane {
-  float qx[Q], qy[Q], nh[Q], sc[Q];
-  Acc acc[Q];
-
-  __device__ inline void pair(float x, float y, float z) {
-#pragma unroll
-    for (int j = 0; j < Q; ++j) {
-      const float dx = qx[j] - x;
-      const float dy = qy[j] - y;
-      const float d2 = __builtin_fmaf(dx, dx, dy * dy);
-      const float t = d2 * sc[j];
-      float w;
-      if constexpr (POW == 0)
-        w = __builtin_amdgcn_exp2f(__builtin_amdgcn_logf(t) * nh[j]);
-      else
-        w = ipow<POW>(__builtin_amdgcn_rsqf(t));
-      acc[j].num_t = __builtin_fmaf(w, z, acc[j].num_t);
-      acc[j].den_t += w;
-    }
-  }
-  __device__ inline void fold() {
-#pragma unroll
-    for (int j = 0; j < Q; ++j) {
-      two_sum_fold(acc[j].num_h, acc[j].num_l, acc[j].num_t);
-      two_sum_fold(acc[j].den_h, acc[j].den_l, acc[j].den_t);
-      acc[j].num_t = 0.0f;
-      acc[j].den_t = 0.0f;
-    }
-  }
-};
+using pair::alpha_class;
+using pair::fuzzy_mu;
+using pair::kChunk;
+using pair::kMaxIntPow;
+using pair::kThreads;
+using pair::Lane;
+using pair::level_alpha;
 
 // Eq. 4-6 per query (float64), the query's class key and the identity permutation.
 __global__ __launch_bounds__(256) void k_alpha_class(const float* __restrict__ r_obs, int m, AlphaParams ap,
@@ -133,9 +58,7 @@ __global__ __launch_bounds__(256) void k_alpha_class(const float* __restrict__ r
   const float af = (float)alpha;
   alpha_f[q] = af;
   if (alpha_out) alpha_out[q] = af;
-  uint32_t key = 0;
-  if (alpha >= 1.0 && alpha <= (double)kMaxIntPow && alpha == floor(alpha)) key = (uint32_t)alpha;
-  keys[q] = key;
+  keys[q] = alpha_class(alpha);
   vals[q] = (uint32_t)q;
 }
 
@@ -176,70 +99,23 @@ __global__ __launch_bounds__(kThreads) void k_interp(const float* __restrict__ x
 #pragma unroll
   for (int j = 0; j < Q; ++j) {
     const int pos = pos0 + j * kThreads + threadIdx.x;
-    float fx = 0.0f, fy = 0.0f, nh = 0.0f, sc = 1.0f;
     qid[j] = 0xffffffffu;
     if (pos < m) {
       const uint32_t q = perm[pos];
       qid[j] = q;
-      fx = qx[q];
-      fy = qy[q];
-      nh = -0.5f * alpha_f[q];
-      const float d1 = d1sq[q];
-      sc = d1 > 0.0f ? (float)(1.0 / (double)d1) : 1.0f;  // d1 == 0: coincident query, fixed up later
+      L.set(j, qx[q], qy[q], alpha_f[q], d1sq[q]);
+    } else {
+      L.clear(j);
     }
-    L.qx[j] = fx;
-    L.qy[j] = fy;
-    L.nh[j] = nh;
-    L.sc[j] = sc;
-    L.acc[j] = Acc{0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
   }
-
   const int lo = split * chunk;
-  const int hi = min(n, lo + chunk);
-  const int nfull = hi > lo ? (hi - lo) / kChunk : 0;
-  constexpr int kFoldMask = kTile / kChunk - 1;
-  // Double-buffered: each iteration fetches the next chunk while it evaluates the
-  // current one, and the compiler is left free to place the fetch (pinning it to
-  // the top of the loop bunches the scalar work and measured slower).  x, y, z are
-  // padded copies with >= kChunk points past the last full chunk, so the final
-  // prefetch stays in bounds.
-  if (nfull > 0) {
-    float cx[kChunk], cy[kChunk], cz[kChunk];
-#pragma unroll
-    for (int i = 0; i < kChunk; ++i) {
-      cx[i] = x[lo + i];
-      cy[i] = y[lo + i];
-      cz[i] = z[lo + i];
-    }
-    for (int ci = 0; ci < nfull; ++ci) {
-      const int pn = lo + (ci + 1) * kChunk;
-      float nx[kChunk], ny[kChunk], nz[kChunk];
-#pragma unroll
-      for (int i = 0; i < kChunk; ++i) {
-        nx[i] = x[pn + i];
-        ny[i] = y[pn + i];
-        nz[i] = z[pn + i];
-      }
-
-#pragma unroll
-      for (int i = 0; i < kChunk; ++i) L.pair(cx[i], cy[i], cz[i]);
-      if (((ci + 1) & kFoldMask) == 0) L.fold();
-#pragma unroll
-      for (int i = 0; i < kChunk; ++i) {
-        cx[i] = nx[i];
-        cy[i] = ny[i];
-        cz[i] = nz[i];
-      }
-    }
-  }
-  for (int p = lo + nfull * kChunk; p < hi; ++p) L.pair(x[p], y[p], z[p]);
-  L.fold();
+  pair::pair_range<Q, POW>(L, x, y, z, lo, min(n, lo + chunk));
 
 #pragma unroll
   for (int j = 0; j < Q; ++j) {
     if (qid[j] == 0xffffffffu) continue;
-    const double num = (double)L.acc[j].num_h + (double)L.acc[j].num_l;
-    const double den = (double)L.acc[j].den_h + (double)L.acc[j].den_l;
+    const double num = L.num(j);
+    const double den = L.den(j);
     if (gridDim.y == 1)
       qz[qid[j]] = (float)(num / den);
     else
@@ -281,13 +157,6 @@ __global__ __launch_bounds__(256) void k_coincident_list(const float* __restrict
   if (d1sq[q] == 0.0f) list[atomicAdd(count, 1u)] = (uint32_t)q;
 }
 
-__device__ inline int clamp_cell(float t, int nc) {
-  if (!(t >= 0.0f)) return 0;
-  if (t >= 2147483520.0f) return nc - 1;
-  const int c = (int)t;
-  return c > nc - 1 ? nc - 1 : c;
-}
-
 // Coincident query = mean z of the data points at its exact position (the limit
 // of Eq. 1).  Those points share the query's cell; the cell is ordered by index,
 // so the sum runs in index order.
@@ -299,21 +168,11 @@ __global__ __launch_bounds__(256) void k_fixup_grid(const uint32_t* __restrict__
                                                     const int32_t* __restrict__ sidx, const float* __restrict__ z,
                                                     float* __restrict__ qz) {
   const uint32_t cnt = *count;
+  const knn::View g{gs->minx, gs->miny, gs->inv_cw, gs->ncol, gs->nrow, gs->cwd};
   for (uint32_t e = blockIdx.x * blockDim.x + threadIdx.x; e < cnt; e += gridDim.x * blockDim.x) {
     const uint32_t q = list[e];
-    const float fx = qx[q], fy = qy[q];
-    const int col = clamp_cell((fx - gs->minx) * gs->inv_cw, gs->ncol);
-    const int row = clamp_cell((fy - gs->miny) * gs->inv_cw, gs->nrow);
-    const int c = row * gs->ncol + col;
-    double s = 0.0;
-    int hits = 0;
-    for (int p = cell_start[c]; p < cell_start[c + 1]; ++p) {
-      if (sx[p] == fx && sy[p] == fy) {
-        s += (double)z[sidx[p]];
-        ++hits;
-      }
-    }
-    if (hits > 0) qz[q] = (float)(s / hits);
+    float v;
+    if (knn::coincident_mean(g, cell_start, sx, sy, sidx, z, qx[q], qy[q], v)) qz[q] = v;
   }
 }
 
@@ -414,7 +273,7 @@ hipError_t launch_interp(const float* x, const float* y, const float* z, int n, 
   }
 }
 
-int interp_padded_len(int n) { return (n + kChunk - 1) / kChunk * kChunk + kChunk; }
+int interp_padded_len(int n) { return pair::padded_len(n); }
 
 hipError_t launch_pad_copy(const float* x, const float* y, const float* z, int n, float* xp, float* yp, float* zp,
                            hipStream_t s) {

@@ -1,0 +1,164 @@
+// Device code shared by the kNN kernels of the single-job path (knn.hip) and the
+// batched path (batch.hip): the exact ring search of Section 3.2.4 / 4.1.4 over
+// one job's grid, and the coincident-query mean.  The search rule, the stop rule
+// and the (squared distance, index) ordering are described in knn.hip.
+#pragma once
+
+#include <float.h>
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace aidw {
+namespace knn {
+
+// Cell coordinate of a float32 offset t = (x - min) * inv_cw: truncated, clamped
+// into [0, nc); negative or NaN -> 0.
+__device__ inline int clamp_cell(float t, int nc) {
+  if (!(t >= 0.0f)) return 0;
+  if (t >= 2147483520.0f) return nc - 1;
+  const int c = (int)t;
+  return c > nc - 1 ? nc - 1 : c;
+}
+
+// One job's grid scalars.  The CSR arrays travel beside it: cell_start indexed
+// from the job's first cell, sx, sy, sidx in cell order.
+struct View {
+  float minx, miny, inv;
+  int ncol, nrow;
+  double cwd;
+};
+
+// The k nearest data points of (fx, fy): on return slots [KMAX - k, KMAX) of
+// (bk, bi) hold their squared distances and indices in ascending (d2, index)
+// order.  slack_cells covers the float32 binning error, in cells.
+template <int KMAX>
+__device__ __forceinline__ void search(const View& g, const int32_t* __restrict__ cell_start,
+                                       const float* __restrict__ sx, const float* __restrict__ sy,
+                                       const int32_t* __restrict__ sidx, float fx, float fy, int k,
+                                       double slack_cells, double (&bk)[KMAX], int32_t (&bi)[KMAX]) {
+  const double px = fx, py = fy;
+  const int ncol = g.ncol, nrow = g.nrow;
+  const double cwd = g.cwd;
+  const double minxd = g.minx, minyd = g.miny;
+  const int c0 = clamp_cell((fx - g.minx) * g.inv, ncol);
+  const int r0 = clamp_cell((fy - g.miny) * g.inv, nrow);
+  const double slack = slack_cells * cwd;
+  // slots [0, KMAX - k) hold a -1 sentinel that no candidate can pass; the k
+  // live slots [KMAX - k, KMAX) are kept in ascending (d2, index) order.
+#pragma unroll
+  for (int s = 0; s < KMAX; ++s) {
+    const bool pad = s < KMAX - k;
+    bk[s] = pad ? -1.0 : INFINITY;
+    bi[s] = pad ? -1 : INT32_MAX;
+  }
+  int count = 0;
+
+  for (int L = 0;; ++L) {
+    const int cl = c0 - L, cr = c0 + L, rb = r0 - L, rt = r0 + L;
+    const int ca = cl > 0 ? cl : 0;
+    const int cb = cr < ncol - 1 ? cr : ncol - 1;
+    const int ra = rb + 1 > 0 ? rb + 1 : 0;
+    const int re = rt - 1 < nrow - 1 ? rt - 1 : nrow - 1;
+    const int nside = re >= ra ? re - ra + 1 : 0;
+    // ring L as segments: [0] bottom row, [1] top row (each one contiguous run of
+    // points in cell order), then the left / right cell of every row in between.
+    const int nseg = L == 0 ? 1 : 2 + 2 * nside;
+    for (int sg = 0; sg < nseg; ++sg) {
+      int row, a, b;
+      bool ok;
+      if (L == 0) {
+        row = r0;
+        a = b = c0;
+        ok = true;
+      } else if (sg < 2) {
+        row = sg == 0 ? rb : rt;
+        a = ca;
+        b = cb;
+        ok = sg == 0 ? rb >= 0 : rt < nrow;
+      } else {
+        const bool right = (sg - 2) & 1;
+        row = ra + ((sg - 2) >> 1);
+        a = b = right ? cr : cl;
+        ok = right ? cr < ncol : cl >= 0;
+      }
+      if (!ok) continue;
+      const int base = row * ncol;
+      const int p0 = cell_start[base + a];
+      const int p1 = cell_start[base + b + 1];
+      count += p1 - p0;
+      for (int p = p0; p < p1; ++p) {
+        const double dx = (double)sx[p] - px;
+        const double dy = (double)sy[p] - py;
+        const double d2 = dx * dx + dy * dy;
+        const int32_t id = sidx[p];
+        if (d2 < bk[KMAX - 1] || (d2 == bk[KMAX - 1] && id < bi[KMAX - 1])) {
+          bk[KMAX - 1] = d2;
+          bi[KMAX - 1] = id;
+#pragma unroll
+          for (int s = KMAX - 1; s > 0; --s) {
+            const bool sw = bk[s] < bk[s - 1] || (bk[s] == bk[s - 1] && bi[s] < bi[s - 1]);
+            const double lo = bk[s], hi = bk[s - 1];
+            const int32_t ilo = bi[s], ihi = bi[s - 1];
+            bk[s - 1] = sw ? lo : hi;
+            bk[s] = sw ? hi : lo;
+            bi[s - 1] = sw ? ilo : ihi;
+            bi[s] = sw ? ihi : ilo;
+          }
+        }
+      }
+    }
+    const bool open_l = cl > 0, open_r = cr < ncol - 1, open_b = rb > 0, open_t = rt < nrow - 1;
+    if (!(open_l || open_r || open_b || open_t)) break;  // the block covers the grid
+    if (count >= k) {
+      double dout = INFINITY;
+      if (open_l) dout = fmin(dout, px - (minxd + (double)cl * cwd));
+      if (open_r) dout = fmin(dout, (minxd + (double)(cr + 1) * cwd) - px);
+      if (open_b) dout = fmin(dout, py - (minyd + (double)rb * cwd));
+      if (open_t) dout = fmin(dout, (minyd + (double)(rt + 1) * cwd) - py);
+      dout -= slack;
+      if (dout > 0.0 && bk[KMAX - 1] < dout * dout) break;
+    }
+  }
+
+}
+
+// Eq. 3 from the search result: r_obs = (1/k) sum of the k distances, added in
+// ascending order in float64; d1 = the nearest squared distance (0 for a
+// coincident query, else at least FLT_MIN so that 1/d1 stays finite).
+template <int KMAX>
+__device__ __forceinline__ void summarise(const double (&bk)[KMAX], int k, float& r_obs, float& d1) {
+  double sum = 0.0;
+  d1 = 0.0f;
+#pragma unroll
+  for (int s = 0; s < KMAX; ++s) {
+    if (s >= KMAX - k) sum += sqrt(bk[s]);
+    if (s == KMAX - k) d1 = bk[s] == 0.0 ? 0.0f : fmaxf((float)bk[s], FLT_MIN);
+  }
+  r_obs = (float)(sum / (double)k);
+}
+
+// A coincident query's value: the mean z of the data points at its exact
+// position (the limit of Eq. 1).  Those points share the query's cell, which is
+// ordered by index, so the float64 sum runs in index order.  Returns false if
+// no data point is at (fx, fy).
+__device__ inline bool coincident_mean(const View& g, const int32_t* __restrict__ cell_start,
+                                       const float* __restrict__ sx, const float* __restrict__ sy,
+                                       const int32_t* __restrict__ sidx, const float* __restrict__ z, float fx,
+                                       float fy, float& out) {
+  const int col = clamp_cell((fx - g.minx) * g.inv, g.ncol);
+  const int row = clamp_cell((fy - g.miny) * g.inv, g.nrow);
+  const int c = row * g.ncol + col;
+  double s = 0.0;
+  int hits = 0;
+  for (int p = cell_start[c]; p < cell_start[c + 1]; ++p) {
+    if (sx[p] == fx && sy[p] == fy) {
+      s += (double)z[sidx[p]];
+      ++hits;
+    }
+  }
+  if (hits > 0) out = (float)(s / hits);
+  return hits > 0;
+}
+
+}  // namespace knn
+}  // namespace aidw

@@ -80,3 +80,72 @@ def test_other_entry_points_validate(L):
     t = aidw._Timing()
     assert L.aidw_last_timing(ctypes.byref(t)) == aidw.EINVAL
     L.aidw_grid_destroy(None)
+
+
+def _jobs(count=2, **over):
+    arr = (aidw._Job * count)()
+    for j in range(count):
+        a = arr[j]
+        a.x = a.y = a.z = a.qx = a.qy = a.qz = FAKE
+        a.n, a.m = 100, 10
+        a.params = aidw.Params(k=10)._c()
+        for k, v in over.items():
+            if k == "p":
+                a.params = aidw.Params(**v)._c()
+            else:
+                setattr(a, k, v)
+    return arr
+
+
+def test_batch_config_default(L):
+    c = aidw._BatchConfig()
+    L.aidw_batch_config_default(ctypes.byref(c))
+    assert (c.q, c.split_points, c.workers_per_cu, c.integer_powers, c.use_graph) == (1, 0, 8, 1, 0)
+
+
+@pytest.mark.parametrize("case", [
+    dict(n=0), dict(m=-1), dict(x=None), dict(z=None), dict(qx=None), dict(qz=None), dict(p=dict(k=0)),
+    dict(p=dict(k=101)), dict(p=dict(k=65)), dict(p=dict(r_min=3.0)), dict(p=dict(occupancy=-1.0)),
+])
+def test_batch_create_rejects_invalid_jobs(L, case):
+    out = ctypes.c_void_p()
+    st = L.aidw_batch_create(_jobs(3, **case), 3, None, ctypes.byref(out))
+    assert st == aidw.EINVAL and not out.value
+    assert "job 0" in L.aidw_last_error_detail().decode()
+
+
+@pytest.mark.parametrize("cfg", [dict(q=3), dict(q=0), dict(split_points=-8), dict(workers_per_cu=0),
+                                 dict(workers_per_cu=33), dict(integer_powers=2), dict(use_graph=-1)])
+def test_batch_create_rejects_invalid_config(L, cfg):
+    c = aidw._BatchConfig()
+    L.aidw_batch_config_default(ctypes.byref(c))
+    for k, v in cfg.items():
+        setattr(c, k, v)
+    out = ctypes.c_void_p()
+    assert L.aidw_batch_create(_jobs(), 2, ctypes.byref(c), ctypes.byref(out)) == aidw.EINVAL
+    if "use_graph" not in cfg:  # the one-shot form ignores use_graph
+        assert L.aidw_run_batch(_jobs(), 2, ctypes.byref(c), None, None) == aidw.EINVAL
+
+
+def test_batch_other_entry_points_validate(L):
+    out = ctypes.c_void_p()
+    assert L.aidw_batch_create(None, 2, None, ctypes.byref(out)) == aidw.EINVAL
+    assert L.aidw_batch_create(_jobs(), 0, None, ctypes.byref(out)) == aidw.EINVAL
+    assert L.aidw_batch_create(_jobs(), 2, None, None) == aidw.EINVAL
+    assert L.aidw_batch_run(None, None) == aidw.EINVAL
+    assert L.aidw_batch_job_status(None, None, None) == aidw.EINVAL
+    assert L.aidw_batch_describe(None, None) == aidw.EINVAL
+    assert L.aidw_batch_set_timing(None, 1) == aidw.EINVAL
+    assert L.aidw_batch_last_timing(None, None) == aidw.EINVAL
+    L.aidw_batch_destroy(None)
+    ms = (ctypes.c_float * 1)()
+    assert L.aidw_batch_tune(_jobs(), 2, None, 1, 1, ms, None) == aidw.EINVAL
+    bad = (aidw._BatchConfig * 1)()
+    bad[0].q = 5
+    assert L.aidw_batch_tune(_jobs(), 2, bad, 1, 1, ms, None) == aidw.EINVAL
+
+
+def test_batch_totals_beyond_int32_are_capacity_errors(L):
+    out = ctypes.c_void_p()
+    st = L.aidw_batch_create(_jobs(3, n=600_000_000, m=600_000_000), 3, None, ctypes.byref(out))
+    assert st == aidw.ECAPACITY
