@@ -9,9 +9,13 @@ workload is n = m = 2^20 uniform points, k = 10 (synthetic, seeded).
 Printed: one JSON line with the metric, the pair kernel's roofline fraction
 (its duration measured with HIP events on the run's stream), the plain FP64
 CPU oracle timed on a bounded sample of the same workload on this host, and
-the z error of the timed run on that sample.
+the z error of the timed run on that sample.  Two more measurements ride on
+the same line: "learned_r" (plain vs learned-R on the clustered 2^20
+workload, after training the network on held-out sets) and "batch" (256
+independent jobs as one autotuned plan replayed as a HIP graph).
 
     python bench.py [--steps K] [--warmup W] [--workload uniform_1m] [--cpu-sample S] [--no-cpu-baseline]
+                    [--no-learned] [--no-batch] [--no-plain] [--batch-loop]
 """
 import argparse
 import json
@@ -57,13 +61,24 @@ def class_mix_peak(alpha, levels):
     return 1.0 / inv.mean(), {("alpha=%d" % p): float(np.mean(a == p)) for p in range(1, 9) if np.any(a == p)}
 
 
-def measured_traffic(workload):
-    """HBM bytes per launch of the dominant pair kernel, from the committed rocprofv3 counter summary
-    (FETCH_SIZE and WRITE_SIZE scaled by a copy-kernel calibration); None if the pair-kernel source has
-    changed since the counters were taken, or no summary exists for this workload."""
+PAIR_SOURCES = {"k_interp": ("interp.hip", "pair_core.h"), "k_b_interp": ("batch.hip", "pair_core.h")}
+
+
+def source_hash(kernel):
+    """Fingerprint of the sources a pair kernel is built from (counter summaries record it)."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", "k_interp_%s_counters.md" % workload)
-    src = os.path.join(ROOT, "paper_1601_05904_amd", "csrc", "interp.hip")
+    h = hashlib.sha256()
+    for name in PAIR_SOURCES[kernel]:
+        with open(os.path.join(ROOT, "paper_1601_05904_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel, workload):
+    """HBM bytes per launch of a pair kernel, from the committed rocprofv3 counter summary
+    (FETCH_SIZE and WRITE_SIZE scaled by a copy-kernel calibration); None if the kernel's sources
+    have changed since the counters were taken, or no summary exists for this workload."""
+    path = os.path.join(ROOT, "profiles", "%s_%s_counters.md" % (kernel, workload))
     if not os.path.exists(path):
         return None
     fields = {}
@@ -72,9 +87,7 @@ def measured_traffic(workload):
             if ":" in line and not line.startswith(("|", "#", "`")):
                 k, v = line.split(":", 1)
                 fields[k.strip()] = v.strip()
-    with open(src, "rb") as f:
-        h = hashlib.sha256(f.read()).hexdigest()[:16]
-    if fields.get("interp_source_sha256_16") != h or "traffic_bytes_per_launch" not in fields:
+    if fields.get("source_sha256_16") != source_hash(kernel) or "traffic_bytes_per_launch" not in fields:
         return None
     return float(fields["traffic_bytes_per_launch"])
 
@@ -92,6 +105,8 @@ def parse():
     ap.add_argument("--learned-steps", type=int, default=5)
     ap.add_argument("--delta", type=float, default=0.3, help="fallback margin of the alpha-exact rule")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-jobs measurement")
+    ap.add_argument("--no-plain", action="store_true",
+                    help="skip the headline plain run (profiling of the other legs only)")
     ap.add_argument("--batch-steps", type=int, default=10)
     ap.add_argument("--batch-loop", action="store_true",
                     help="also time the same jobs as one aidw_run per job (context for the batched form)")
@@ -247,7 +262,8 @@ def batch_measurement(args, with_oracle):
            "config": info["config"], "work_items": info["work_items"], "workers": info["workers"],
            "autotune_s": tune_s, "stages_ms": st,
            "roofline": {"bound": "alu", "kernel": "k_b_interp", "achieved": achieved / 1e9, "peak": peak / 1e9,
-                        "unit": "Gpair/s", "frac": achieved / peak, "units_per_launch": pairs}}
+                        "unit": "Gpair/s", "frac": achieved / peak, "units_per_launch": pairs,
+                        "traffic": measured_traffic("k_b_interp", "batch_256")}}
     if args.batch_loop:
         aidw.set_interp_config(0, 0, -1)
         outs = []
@@ -272,25 +288,13 @@ def batch_measurement(args, with_oracle):
     return out
 
 
-def main():
-    args = parse()
-    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py runs on one GPU only: the method is measured on a single MI355X "
-              "(the query-sharded multi-GPU design is documented, not built); use --gpus 1", file=sys.stderr)
-        sys.exit(2)
-
+def plain_measurement(args):
+    """The headline: aidw_run over the workload, timed; the pair kernel's roofline; the CPU oracle baseline."""
     import torch
 
     import paper_1601_05904_amd as aidw
     from paper_1601_05904_amd import workloads as W
 
-    if args.copy_calibration:
-        copy_calibration(args.copy_calibration)
-        return
-    if not torch.cuda.is_available():
-        print("no GPU visible", file=sys.stderr)
-        sys.exit(1)
-    aidw.load(build_if_missing=True)
     ds = W.WORKLOADS[args.workload]()
     dev = torch.device("cuda", 0)
     x, y, z, qx, qy = (torch.from_numpy(getattr(ds, k)).to(dev) for k in ("x", "y", "z", "qx", "qy"))
@@ -339,7 +343,7 @@ def main():
         "stages_ms": {k: float(np.mean([s[k] for s in stages])) for k in ("grid_ms", "knn_ms", "interp_ms",
                                                                           "finish_ms")},
         "roofline": {"bound": "alu", "kernel": "k_interp", "achieved": achieved / 1e9, "peak": peak / 1e9,
-                     "unit": "Gpair/s", "frac": achieved / peak, "traffic": measured_traffic(args.workload),
+                     "unit": "Gpair/s", "frac": achieved / peak, "traffic": measured_traffic("k_interp", args.workload),
                      "per_unit": "pair: general alpha 7 VALU + 2 transcendental; integer alpha p 6 VALU + chain(p) "
                                  "multiplies + 1 transcendental", "class_mix": mix,
                      "peak_general_form": PEAK_GENERAL / 1e9, "units_per_launch": pairs},
@@ -361,6 +365,28 @@ def main():
         out["z_error"] = {"metric": "|z - z64| / max(|z64|, sum w|z| / sum w)", "max": float(e.max()),
                           "p999": float(np.quantile(e, 0.999)), "median": float(np.median(e)),
                           "sample": len(sel)}
+    return out
+
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on one GPU only: the method is measured on a single MI355X "
+              "(the query-sharded multi-GPU design is documented, not built); use --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_1601_05904_amd as aidw
+
+    if args.copy_calibration:
+        copy_calibration(args.copy_calibration)
+        return
+    if not torch.cuda.is_available():
+        print("no GPU visible", file=sys.stderr)
+        sys.exit(1)
+    aidw.load(build_if_missing=True)
+    out = {} if args.no_plain else plain_measurement(args)
     if not args.no_learned:
         out["learned_r"] = learned_comparison(args, with_oracle=not args.no_cpu_baseline)
     if not args.no_batch:
