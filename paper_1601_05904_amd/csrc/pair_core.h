@@ -67,23 +67,37 @@ __device__ inline float ipow(float r) {
   }
 }
 
-// Per-lane state of Q queries.  The weight of Eq. 1 is evaluated as
-// w = (d1 / d)^alpha = t^(-alpha/2) with t = d^2 / d1^2 (d1 = the query's nearest
-// distance): the common factor d1^alpha cancels between numerator and
-// denominator and keeps the float32 sums in range.  POW = 0: general alpha,
-// w = 2^(nh log2 t) with nh = -alpha/2; POW = p > 0: alpha == p, w = rsq(t)^p.
+// Scale of a query: s = 2^k, the smallest power of two with s^2 * d1sq >= 1
+// (d1sq = the query's nearest squared distance; 1 when d1sq is 0 or not finite).
+__device__ inline float pow2_scale(float d1sq) {
+  if (!(d1sq > 0.0f) || !(d1sq <= 3.402823466e38f)) return 1.0f;
+  int e;
+  (void)frexpf(d1sq, &e);       // d1sq = m 2^e, m in [0.5, 1)
+  int k = (1 - e + 1) >> 1;     // ceil((1 - e) / 2): m 2^(2k + e) in [1, 4)
+  k = k < -64 ? -64 : (k > 64 ? 64 : k);
+  return ldexpf(1.0f, k);
+}
+
+// Per-lane state of Q queries.  The weight of Eq. 1 is evaluated on the
+// query's scaled squared distance t = s^2 d^2 (s = pow2_scale(d1sq)):
+//   dx s = fma(x, -s, qx s), dy s likewise, t = fma(dx s, dx s, (dy s)^2),
+// which is exactly s^2 times the float32 d^2 = fma(dx, dx, dy dy) because
+// scaling by a power of two commutes with rounding; t >= 1 for every data
+// point (up to one rounding of d1sq), so the weights w = t^(-alpha/2) stay
+// <= ~1 for any alpha, and the common factor s^-alpha cancels between the
+// numerator and the denominator.  POW = 0: general alpha, w = 2^(nh log2 t)
+// with nh = -alpha/2; POW = p > 0: alpha == p, w = rsq(t)^p.
 template <int Q, int POW>
 struct Lane {
-  float qx[Q], qy[Q], nh[Q], sc[Q];
+  float qxs[Q], qys[Q], ns[Q], nh[Q];
   Acc acc[Q];
 
   __device__ inline void pair(float x, float y, float z) {
 #pragma unroll
     for (int j = 0; j < Q; ++j) {
-      const float dx = qx[j] - x;
-      const float dy = qy[j] - y;
-      const float d2 = __builtin_fmaf(dx, dx, dy * dy);
-      const float t = d2 * sc[j];
+      const float dx = __builtin_fmaf(x, ns[j], qxs[j]);
+      const float dy = __builtin_fmaf(y, ns[j], qys[j]);
+      const float t = __builtin_fmaf(dx, dx, dy * dy);
       float w;
       if constexpr (POW == 0)
         w = __builtin_amdgcn_exp2f(__builtin_amdgcn_logf(t) * nh[j]);
@@ -105,18 +119,19 @@ struct Lane {
   // Query j at (fx, fy) with alpha a and nearest squared distance d1 (0: coincident
   // query, whose sums are replaced by the fix-up, so any finite scale serves).
   __device__ inline void set(int j, float fx, float fy, float a, float d1) {
-    qx[j] = fx;
-    qy[j] = fy;
+    const float sc = pow2_scale(d1);
+    qxs[j] = fx * sc;
+    qys[j] = fy * sc;
+    ns[j] = -sc;
     nh[j] = -0.5f * a;
-    sc[j] = d1 > 0.0f ? (float)(1.0 / (double)d1) : 1.0f;
     acc[j] = Acc{0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
   }
   // Unused slot: finite values, result discarded.
   __device__ inline void clear(int j) {
-    qx[j] = 0.0f;
-    qy[j] = 0.0f;
+    qxs[j] = 0.0f;
+    qys[j] = 0.0f;
+    ns[j] = -1.0f;
     nh[j] = 0.0f;
-    sc[j] = 1.0f;
     acc[j] = Acc{0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
   }
   __device__ inline double num(int j) const { return (double)acc[j].num_h + (double)acc[j].num_l; }
