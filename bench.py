@@ -110,6 +110,10 @@ def parse():
     ap.add_argument("--batch-steps", type=int, default=10)
     ap.add_argument("--batch-loop", action="store_true",
                     help="also time the same jobs as one aidw_run per job (context for the batched form)")
+    ap.add_argument("--sweep", action="store_true",
+                    help="only the paper's size sweep (n = m = 10K..1000K): grid vs brute-force kNN, tiled vs "
+                         "untiled interpolation, device stage times and host-inclusive totals")
+    ap.add_argument("--sweep-sizes", default="10,50,100,500,1000", help="sizes in units of 1024 points")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MB",
                     help="only run a plain device copy of MB megabytes (reference for HBM traffic counters)")
     return ap.parse_args()
@@ -368,6 +372,65 @@ def plain_measurement(args):
     return out
 
 
+def sweep_measurement(args):
+    """The paper's sweep shape (Section 5, Tables 1-3): n = m in {10, 50, 100, 500, 1000} x 1024 uniform points,
+    k = 10, each with four versions -- kNN by the even grid ("improved") or by brute force per query
+    ("original", the earlier GPU AIDW), and the interpolation by the tiled kernel or the untiled one.  Per
+    version: device times of the kNN stage (grid build included) and of the interpolation stage (HIP events),
+    and the host-inclusive total (inputs copied from pinned host memory, result copied back)."""
+    import torch
+
+    import paper_1601_05904_amd as aidw
+    from paper_1601_05904_amd import workloads as W
+
+    rows = []
+    for kk in [int(v) for v in args.sweep_sizes.split(",")]:
+        n = kk * 1024
+        ds = W.make(n, n, 10, 700 + kk)
+        host = {a: torch.from_numpy(getattr(ds, a)).pin_memory() for a in ("x", "y", "z", "qx", "qy")}
+        p = aidw.Params(k=10)
+        row = {"n": n, "m": n, "label": "%dK" % kk, "versions": {}}
+        for kname in ("grid", "brute"):
+            for iname in ("tiled", "untiled"):
+                reps = 1 if (kname == "brute" or iname == "untiled") and n >= 500 * 1024 else 2
+                ts = []
+                for rep in range(reps + 1):  # the first pass warms up
+                    torch.cuda.synchronize()
+                    h0 = time.perf_counter()
+                    dev = {a: t.to("cuda", non_blocking=True) for a, t in host.items()}
+                    e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+                    e[0].record()
+                    g = aidw.build_grid(dev["x"], dev["y"], dev["qx"], dev["qy"], p)
+                    if kname == "grid":
+                        r, d1, _ = aidw.knn(g, dev["qx"], dev["qy"], 10)
+                    else:
+                        r, d1, _ = aidw.knn_bruteforce(dev["x"], dev["y"], dev["qx"], dev["qy"], 10)
+                    e[1].record()
+                    qz = aidw.interpolate(dev["x"], dev["y"], dev["z"], dev["qx"], dev["qy"], r, d1, p, grid=g,
+                                          naive=iname == "untiled")
+                    e[2].record()
+                    out = qz.to("cpu")
+                    torch.cuda.synchronize()
+                    h1 = time.perf_counter()
+                    g.close()
+                    if rep:
+                        ts.append((e[0].elapsed_time(e[1]), e[1].elapsed_time(e[2]), (h1 - h0) * 1e3))
+                    del out
+                knn_ms, interp_ms, host_ms = (float(np.mean([t[i] for t in ts])) for i in range(3))
+                name = ("improved" if kname == "grid" else "original") + "_" + ("tiled" if iname == "tiled" else
+                                                                                "naive")
+                row["versions"][name] = {"knn_ms": knn_ms, "interp_ms": interp_ms, "total_host_ms": host_ms}
+        v = row["versions"]
+        row["speedup_knn_improved_vs_original"] = v["original_tiled"]["knn_ms"] / v["improved_tiled"]["knn_ms"]
+        row["speedup_interp_tiled_vs_naive"] = v["improved_naive"]["interp_ms"] / v["improved_tiled"]["interp_ms"]
+        row["speedup_total_improved_vs_original_tiled"] = (v["original_tiled"]["total_host_ms"] /
+                                                           v["improved_tiled"]["total_host_ms"])
+        rows.append(row)
+        print(json.dumps({"sweep_row": row["label"], "improved_tiled_host_ms": v["improved_tiled"]["total_host_ms"]}),
+              file=sys.stderr, flush=True)
+    return rows
+
+
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -386,6 +449,10 @@ def main():
         print("no GPU visible", file=sys.stderr)
         sys.exit(1)
     aidw.load(build_if_missing=True)
+    if args.sweep:
+        print(json.dumps({"sweep": sweep_measurement(args), "unit": "ms", "dtype": "f32",
+                          "data": "synthetic uniform, k = 10, levels 1-5"}))
+        return
     out = {} if args.no_plain else plain_measurement(args)
     if not args.no_learned:
         out["learned_r"] = learned_comparison(args, with_oracle=not args.no_cpu_baseline)

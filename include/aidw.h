@@ -160,6 +160,20 @@ aidw_status aidw_knn(const aidw_grid* g, const float* qx, const float* qy, int64
                      float* d1sq, int32_t* nn_idx, hipStream_t stream);
 
 /*
+ * The paper's own stop rule for the grid kNN search (Section 3.2.4 and its
+ * Remark), for measuring it: the level grows until the block of
+ * (2L + 1) x (2L + 1) cells around the query's cell holds at least k points,
+ * one more level is searched, and the k nearest points found in that block are
+ * returned in (squared distance, index) order.  This is NOT exact kNN in
+ * general: the final block only guarantees the distance to its own edge, so a
+ * nearer point just outside it can be missed (the case of the Remark's
+ * figure).  The paper pairs the rule with the cell width of Eq. 2 (build the
+ * grid with occupancy = 0.25).  Arguments, outputs and errors as aidw_knn.
+ */
+aidw_status aidw_knn_paper(const aidw_grid* g, const float* qx, const float* qy, int64_t m, int32_t k, float* r_obs,
+                           float* d1sq, int32_t* nn_idx, hipStream_t stream);
+
+/*
  * Stage 2, adaptive power and weighted interpolation (Eq. 1, 2, 4, 5, 6;
  * Section 3.3, 4.2).
  * For each query j: R = r_obs[j] / r_exp with r_exp = 1 / (2 sqrt(n / A)),
@@ -183,6 +197,30 @@ aidw_status aidw_interpolate(const float* x, const float* y, const float* z, int
                              const float* qy, int64_t m, const float* r_obs, const float* d1sq,
                              const aidw_params* p, const aidw_grid* g, float* qz, float* alpha_out,
                              hipStream_t stream);
+
+/*
+ * Baselines the paper measures its method against, for comparison runs.
+ *
+ * aidw_knn_bruteforce: the per-query kNN of the earlier GPU AIDW (Section 3.1):
+ * every query scans all n data points and keeps its k best; no grid.  Same
+ * definition and outputs as aidw_knn (x, y [n] device arrays; r_obs, d1sq,
+ * nn_idx as there), so the two agree bit for bit; the cost is O(n m).
+ * Errors: AIDW_EINVAL (pointers, n < 1, m < 0, k outside [1, min(n, AIDW_KMAX)]),
+ * AIDW_ECAPACITY (sizes beyond int32).
+ *
+ * aidw_interpolate_naive: the untiled interpolation kernel (Section 4.2): one
+ * query per thread, every thread reads each data point from global memory
+ * itself (no sharing of the loaded points across the threads of a wavefront),
+ * general alpha form only, one pass over the data.  Arguments, outputs and
+ * errors as aidw_interpolate; the sums are those of aidw_interpolate with one
+ * data range and integer powers off (aidw_set_interp_config(1, 1, 0)), bit for bit.
+ */
+aidw_status aidw_knn_bruteforce(const float* x, const float* y, int64_t n, const float* qx, const float* qy,
+                                int64_t m, int32_t k, float* r_obs, float* d1sq, int32_t* nn_idx, hipStream_t stream);
+aidw_status aidw_interpolate_naive(const float* x, const float* y, const float* z, int64_t n, const float* qx,
+                                   const float* qy, int64_t m, const float* r_obs, const float* d1sq,
+                                   const aidw_params* p, const aidw_grid* g, float* qz, float* alpha_out,
+                                   hipStream_t stream);
 
 /*
  * The whole method (Fig. 1): aidw_build_grid -> aidw_knn -> aidw_interpolate

@@ -59,6 +59,8 @@ def lib():
                                         ctypes.c_int32, ctypes.c_int32, i32p]
         L.oracle_knn.argtypes = [f32p, f32p, i64, f32p, f32p, i64, ctypes.c_int32, i32p, f64p]
         L.oracle_robs.argtypes = [f64p, i64, ctypes.c_int32, f64p]
+        L.oracle_knn_paper.argtypes = [f32p, f32p, i64, f32p, f32p, i64, ctypes.c_int32, ctypes.c_float,
+                                       ctypes.c_float, ctypes.c_float, ctypes.c_int32, ctypes.c_int32, i32p, f64p]
         L.oracle_alpha.argtypes = [f64p, i64, ctypes.c_double, ctypes.c_double, ctypes.c_double, f64p,
                                    ctypes.c_void_p, ctypes.c_void_p, f64p]
         L.oracle_idw.argtypes = [f32p, f32p, f32p, i64, f32p, f32p, i64, f64p, f64p, ctypes.c_void_p]
@@ -137,6 +139,19 @@ def knn(x, y, qx, qy, k):
     d2 = np.zeros((m, k), np.float64)
     if m:
         lib().oracle_knn(x, y, x.size, qx, qy, m, int(k), idx, d2)
+    return idx, d2
+
+
+def knn_paper(x, y, qx, qy, k, minx, miny, inv_cw, ncol, nrow):
+    """Section 3.2.4 as printed: level expansion to >= k points, one more level, k best in
+    that block -> (idx [m, k] int32, d2 [m, k] float64).  Not exact kNN in general."""
+    x, y, qx, qy = _f32(x), _f32(y), _f32(qx), _f32(qy)
+    m = qx.size
+    idx = np.zeros((m, k), np.int32)
+    d2 = np.zeros((m, k), np.float64)
+    if m:
+        lib().oracle_knn_paper(x, y, x.size, qx, qy, m, int(k), np.float32(minx), np.float32(miny),
+                               np.float32(inv_cw), int(ncol), int(nrow), idx, d2)
     return idx, d2
 
 

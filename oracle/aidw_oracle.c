@@ -20,6 +20,8 @@
  *   oracle_idw                                            pinned (coincidence, constant field, hull, symmetric closed forms, hand-derived worked examples)
  *   oracle_aidw                                           composition of the above
  *   oracle_features                                       pinned (counts of a constructed grid, window clipping, offsets)
+ *   oracle_knn_paper                                      pinned (a constructed miss of the "+1 level" rule, single-cell
+ *                                                         grid = brute force, block and distance invariants)
  */
 #include <math.h>
 #include <stdint.h>
@@ -180,6 +182,69 @@ void oracle_knn(const float* x, const float* y, int64_t n, const float* qx, cons
       bi[s] = (int32_t)i;
     }
   }
+}
+
+/*
+ * The paper's grid kNN search as printed (Section 3.2.4 and its Remark; Fig. 3, 4):
+ * the "level" L block is the (2L + 1) x (2L + 1) cells centred on the query's cell
+ * (clipped to the grid).  Starting at L = 0 the level grows until the block holds
+ * at least k data points (the worked example expands at 14 < 15, read as count >= k
+ * to stop); the search then takes one more level, and the k nearest data points
+ * among those in that final block, ordered by (squared distance, index), are the
+ * result.  Binning as oracle_cell_index.  This is NOT exact kNN in general: the
+ * final block only guarantees the distance to its own edge (the failure class the
+ * Remark's Fig. 4 illustrates); it is kept to measure that rule.
+ * Outputs as oracle_knn (m x k, ascending); idx = INT32_MAX / d2 = +inf if fewer than k.
+ */
+void oracle_knn_paper(const float* x, const float* y, int64_t n, const float* qx, const float* qy, int64_t m,
+                      int32_t k, float minX, float minY, float inv_cw, int32_t ncol, int32_t nrow, int32_t* idx,
+                      double* d2) {
+  int32_t* cell = (int32_t*)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+  int32_t* qcell = (int32_t*)malloc(sizeof(int32_t) * (size_t)(m > 0 ? m : 1));
+  if (!cell || !qcell) {
+    free(cell);
+    free(qcell);
+    return;
+  }
+  oracle_cell_index(x, y, n, minX, minY, inv_cw, ncol, nrow, cell);
+  oracle_cell_index(qx, qy, m, minX, minY, inv_cw, ncol, nrow, qcell);
+  const int32_t maxlev = ncol > nrow ? ncol : nrow;
+#pragma omp parallel for schedule(dynamic, 4)
+  for (int64_t j = 0; j < m; ++j) {
+    const int32_t c0 = qcell[j] % ncol, r0 = qcell[j] / ncol;
+    int32_t L = 0;
+    for (;; ++L) {  /* smallest level whose block holds >= k points (the whole grid always does) */
+      int64_t count = 0;
+      for (int64_t i = 0; i < n; ++i) {
+        const int32_t c = cell[i] % ncol, r = cell[i] / ncol;
+        if (abs(c - c0) <= L && abs(r - r0) <= L) ++count;
+      }
+      if (count >= k || L >= maxlev) break;
+    }
+    const int32_t Lf = L + 1; /* the Remark: one more level */
+    double* bd = d2 + j * (int64_t)k;
+    int32_t* bi = idx + j * (int64_t)k;
+    for (int32_t s = 0; s < k; ++s) {
+      bd[s] = INFINITY;
+      bi[s] = INT32_MAX;
+    }
+    for (int64_t i = 0; i < n; ++i) {
+      const int32_t c = cell[i] % ncol, r = cell[i] / ncol;
+      if (abs(c - c0) > Lf || abs(r - r0) > Lf) continue;
+      const double d = dist2(x[i], y[i], qx[j], qy[j]);
+      if (!key_less(d, (int32_t)i, bd[k - 1], bi[k - 1])) continue;
+      int32_t s = k - 1;
+      while (s > 0 && key_less(d, (int32_t)i, bd[s - 1], bi[s - 1])) {
+        bd[s] = bd[s - 1];
+        bi[s] = bi[s - 1];
+        --s;
+      }
+      bd[s] = d;
+      bi[s] = (int32_t)i;
+    }
+  }
+  free(cell);
+  free(qcell);
 }
 
 /* Eq. 3: r_obs = (1/k) * sum of the k nearest-neighbour distances (summed in ascending order). */

@@ -136,6 +136,10 @@ def load(build_if_missing: bool = True):
     L.aidw_grid_destroy.argtypes = [_VP]
     L.aidw_grid_destroy.restype = None
     L.aidw_knn.argtypes = [_VP, _VP, _VP, i64, i32, _VP, _VP, _VP, _VP]
+    L.aidw_knn_paper.argtypes = [_VP, _VP, _VP, i64, i32, _VP, _VP, _VP, _VP]
+    L.aidw_knn_bruteforce.argtypes = [_VP, _VP, i64, _VP, _VP, i64, i32, _VP, _VP, _VP, _VP]
+    L.aidw_interpolate_naive.argtypes = [_VP, _VP, _VP, i64, _VP, _VP, i64, _VP, _VP, P(_Params), _VP, _VP, _VP,
+                                         _VP]
     L.aidw_interpolate.argtypes = [_VP, _VP, _VP, i64, _VP, _VP, i64, _VP, _VP, P(_Params), _VP, _VP, _VP, _VP]
     L.aidw_run.argtypes = [_VP, _VP, _VP, i64, _VP, _VP, i64, P(_Params), _VP, _VP, _VP, _VP]
     L.aidw_set_timing.argtypes = [ctypes.c_int]
@@ -175,7 +179,8 @@ def load(build_if_missing: bool = True):
     L.aidw_run_batch.argtypes = [P(_Job), i32, P(_BatchConfig), P(i32), _VP]
     L.aidw_batch_tune.argtypes = [P(_Job), i32, P(_BatchConfig), i32, i32, P(ctypes.c_float), _VP]
     for name in ("aidw_build_grid", "aidw_grid_describe", "aidw_grid_arrays", "aidw_grid_copy_arrays", "aidw_knn",
-                 "aidw_interpolate", "aidw_run", "aidw_set_timing", "aidw_last_timing", "aidw_set_interp_config",
+                 "aidw_interpolate", "aidw_run", "aidw_knn_paper", "aidw_knn_bruteforce", "aidw_interpolate_naive",
+                 "aidw_set_timing", "aidw_last_timing", "aidw_set_interp_config",
                  "aidw_mlp_create", "aidw_mlp_set_params", "aidw_mlp_get_params", "aidw_mlp_save", "aidw_mlp_load",
                  "aidw_features", "aidw_mlp_forward", "aidw_mlp_gradients", "aidw_mlp_train", "aidw_run_learned",
                  "aidw_batch_create", "aidw_batch_run", "aidw_batch_job_status", "aidw_batch_describe",
@@ -266,32 +271,47 @@ def build_grid(x, y, qx=None, qy=None, params: Params | None = None, stream=None
     return Grid(h.value, x.numel())
 
 
-def knn(grid: Grid, qx, qy, k: int, want_d1sq=True, want_idx=False, stream=None):
-    """aidw_knn -> (r_obs [m], d1sq [m] or None, nn_idx [m, k] or None)."""
+def knn(grid: Grid, qx, qy, k: int, want_d1sq=True, want_idx=False, stream=None, paper_rule=False):
+    """aidw_knn (or aidw_knn_paper, the paper's "+1 level" stop rule, when paper_rule)
+    -> (r_obs [m], d1sq [m] or None, nn_idx [m, k] or None)."""
     import torch
     m = qx.numel()
     r = torch.empty(m, dtype=torch.float32, device=qx.device)
     d1 = torch.empty(m, dtype=torch.float32, device=qx.device) if want_d1sq else None
     ix = torch.empty((m, k), dtype=torch.int32, device=qx.device) if want_idx else None
-    _check(load().aidw_knn(grid.handle, _dev(qx, "qx"), _dev(qy, "qy"), m, int(k), r.data_ptr(),
-                           None if d1 is None else d1.data_ptr(), None if ix is None else ix.data_ptr(),
-                           _stream(stream)))
+    fn = load().aidw_knn_paper if paper_rule else load().aidw_knn
+    _check(fn(grid.handle, _dev(qx, "qx"), _dev(qy, "qy"), m, int(k), r.data_ptr(),
+              None if d1 is None else d1.data_ptr(), None if ix is None else ix.data_ptr(), _stream(stream)))
     return r, d1, ix
 
 
 def interpolate(x, y, z, qx, qy, r_obs, d1sq, params: Params | None = None, grid: Grid | None = None,
-                want_alpha=False, stream=None):
-    """aidw_interpolate -> qz [m] (and alpha [m] if requested)."""
+                want_alpha=False, stream=None, naive=False):
+    """aidw_interpolate (aidw_interpolate_naive, the untiled baseline, when naive)
+    -> qz [m] (and alpha [m] if requested)."""
     import torch
     p = (params or Params())._c()
     m = qx.numel()
     qz = torch.empty(m, dtype=torch.float32, device=qx.device)
     al = torch.empty(m, dtype=torch.float32, device=qx.device) if want_alpha else None
-    _check(load().aidw_interpolate(_dev(x, "x"), _dev(y, "y"), _dev(z, "z"), x.numel(), _dev(qx, "qx"),
-                                   _dev(qy, "qy"), m, _dev(r_obs, "r_obs"), _dev(d1sq, "d1sq"), ctypes.byref(p),
-                                   None if grid is None else grid.handle, qz.data_ptr(),
-                                   None if al is None else al.data_ptr(), _stream(stream)))
+    fn = load().aidw_interpolate_naive if naive else load().aidw_interpolate
+    _check(fn(_dev(x, "x"), _dev(y, "y"), _dev(z, "z"), x.numel(), _dev(qx, "qx"), _dev(qy, "qy"), m,
+              _dev(r_obs, "r_obs"), _dev(d1sq, "d1sq"), ctypes.byref(p), None if grid is None else grid.handle,
+              qz.data_ptr(), None if al is None else al.data_ptr(), _stream(stream)))
     return (qz, al) if want_alpha else qz
+
+
+def knn_bruteforce(x, y, qx, qy, k: int, want_d1sq=True, want_idx=False, stream=None):
+    """aidw_knn_bruteforce (no grid, O(n m)) -> (r_obs [m], d1sq [m] or None, nn_idx [m, k] or None)."""
+    import torch
+    m = qx.numel()
+    r = torch.empty(m, dtype=torch.float32, device=qx.device)
+    d1 = torch.empty(m, dtype=torch.float32, device=qx.device) if want_d1sq else None
+    ix = torch.empty((m, k), dtype=torch.int32, device=qx.device) if want_idx else None
+    _check(load().aidw_knn_bruteforce(_dev(x, "x"), _dev(y, "y"), x.numel(), _dev(qx, "qx"), _dev(qy, "qy"), m,
+                                      int(k), r.data_ptr(), None if d1 is None else d1.data_ptr(),
+                                      None if ix is None else ix.data_ptr(), _stream(stream)))
+    return r, d1, ix
 
 
 def run(x, y, z, qx, qy, params: Params | None = None, want_alpha=False, want_robs=False, out=None, stream=None):

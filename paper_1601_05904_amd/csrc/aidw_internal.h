@@ -93,6 +93,18 @@ hipError_t launch_knn(const GridScalars* gs, const int32_t* cell_start, const fl
                       const int32_t* sidx, const float* qx, const float* qy, const uint32_t* qperm,
                       const uint32_t* active, int m, int k, double slack_cells, float* r_obs, float* d1sq,
                       int32_t* nn_idx, hipStream_t s);
+// Brute-force kNN over all n points per query (the method the grid search replaces); exact.
+hipError_t launch_knn_brute(const float* x, const float* y, int n, const float* qx, const float* qy, int m, int k,
+                            float* r_obs, float* d1sq, int32_t* nn_idx, hipStream_t s);
+// The paper's stop rule (one more level after the block holds >= k points; not exact in general).
+hipError_t launch_knn_paper(const GridScalars* gs, const int32_t* cell_start, const float* sx, const float* sy,
+                            const int32_t* sidx, const float* qx, const float* qy, const uint32_t* qperm, int m, int k,
+                            float* r_obs, float* d1sq, int32_t* nn_idx, hipStream_t s);
+// The same with four lanes per query (for small or sparse query sets); identical results.
+hipError_t launch_knn4(const GridScalars* gs, const int32_t* cell_start, const float* sx, const float* sy,
+                       const int32_t* sidx, const float* qx, const float* qy, const uint32_t* qperm,
+                       const uint32_t* active, int m, int k, double slack_cells, float* r_obs, float* d1sq,
+                       int32_t* nn_idx, hipStream_t s);
 
 struct AlphaParams {
   double r_exp;
@@ -110,6 +122,9 @@ hipError_t launch_alpha_class(const float* r_obs, int m, const AlphaParams& ap, 
 hipError_t launch_interp(const float* x, const float* y, const float* z, int n, const float* qx, const float* qy,
                          const float* alpha_f, const float* d1sq, const uint32_t* perm, const uint32_t* skeys, int m,
                          uint32_t fast_mask, int q, int split, float* qz, double2* partial, hipStream_t s);
+// The untiled pair kernel (per-lane global loads, general alpha form, one data range).
+hipError_t launch_interp_naive(const float* x, const float* y, const float* z, int n, const float* qx, const float* qy,
+                               const float* alpha_f, const float* d1sq, int m, float* qz, hipStream_t s);
 // Zero-padded copies of x, y, z for the pair kernels, which may prefetch one chunk past n.
 int interp_padded_len(int n);
 hipError_t launch_pad_copy(const float* x, const float* y, const float* z, int n, float* xp, float* yp, float* zp,
@@ -134,6 +149,14 @@ struct MlpDevice {
   uint32_t* w3p;   // [32]
   float* w2r;      // [64][64] float32 of the bf16-rounded W2
   float* w3r;      // [64]
+  // MFMA operands of the inference kernels (16-byte aligned): per lane of a wavefront
+  // 8 bf16 of W1 per 16-row tile and of W2 per (tile, k-step); float32 b1, b2 and the
+  // bf16-rounded W3 as float32.
+  uint32_t* w1a;   // [4][64 lanes][4]
+  uint32_t* w2a;   // [4][2][64 lanes][4]
+  float* b1f;      // [64]
+  float* b2f;      // [64]
+  float* w3f;      // [64]
 };
 
 // perm (may be null): lane t handles query perm[t] and writes its outputs at position t.
@@ -142,6 +165,13 @@ hipError_t launch_features(const GridScalars* gs, const int32_t* cell_start, con
                            double slack_cells, float* feat, float* d1sq, hipStream_t s);
 hipError_t launch_mlp_repack(const MlpDevice& d, hipStream_t s);
 hipError_t launch_mlp_forward(const MlpDevice& d, const float* feat, int m, float* out, hipStream_t s);
+// Fused inference front of the learned run, per position t of the order perm (may be null):
+// features, the network (MFMA) and the fallback decision of launch_decide in one kernel.
+hipError_t launch_learned_front(const MlpDevice& d, const GridScalars* gs, const int32_t* cell_start, const float* sx,
+                                const float* sy, const float* qx, const float* qy, const uint32_t* perm, int m,
+                                double inv_occ, double slack_cells, const AlphaParams& ap, int rule, double delta,
+                                double r_sat_lo, double r_sat_hi, uint32_t* flag, float* alpha_f, float* d1sq,
+                                float* r_hat_out, hipStream_t s);
 size_t mlp_batch_scratch_floats(int B);
 // grad [AIDW_MLP_PARAMS + 1]: the batch gradient, then the batch's mean squared error.
 hipError_t launch_mlp_gradients(const MlpDevice& d, const float* feat, const float* target, const uint32_t* sel, int B,

@@ -202,7 +202,7 @@ aidw_status check_data(const float* x, const float* y, int64_t n, const float* q
 }
 
 aidw_status knn_impl(const aidw_grid* g, const float* qx, const float* qy, int64_t m, int32_t k, float* r_obs,
-                     float* d1sq, int32_t* nn_idx, hipStream_t s) {
+                     float* d1sq, int32_t* nn_idx, hipStream_t s, bool paper_rule = false) {
   Temps t(s);
   uint32_t *keys, *vals, *tk, *tv, *hist, *scan;
   hipError_t e;
@@ -213,8 +213,16 @@ aidw_status knn_impl(const aidw_grid* g, const float* qx, const float* qy, int64
   // bin the queries with the data's cell formula, then sort them by cell
   HIP_TRY(launch_cell_keys(qx, qy, (int)m, g->dev, keys, vals, s), "query key kernel");
   HIP_TRY(radix_sort_pairs(keys, vals, tk, tv, (int)m, bits_for(g->host.ncells), hist, scan, s), "query sort");
-  HIP_TRY(launch_knn(g->dev, g->cell_start, g->sx, g->sy, g->sidx, qx, qy, vals, nullptr, (int)m, k, slack_cells(g->host), r_obs,
-                     d1sq, nn_idx, s),
+  if (paper_rule) {
+    HIP_TRY(launch_knn_paper(g->dev, g->cell_start, g->sx, g->sy, g->sidx, qx, qy, vals, (int)m, k, r_obs, d1sq,
+                             nn_idx, s),
+            "kNN kernel (paper rule)");
+    return AIDW_OK;
+  }
+  // below 2^17 queries one lane per query leaves the chip idle: four lanes share each query
+  auto knn = m < (1 << 17) ? launch_knn4 : launch_knn;
+  HIP_TRY(knn(g->dev, g->cell_start, g->sx, g->sy, g->sidx, qx, qy, vals, nullptr, (int)m, k, slack_cells(g->host), r_obs,
+              d1sq, nn_idx, s),
           "kNN kernel");
   return AIDW_OK;
 }
@@ -241,7 +249,7 @@ void choose_interp_config(int64_t n, int64_t m, int* q, int* split) {
 aidw_status interp_impl(const float* x, const float* y, const float* z, int64_t n, const float* qx, const float* qy,
                         int64_t m, const float* r_obs, const float* d1sq, const aidw_params* p, const aidw_grid* g,
                         float* qz, float* alpha_out, hipStream_t s, hipEvent_t ev_begin, hipEvent_t ev_end,
-                        int* used_q, int* used_split, const float* alpha_in = nullptr) {
+                        int* used_q, int* used_split, const float* alpha_in = nullptr, bool naive = false) {
   double area = p->area > 0 ? p->area : (g ? g->host.area : 0.0);
   if (!(area > 0)) return fail(AIDW_EINVAL, "aidw_interpolate needs params.area > 0 or a grid");
   AlphaParams ap;
@@ -274,7 +282,7 @@ aidw_status interp_impl(const float* x, const float* y, const float* z, int64_t 
       (e = t.get(&scan, radix_scan_tmp_words((int)m))) != hipSuccess || (e = t.get(&xp, npad)) != hipSuccess ||
       (e = t.get(&yp, npad)) != hipSuccess || (e = t.get(&zp, npad)) != hipSuccess)
     return hip_fail(e, "allocating interpolation buffers");
-  HIP_TRY(launch_pad_copy(x, y, z, (int)n, xp, yp, zp, s), "padding copy");
+  if (!naive) HIP_TRY(launch_pad_copy(x, y, z, (int)n, xp, yp, zp, s), "padding copy");
   HIP_TRY(hipMemsetAsync(count, 0, sizeof(uint32_t), s), "clearing coincidence count");
   HIP_TRY(launch_coincident_list(d1sq, (int)m, count, list, s), "coincidence list kernel");
   if (alpha_in) {  // alpha given per query: only the class keys are needed
@@ -285,12 +293,17 @@ aidw_status interp_impl(const float* x, const float* y, const float* z, int64_t 
   } else {
     HIP_TRY(launch_alpha_class(r_obs, (int)m, ap, alpha_f, alpha_out, keys, perm, s), "alpha kernel");
   }
-  if (fast_mask) HIP_TRY(radix_sort_pairs(keys, perm, tk, tv, (int)m, 4, hist, scan, s), "class sort");
+  if (fast_mask && !naive) HIP_TRY(radix_sort_pairs(keys, perm, tk, tv, (int)m, 4, hist, scan, s), "class sort");
   if (ev_begin) HIP_TRY(hipEventRecord(ev_begin, s), "event");
-  HIP_TRY(launch_interp(xp, yp, zp, (int)n, qx, qy, alpha_f, d1sq, perm, keys, (int)m, fast_mask, q, split, qz, partial, s),
-          "interpolation kernel");
+  if (naive) {
+    HIP_TRY(launch_interp_naive(x, y, z, (int)n, qx, qy, alpha_f, d1sq, (int)m, qz, s), "interpolation kernel (untiled)");
+  } else {
+    HIP_TRY(launch_interp(xp, yp, zp, (int)n, qx, qy, alpha_f, d1sq, perm, keys, (int)m, fast_mask, q, split, qz,
+                          partial, s),
+            "interpolation kernel");
+  }
   if (ev_end) HIP_TRY(hipEventRecord(ev_end, s), "event");
-  if (split > 1) HIP_TRY(launch_combine(partial, (int)m, split, qz, s), "combine kernel");
+  if (split > 1 && !naive) HIP_TRY(launch_combine(partial, (int)m, split, qz, s), "combine kernel");
   if (g && g->n == n)
     HIP_TRY(launch_fixup_grid(count, list, qx, qy, g->dev, g->cell_start, g->sx, g->sy, g->sidx, z, qz, s),
             "coincidence fix-up kernel");
@@ -315,7 +328,9 @@ constexpr int kP = AIDW_MLP_PARAMS;
 // Float offsets of the network's arrays inside its single device allocation.
 struct MlpLayout {
   static constexpr size_t master = 0, mom = kP, vel = 2 * kP, w1p = 3 * kP, w2p = w1p + 64 * 14, w3p = w2p + 64 * 32,
-                          w2r = w3p + 32, w3r = w2r + 64 * 64, total = w3r + 64;
+                          w2r = w3p + 32, w3r = w2r + 64 * 64,
+                          w1a = (w3r + 64 + 63) / 64 * 64, w2a = w1a + 4 * 64 * 4, b1f = w2a + 8 * 64 * 4,
+                          b2f = b1f + 64, w3f = b2f + 64, total = w3f + 64;
 };
 
 aidw_status mlp_alloc(aidw_mlp** out) {
@@ -334,6 +349,11 @@ aidw_status mlp_alloc(aidw_mlp** out) {
   h->d.w3p = reinterpret_cast<uint32_t*>(b + MlpLayout::w3p);
   h->d.w2r = b + MlpLayout::w2r;
   h->d.w3r = b + MlpLayout::w3r;
+  h->d.w1a = reinterpret_cast<uint32_t*>(b + MlpLayout::w1a);
+  h->d.w2a = reinterpret_cast<uint32_t*>(b + MlpLayout::w2a);
+  h->d.b1f = b + MlpLayout::b1f;
+  h->d.b2f = b + MlpLayout::b2f;
+  h->d.w3f = b + MlpLayout::w3f;
   *out = h;
   return AIDW_OK;
 }
@@ -455,6 +475,20 @@ aidw_status aidw_knn(const aidw_grid* g, const float* qx, const float* qy, int64
   return knn_impl(g, qx, qy, m, k, r_obs, d1sq, nn_idx, stream);
 }
 
+aidw_status aidw_knn_paper(const aidw_grid* g, const float* qx, const float* qy, int64_t m, int32_t k, float* r_obs,
+                           float* d1sq, int32_t* nn_idx, hipStream_t stream) {
+  g_detail.clear();
+  if (!g) return fail(AIDW_EINVAL, "grid is NULL");
+  if (m < 0) return fail(AIDW_EINVAL, "m = %lld < 0", (long long)m);
+  if (m > INT32_MAX) return fail(AIDW_ECAPACITY, "m exceeds INT32_MAX");
+  if (k < 1 || k > AIDW_KMAX || k > g->n)
+    return fail(AIDW_EINVAL, "k = %d must be in [1, min(n = %lld, %d)]", k, (long long)g->n, AIDW_KMAX);
+  if (m == 0) return AIDW_OK;
+  if (!qx || !qy || !r_obs) return fail(AIDW_EINVAL, "qx / qy / r_obs is NULL");
+  if ((int64_t)m * k > INT32_MAX && nn_idx) return fail(AIDW_ECAPACITY, "m * k exceeds INT32_MAX");
+  return knn_impl(g, qx, qy, m, k, r_obs, d1sq, nn_idx, stream, true);
+}
+
 aidw_status aidw_interpolate(const float* x, const float* y, const float* z, int64_t n, const float* qx,
                              const float* qy, int64_t m, const float* r_obs, const float* d1sq, const aidw_params* p,
                              const aidw_grid* g, float* qz, float* alpha_out, hipStream_t stream) {
@@ -467,6 +501,37 @@ aidw_status aidw_interpolate(const float* x, const float* y, const float* z, int
   if (!r_obs || !d1sq || !qz) return fail(AIDW_EINVAL, "r_obs / d1sq / qz is NULL");
   return interp_impl(x, y, z, n, qx, qy, m, r_obs, d1sq, p, g, qz, alpha_out, stream, nullptr, nullptr, nullptr,
                      nullptr);
+}
+
+aidw_status aidw_interpolate_naive(const float* x, const float* y, const float* z, int64_t n, const float* qx,
+                                   const float* qy, int64_t m, const float* r_obs, const float* d1sq,
+                                   const aidw_params* p, const aidw_grid* g, float* qz, float* alpha_out,
+                                   hipStream_t stream) {
+  g_detail.clear();
+  aidw_status st = check_data(x, y, n, qx, qy, m);
+  if (st != AIDW_OK) return st;
+  if (!z) return fail(AIDW_EINVAL, "z is NULL");
+  if ((st = check_params(p)) != AIDW_OK) return st;
+  if (m == 0) return AIDW_OK;
+  if (!r_obs || !d1sq || !qz) return fail(AIDW_EINVAL, "r_obs / d1sq / qz is NULL");
+  return interp_impl(x, y, z, n, qx, qy, m, r_obs, d1sq, p, g, qz, alpha_out, stream, nullptr, nullptr, nullptr,
+                     nullptr, nullptr, true);
+}
+
+aidw_status aidw_knn_bruteforce(const float* x, const float* y, int64_t n, const float* qx, const float* qy,
+                                int64_t m, int32_t k, float* r_obs, float* d1sq, int32_t* nn_idx, hipStream_t stream) {
+  g_detail.clear();
+  if (!x || !y) return fail(AIDW_EINVAL, "x / y is NULL");
+  if (n < 1 || m < 0) return fail(AIDW_EINVAL, "need n >= 1 and m >= 0 (n = %lld, m = %lld)", (long long)n,
+                                  (long long)m);
+  if (n > INT32_MAX || m > INT32_MAX) return fail(AIDW_ECAPACITY, "sizes exceed INT32_MAX");
+  if (k < 1 || k > AIDW_KMAX || k > n)
+    return fail(AIDW_EINVAL, "k = %d must be in [1, min(n = %lld, %d)]", k, (long long)n, AIDW_KMAX);
+  if (m == 0) return AIDW_OK;
+  if (!qx || !qy || !r_obs) return fail(AIDW_EINVAL, "qx / qy / r_obs is NULL");
+  if ((int64_t)m * k > INT32_MAX && nn_idx) return fail(AIDW_ECAPACITY, "m * k exceeds INT32_MAX");
+  HIP_TRY(launch_knn_brute(x, y, (int)n, qx, qy, (int)m, k, r_obs, d1sq, nn_idx, stream), "brute-force kNN kernel");
+  return AIDW_OK;
 }
 
 aidw_status aidw_run(const float* x, const float* y, const float* z, int64_t n, const float* qx, const float* qy,
@@ -733,17 +798,15 @@ aidw_status aidw_run_learned(const float* x, const float* y, const float* z, int
     Temps t(stream);
     hipError_t e = hipSuccess;
     if (ev) e = hipEventRecord(ev[1], stream);
-    // Queries are processed in cell order (as the kNN kernel takes them): features, network and
-    // the decision per position of that order; the fallback list is the flagged positions,
-    // compacted in order by a prefix sum, so the kNN kernel sees them binned as well.
-    float *feat = nullptr, *d1pos = nullptr, *d1sq = nullptr, *r_hat = nullptr, *alpha_f = nullptr, *r_obs = nullptr;
+    // Queries are processed in cell order (as the kNN kernel takes them): one kernel computes
+    // the features, the network (on the matrix cores) and the decision per position of that
+    // order; the fallback list is the flagged positions, compacted in order by a prefix sum,
+    // so the kNN kernel sees them binned as well.
+    float *d1sq = nullptr, *alpha_f = nullptr, *r_obs = nullptr;
     uint32_t *keys = nullptr, *perm = nullptr, *tk = nullptr, *tv = nullptr, *hist = nullptr, *scan = nullptr,
              *flag = nullptr, *idx = nullptr, *list = nullptr, *stmp = nullptr, *count = nullptr;
     const int mm = (int)m;
-    if (e == hipSuccess) e = t.get(&feat, (size_t)mm * AIDW_MLP_INPUTS);
-    if (e == hipSuccess) e = t.get(&d1pos, mm);
     if (e == hipSuccess) e = t.get(&d1sq, mm);
-    if (e == hipSuccess) e = t.get(&r_hat, mm);
     if (e == hipSuccess) e = t.get(&alpha_f, mm);
     if (e == hipSuccess) e = t.get(&r_obs, mm);
     if (e == hipSuccess) e = t.get(&keys, mm);
@@ -771,16 +834,13 @@ aidw_status aidw_run_learned(const float* x, const float* y, const float* z, int
   if (st == AIDW_OK && (e = (expr)) != hipSuccess) st = hip_fail(e, what)
     STEP(launch_cell_keys(qx, qy, mm, g->dev, keys, perm, stream), "query key kernel");
     STEP(radix_sort_pairs(keys, perm, tk, tv, mm, bits_for(g->host.ncells), hist, scan, stream), "query sort");
-    STEP(launch_features(g->dev, g->cell_start, g->sx, g->sy, qx, qy, perm, mm, inv_occ, slack_cells(g->host), feat,
-                         d1pos, stream),
-         "feature kernel");
-    STEP(launch_mlp_forward(mlp->d, feat, mm, r_hat, stream), "network forward kernel");
-    STEP(launch_decide(r_hat, d1pos, perm, mm, ap, rule, delta, r_sat_lo, r_sat_hi, flag, alpha_f, d1sq, r_hat_out,
-                       stream),
-         "decision kernel");
+    STEP(launch_learned_front(mlp->d, g->dev, g->cell_start, g->sx, g->sy, qx, qy, perm, mm, inv_occ,
+                              slack_cells(g->host), ap, rule, delta, r_sat_lo, r_sat_hi, flag, alpha_f, d1sq, r_hat_out,
+                              stream),
+         "features / network / decision kernel");
     STEP(exclusive_scan_u32(flag, idx, mm, stmp, count, stream), "fallback scan");
     STEP(launch_compact(flag, idx, perm, mm, list, stream), "fallback compaction");
-    STEP(launch_knn(g->dev, g->cell_start, g->sx, g->sy, g->sidx, qx, qy, list, count, mm, p->k, slack_cells(g->host),
+    STEP(launch_knn4(g->dev, g->cell_start, g->sx, g->sy, g->sidx, qx, qy, list, count, mm, p->k, slack_cells(g->host),
                     r_obs, d1sq, nullptr, stream),
          "kNN kernel");
     STEP(launch_alpha_fallback(list, count, mm, r_obs, ap, alpha_f, stream), "alpha kernel");

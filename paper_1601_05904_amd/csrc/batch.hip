@@ -204,17 +204,19 @@ __global__ __launch_bounds__(256) void k_b_query_keys(const BatchJob* __restrict
   vals[q] = (uint32_t)q;
 }
 
-// kNN + Eq. 3 for every query, lanes in binned order; each lane searches its own job's grid.
+// kNN + Eq. 3 for the queries at binned positions [t_begin, t_end); each lane searches its
+// own job's grid.  The jobs are ordered by the length of their register k-list, so each
+// length class is one range of positions and one launch.
 template <int KMAX>
 __global__ __launch_bounds__(256) void k_b_knn(const BatchJob* __restrict__ jobs, const int32_t* __restrict__ qoff,
-                                               int njobs, int sum_m, const GridScalars* __restrict__ gs,
+                                               int njobs, int t_begin, int t_end, const GridScalars* __restrict__ gs,
                                                const int32_t* __restrict__ cell_start, const float* __restrict__ sx,
                                                const float* __restrict__ sy, const int32_t* __restrict__ sidx,
                                                const float* __restrict__ cqx, const float* __restrict__ cqy,
                                                const uint32_t* __restrict__ qperm, float* __restrict__ r_obs,
                                                float* __restrict__ d1sq) {
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= sum_m) return;
+  const int t = t_begin + (int)(blockIdx.x * blockDim.x + threadIdx.x);
+  if (t >= t_end) return;
   const int q = (int)qperm[t];
   const int j = find_seg(qoff, njobs, q);
   const GridScalars& G = gs[j];
@@ -395,6 +397,11 @@ using namespace aidw;
 
 struct aidw_batch {
   int njobs = 0;
+  std::vector<int32_t> caller;  // internal job -> the caller's job index
+  struct KnnRange {
+    int kmax, t_begin, t_end;
+  };
+  std::vector<KnnRange> knn_ranges;
   aidw_batch_config cfg{};
   int kmax = 16;
   uint32_t fast_mask = 0;
@@ -485,6 +492,7 @@ aidw_status create_plan(const aidw_job* jobs, int32_t njobs, const aidw_batch_co
   uint32_t mask = 0;  // union of the jobs' integer levels
   double pairs = 0.0;
   const int qb = pair::kThreads * cfg.q;
+  auto kclass = [](int k) { return k <= 8 ? 8 : k <= 16 ? 16 : k <= 32 ? 32 : 64; };
   for (int j = 0; j < njobs; ++j) {
     const aidw_job& a = jobs[j];
     if (a.n < 1) return fail(AIDW_EINVAL, "job %d: n must be >= 1", j);
@@ -496,6 +504,16 @@ aidw_status create_plan(const aidw_job* jobs, int32_t njobs, const aidw_batch_co
     const int k = a.params.k;
     if (k < 1 || k > AIDW_KMAX || k > a.n)
       return fail(AIDW_EINVAL, "job %d: k = %d must be in [1, min(n, %d)]", j, k, AIDW_KMAX);
+  }
+  // internal order: by k-list class (stable), so that each class is one range of queries
+  std::vector<int32_t> order(njobs);
+  for (int j = 0; j < njobs; ++j) order[j] = j;
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int32_t a, int32_t b) { return kclass(jobs[a].params.k) < kclass(jobs[b].params.k); });
+  for (int jj = 0; jj < njobs; ++jj) {
+    const int j = jj;  // internal index
+    const aidw_job& a = jobs[order[jj]];
+    const int k = a.params.k;
     kmax = std::max(kmax, k);
     uint32_t jm = 0;
     for (int l = 0; l < 5; ++l) {
@@ -546,7 +564,7 @@ aidw_status create_plan(const aidw_job* jobs, int32_t njobs, const aidw_batch_co
     spart += (int64_t)J.splits * a.m;
     pairs += (double)a.n * (double)a.m;
     if (snp >= INT32_MAX / 2 || sm >= INT32_MAX / 2 || scap >= INT32_MAX / 2 || sb >= INT32_MAX / 2)
-      return fail(AIDW_ECAPACITY, "batch totals exceed int32 (at job %d)", j);
+      return fail(AIDW_ECAPACITY, "batch totals exceed int32 (at job %d)", order[jj]);
   }
   doff[njobs] = (int32_t)snp;
   noff[njobs] = (int32_t)sn;
@@ -569,16 +587,23 @@ aidw_status create_plan(const aidw_job* jobs, int32_t njobs, const aidw_batch_co
     }
   }
   if (items.size() >= (size_t)INT32_MAX) return fail(AIDW_ECAPACITY, "too many work items");
-  std::vector<int32_t> order(items.size());
-  for (size_t i = 0; i < order.size(); ++i) order[i] = (int32_t)i;
-  std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return cost[a] > cost[b]; });
+  std::vector<int32_t> by_cost(items.size());
+  for (size_t i = 0; i < by_cost.size(); ++i) by_cost[i] = (int32_t)i;
+  std::stable_sort(by_cost.begin(), by_cost.end(), [&](int32_t a, int32_t b) { return cost[a] > cost[b]; });
   std::vector<WorkItem> sorted(items.size());
-  for (size_t i = 0; i < order.size(); ++i) sorted[i] = items[order[i]];
+  for (size_t i = 0; i < by_cost.size(); ++i) sorted[i] = items[by_cost[i]];
 
   aidw_batch* b = new aidw_batch();
   b->njobs = njobs;
   b->cfg = cfg;
-  b->kmax = kmax <= 8 ? 8 : kmax <= 16 ? 16 : kmax <= 32 ? 32 : 64;
+  b->kmax = kclass(kmax);
+  b->caller = order;
+  for (int jj = 0; jj < njobs;) {  // one kNN launch per k-list class: a contiguous range of jobs
+    int je = jj;
+    while (je < njobs && hj[je].k <= b->kmax && kclass(hj[je].k) == kclass(hj[jj].k)) ++je;
+    if (qoff[je] > qoff[jj]) b->knn_ranges.push_back({kclass(hj[jj].k), qoff[jj], qoff[je]});
+    jj = je;
+  }
   b->fast_mask = mask;
   b->sum_n = (int)sn;
   b->sum_npad = (int)snp;
@@ -673,9 +698,9 @@ aidw_status create_plan(const aidw_job* jobs, int32_t njobs, const aidw_batch_co
   } while (0)
 
 template <int KMAX>
-void launch_b_knn(const aidw_batch* b, hipStream_t s) {
-  hipLaunchKernelGGL(k_b_knn<KMAX>, dim3(div_up(b->sum_m, 256)), dim3(256), 0, s, b->jobs, b->qoff, b->njobs,
-                     b->sum_m, b->gs, b->cell_start, b->sx, b->sy, b->sidx, b->cqx, b->cqy, b->qperm, b->r_obs,
+void launch_b_knn(const aidw_batch* b, int t_begin, int t_end, hipStream_t s) {
+  hipLaunchKernelGGL(k_b_knn<KMAX>, dim3(div_up(t_end - t_begin, 256)), dim3(256), 0, s, b->jobs, b->qoff, b->njobs,
+                     t_begin, t_end, b->gs, b->cell_start, b->sx, b->sy, b->sidx, b->cqx, b->cqy, b->qperm, b->r_obs,
                      b->d1sq);
 }
 
@@ -714,11 +739,13 @@ aidw_status enqueue(aidw_batch* b, hipStream_t s, bool timed) {
                        b->cqy, b->qkeys, b->qperm);
     STEP(radix_sort_pairs(b->qkeys, b->qperm, b->tkeys, b->tvals, b->sum_m, b->cell_bits, b->hist, b->scan_tmp, s),
          "binning the queries");
-    switch (b->kmax) {
-      case 8: launch_b_knn<8>(b, s); break;
-      case 16: launch_b_knn<16>(b, s); break;
-      case 32: launch_b_knn<32>(b, s); break;
-      default: launch_b_knn<64>(b, s); break;
+    for (const auto& r : b->knn_ranges) {
+      switch (r.kmax) {
+        case 8: launch_b_knn<8>(b, r.t_begin, r.t_end, s); break;
+        case 16: launch_b_knn<16>(b, r.t_begin, r.t_end, s); break;
+        case 32: launch_b_knn<32>(b, r.t_begin, r.t_end, s); break;
+        default: launch_b_knn<64>(b, r.t_begin, r.t_end, s); break;
+      }
     }
     STEP(hipSuccess, "kNN search");
     const bool classes = b->fast_mask != 0;
@@ -786,12 +813,14 @@ aidw_status job_status(aidw_batch* b, int32_t* status, hipStream_t s) {
   HIP_TRY(hipMemcpyAsync(h.data(), b->gs, sizeof(GridScalars) * b->njobs, hipMemcpyDeviceToHost, s),
           "reading job status");
   HIP_TRY(hipStreamSynchronize(s), "synchronising");
+  std::vector<int32_t> by_caller(b->njobs);
+  for (int jj = 0; jj < b->njobs; ++jj) by_caller[b->caller[jj]] = h[jj].status;
   aidw_status first = AIDW_OK;
   int first_job = -1;
   for (int j = 0; j < b->njobs; ++j) {
-    if (status) status[j] = h[j].status;
-    if (h[j].status != AIDW_OK && first == AIDW_OK) {
-      first = (aidw_status)h[j].status;
+    if (status) status[j] = by_caller[j];
+    if (by_caller[j] != AIDW_OK && first == AIDW_OK) {
+      first = (aidw_status)by_caller[j];
       first_job = j;
     }
   }

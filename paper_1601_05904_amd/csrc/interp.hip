@@ -123,6 +123,31 @@ __global__ __launch_bounds__(kThreads) void k_interp(const float* __restrict__ x
   }
 }
 
+// The untiled kernel the paper compares its tiled kernel against (Section 4.2): one
+// query per lane, and every lane reads each data point from global memory itself.
+// lane_stride is 0 at run time; the compiler cannot prove the address uniform, so the
+// loads stay per-lane vector loads instead of the wavefront-shared scalar stream of
+// k_interp.  Same per-query state, weight form (general alpha) and tile folds as
+// k_interp with one data range, hence the same sums bit for bit.
+__global__ __launch_bounds__(kThreads) void k_interp_naive(const float* __restrict__ x, const float* __restrict__ y,
+                                                           const float* __restrict__ z, int n,
+                                                           const float* __restrict__ qx, const float* __restrict__ qy,
+                                                           const float* __restrict__ alpha_f,
+                                                           const float* __restrict__ d1sq, int m, int lane_stride,
+                                                           float* __restrict__ qz) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= m) return;
+  Lane<1, 0> L;
+  L.set(0, qx[q], qy[q], alpha_f[q], d1sq[q]);
+  const int off = lane_stride * (int)threadIdx.x;
+  for (int i = 0; i < n; ++i) {
+    L.pair(x[i + off], y[i + off], z[i + off]);
+    if (((i + 1) & (pair::kTile - 1)) == 0) L.fold();
+  }
+  L.fold();
+  qz[q] = (float)(L.num(0) / L.den(0));
+}
+
 // Copies the data into zero-padded arrays of interp_padded_len(n) points.
 __global__ __launch_bounds__(256) void k_pad_copy(const float* __restrict__ x, const float* __restrict__ y,
                                                   const float* __restrict__ z, int n, int npad,
@@ -274,6 +299,14 @@ hipError_t launch_interp(const float* x, const float* y, const float* z, int n, 
 }
 
 int interp_padded_len(int n) { return pair::padded_len(n); }
+
+hipError_t launch_interp_naive(const float* x, const float* y, const float* z, int n, const float* qx, const float* qy,
+                               const float* alpha_f, const float* d1sq, int m, float* qz, hipStream_t s) {
+  if (m <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_interp_naive, dim3((m + kThreads - 1) / kThreads), dim3(kThreads), 0, s, x, y, z, n, qx, qy,
+                     alpha_f, d1sq, m, 0, qz);
+  return hipGetLastError();
+}
 
 hipError_t launch_pad_copy(const float* x, const float* y, const float* z, int n, float* xp, float* yp, float* zp,
                            hipStream_t s) {

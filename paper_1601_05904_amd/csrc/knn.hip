@@ -31,7 +31,7 @@ namespace aidw {
 
 namespace {
 
-template <int KMAX>
+template <int KMAX, bool PAPER = false>
 __global__ __launch_bounds__(256) void k_knn(const GridScalars* __restrict__ gs, const int32_t* __restrict__ cell_start,
                                              const float* __restrict__ sx, const float* __restrict__ sy,
                                              const int32_t* __restrict__ sidx, const float* __restrict__ qx,
@@ -46,7 +46,88 @@ __global__ __launch_bounds__(256) void k_knn(const GridScalars* __restrict__ gs,
   const knn::View g{gs->minx, gs->miny, gs->inv_cw, gs->ncol, gs->nrow, gs->cwd};
   double bk[KMAX];
   int32_t bi[KMAX];
-  knn::search<KMAX>(g, cell_start, sx, sy, sidx, fx, fy, k, slack_cells, bk, bi);
+  knn::search<KMAX, 1, PAPER>(g, cell_start, sx, sy, sidx, fx, fy, k, slack_cells, bk, bi);
+  float ro, d1;
+  knn::summarise<KMAX>(bk, k, ro, d1);
+  r_obs[q] = ro;
+  if (d1sq) d1sq[q] = d1;
+  if (nn_idx) {
+    int32_t* row = nn_idx + (size_t)q * k;
+#pragma unroll
+    for (int s = 0; s < KMAX; ++s)
+      if (s >= KMAX - k) row[s - (KMAX - k)] = bi[s];
+  }
+}
+
+// Four lanes per query (knn::search with LANES = 4), for query sets too small to fill
+// the chip with one query per lane: four times the wavefronts to hide the gathers'
+// latency, and a quarter of the candidates per lane.
+template <int KMAX>
+__global__ __launch_bounds__(256) void k_knn4(const GridScalars* __restrict__ gs, const int32_t* __restrict__ cell_start,
+                                              const float* __restrict__ sx, const float* __restrict__ sy,
+                                              const int32_t* __restrict__ sidx, const float* __restrict__ qx,
+                                              const float* __restrict__ qy, const uint32_t* __restrict__ qperm,
+                                              const uint32_t* __restrict__ active, int m, int k, double slack_cells,
+                                              float* __restrict__ r_obs, float* __restrict__ d1sq,
+                                              int32_t* __restrict__ nn_idx) {
+  const int gt = blockIdx.x * blockDim.x + threadIdx.x;
+  const int t = gt >> 2, sub = gt & 3;
+  if (t >= m || (active && (uint32_t)t >= *active)) return;  // the four lanes of a query leave together
+  const int q = qperm ? (int)qperm[t] : t;
+  const knn::View g{gs->minx, gs->miny, gs->inv_cw, gs->ncol, gs->nrow, gs->cwd};
+  double bk[KMAX];
+  int32_t bi[KMAX];
+  knn::search<KMAX, 4>(g, cell_start, sx, sy, sidx, qx[q], qy[q], k, slack_cells, bk, bi, sub);
+  float ro, d1;
+  knn::merge_lanes<KMAX, 4>(bk, bi, k, sub, ro, d1, nn_idx ? nn_idx + (size_t)q * k : nullptr);
+  if (sub == 0) {
+    r_obs[q] = ro;
+    if (d1sq) d1sq[q] = d1;
+  }
+}
+
+// The per-query brute-force kNN of the earlier GPU AIDW that the paper improves on
+// (Section 3.1): every query scans all n data points and keeps its k best in
+// registers.  One query per lane; the data index is the same across a wavefront,
+// so x, y come through the scalar cache.  Squared distances in float64 and the
+// (d2, index) order as in k_knn, so the result is the exact kNN, bit for bit.
+template <int KMAX>
+__global__ __launch_bounds__(256) void k_knn_brute(const float* __restrict__ x, const float* __restrict__ y, int n,
+                                                   const float* __restrict__ qx, const float* __restrict__ qy, int m,
+                                                   int k, float* __restrict__ r_obs, float* __restrict__ d1sq,
+                                                   int32_t* __restrict__ nn_idx) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  const bool live = q < m;
+  const double px = live ? qx[q] : 0.0, py = live ? qy[q] : 0.0;
+  double bk[KMAX];
+  int32_t bi[KMAX];
+#pragma unroll
+  for (int s = 0; s < KMAX; ++s) {
+    const bool pad = s < KMAX - k;
+    bk[s] = pad ? -1.0 : INFINITY;
+    bi[s] = pad ? -1 : INT32_MAX;
+  }
+  // points arrive in index order, so a later point with an equal distance never enters
+  for (int i = 0; i < n; ++i) {
+    const double dx = (double)x[i] - px;
+    const double dy = (double)y[i] - py;
+    const double d2 = dx * dx + dy * dy;
+    if (d2 < bk[KMAX - 1]) {
+      bk[KMAX - 1] = d2;
+      bi[KMAX - 1] = i;
+#pragma unroll
+      for (int s = KMAX - 1; s > 0; --s) {
+        const bool sw = bk[s] < bk[s - 1];
+        const double lo = bk[s], hi = bk[s - 1];
+        const int32_t ilo = bi[s], ihi = bi[s - 1];
+        bk[s - 1] = sw ? lo : hi;
+        bk[s] = sw ? hi : lo;
+        bi[s - 1] = sw ? ilo : ihi;
+        bi[s] = sw ? ihi : ilo;
+      }
+    }
+  }
+  if (!live) return;
   float ro, d1;
   knn::summarise<KMAX>(bk, k, ro, d1);
   r_obs[q] = ro;
@@ -60,6 +141,65 @@ __global__ __launch_bounds__(256) void k_knn(const GridScalars* __restrict__ gs,
 }
 
 }  // namespace
+
+hipError_t launch_knn_brute(const float* x, const float* y, int n, const float* qx, const float* qy, int m, int k,
+                            float* r_obs, float* d1sq, int32_t* nn_idx, hipStream_t s) {
+  if (m <= 0) return hipSuccess;
+  const dim3 grid((m + 255) / 256), block(256);
+#define AIDW_KNNB(K) \
+  hipLaunchKernelGGL(k_knn_brute<K>, grid, block, 0, s, x, y, n, qx, qy, m, k, r_obs, d1sq, nn_idx)
+  if (k <= 8)
+    AIDW_KNNB(8);
+  else if (k <= 16)
+    AIDW_KNNB(16);
+  else if (k <= 32)
+    AIDW_KNNB(32);
+  else
+    AIDW_KNNB(64);
+#undef AIDW_KNNB
+  return hipGetLastError();
+}
+
+hipError_t launch_knn_paper(const GridScalars* gs, const int32_t* cell_start, const float* sx, const float* sy,
+                            const int32_t* sidx, const float* qx, const float* qy, const uint32_t* qperm, int m, int k,
+                            float* r_obs, float* d1sq, int32_t* nn_idx, hipStream_t s) {
+  if (m <= 0) return hipSuccess;
+  const dim3 grid((m + 255) / 256), block(256);
+#define AIDW_KNNP(K)                                                                                                \
+  hipLaunchKernelGGL((k_knn<K, true>), grid, block, 0, s, gs, cell_start, sx, sy, sidx, qx, qy, qperm, nullptr, m, \
+                     k, 0.0, r_obs, d1sq, nn_idx)
+  if (k <= 8)
+    AIDW_KNNP(8);
+  else if (k <= 16)
+    AIDW_KNNP(16);
+  else if (k <= 32)
+    AIDW_KNNP(32);
+  else
+    AIDW_KNNP(64);
+#undef AIDW_KNNP
+  return hipGetLastError();
+}
+
+hipError_t launch_knn4(const GridScalars* gs, const int32_t* cell_start, const float* sx, const float* sy,
+                       const int32_t* sidx, const float* qx, const float* qy, const uint32_t* qperm,
+                       const uint32_t* active, int m, int k, double slack_cells, float* r_obs, float* d1sq,
+                       int32_t* nn_idx, hipStream_t s) {
+  if (m <= 0) return hipSuccess;
+  const dim3 grid((int)(((int64_t)m * 4 + 255) / 256)), block(256);
+#define AIDW_KNN4(K)                                                                                              \
+  hipLaunchKernelGGL(k_knn4<K>, grid, block, 0, s, gs, cell_start, sx, sy, sidx, qx, qy, qperm, active, m, k, \
+                     slack_cells, r_obs, d1sq, nn_idx)
+  if (k <= 8)
+    AIDW_KNN4(8);
+  else if (k <= 16)
+    AIDW_KNN4(16);
+  else if (k <= 32)
+    AIDW_KNN4(32);
+  else
+    AIDW_KNN4(64);
+#undef AIDW_KNN4
+  return hipGetLastError();
+}
 
 hipError_t launch_knn(const GridScalars* gs, const int32_t* cell_start, const float* sx, const float* sy,
                       const int32_t* sidx, const float* qx, const float* qy, const uint32_t* qperm,

@@ -31,11 +31,24 @@ struct View {
 // The k nearest data points of (fx, fy): on return slots [KMAX - k, KMAX) of
 // (bk, bi) hold their squared distances and indices in ascending (d2, index)
 // order.  slack_cells covers the float32 binning error, in cells.
-template <int KMAX>
+//
+// LANES > 1: LANES consecutive lanes (sub = 0 .. LANES - 1) search for the same
+// query together; each takes every LANES-th candidate of a segment and keeps the
+// k best of its own candidates, so the union of the lanes' lists holds the k
+// nearest.  The lanes walk the same rings in step and stop together: the global
+// k-th distance is at most the largest over the lanes of each lane's
+// ceil(k / LANES)-th, and that bound must pass the stop test (a lane with fewer
+// candidates contributes +inf, which only delays the stop).  merge_lanes then
+// reads the k nearest out in ascending order.
+//
+// PAPER = true: the paper's stop rule instead (Section 3.2.4 and its Remark):
+// grow the level until the block holds >= k points, search one more level, stop.
+// Not exact in general; kept to measure that rule.
+template <int KMAX, int LANES = 1, bool PAPER = false>
 __device__ __forceinline__ void search(const View& g, const int32_t* __restrict__ cell_start,
                                        const float* __restrict__ sx, const float* __restrict__ sy,
                                        const int32_t* __restrict__ sidx, float fx, float fy, int k,
-                                       double slack_cells, double (&bk)[KMAX], int32_t (&bi)[KMAX]) {
+                                       double slack_cells, double (&bk)[KMAX], int32_t (&bi)[KMAX], int sub = 0) {
   const double px = fx, py = fy;
   const int ncol = g.ncol, nrow = g.nrow;
   const double cwd = g.cwd;
@@ -52,6 +65,7 @@ __device__ __forceinline__ void search(const View& g, const int32_t* __restrict_
     bi[s] = pad ? -1 : INT32_MAX;
   }
   int count = 0;
+  int final_level = -1;  // PAPER: the level after the one where the block first held >= k points
 
   for (int L = 0;; ++L) {
     const int cl = c0 - L, cr = c0 + L, rb = r0 - L, rt = r0 + L;
@@ -86,7 +100,7 @@ __device__ __forceinline__ void search(const View& g, const int32_t* __restrict_
       const int p0 = cell_start[base + a];
       const int p1 = cell_start[base + b + 1];
       count += p1 - p0;
-      for (int p = p0; p < p1; ++p) {
+      for (int p = p0 + sub; p < p1; p += LANES) {
         const double dx = (double)sx[p] - px;
         const double dy = (double)sy[p] - py;
         const double d2 = dx * dx + dy * dy;
@@ -109,6 +123,11 @@ __device__ __forceinline__ void search(const View& g, const int32_t* __restrict_
     }
     const bool open_l = cl > 0, open_r = cr < ncol - 1, open_b = rb > 0, open_t = rt < nrow - 1;
     if (!(open_l || open_r || open_b || open_t)) break;  // the block covers the grid
+    if constexpr (PAPER) {
+      if (final_level < 0 && count >= k) final_level = L + 1;
+      if (L == final_level) break;
+      continue;
+    }
     if (count >= k) {
       double dout = INFINITY;
       if (open_l) dout = fmin(dout, px - (minxd + (double)cl * cwd));
@@ -116,10 +135,66 @@ __device__ __forceinline__ void search(const View& g, const int32_t* __restrict_
       if (open_b) dout = fmin(dout, py - (minyd + (double)rb * cwd));
       if (open_t) dout = fmin(dout, (minyd + (double)(rt + 1) * cwd) - py);
       dout -= slack;
-      if (dout > 0.0 && bk[KMAX - 1] < dout * dout) break;
+      double kth = bk[KMAX - 1];
+      if constexpr (LANES > 1) {
+        const int kq = (k + LANES - 1) / LANES;  // the lane's kq-th best: slot KMAX - k + kq - 1
+#pragma unroll
+        for (int s = 0; s < KMAX; ++s)
+          if (s == KMAX - k + kq - 1) kth = bk[s];
+#pragma unroll
+        for (int o = 1; o < LANES; o <<= 1) kth = fmax(kth, __shfl_xor(kth, o, 64));
+      }
+      if (dout > 0.0 && kth < dout * dout) break;
     }
   }
 
+}
+
+// The k nearest over a group of LANES lanes that searched together (search with
+// LANES > 1): popped in ascending (d2, index) order, the same order summarise
+// uses, so r_obs and d1 are bitwise those of a one-lane search.  Every lane of the
+// group returns r_obs and d1; idx (may be null) receives the indices from lane sub 0.
+template <int KMAX, int LANES>
+__device__ __forceinline__ void merge_lanes(double (&bk)[KMAX], int32_t (&bi)[KMAX], int k, int sub, float& r_obs,
+                                            float& d1, int32_t* __restrict__ idx) {
+  // move the k live slots to the front: left shift by KMAX - k, one power of two at a time
+  const int sh = KMAX - k;
+#pragma unroll
+  for (int b = 1; b < KMAX; b <<= 1) {
+    if (sh & b) {
+#pragma unroll
+      for (int s = 0; s < KMAX; ++s) {
+        bk[s] = s + b < KMAX ? bk[s + b] : INFINITY;
+        bi[s] = s + b < KMAX ? bi[s + b] : INT32_MAX;
+      }
+    }
+  }
+  double sum = 0.0;
+  d1 = 0.0f;
+  for (int it = 0; it < k; ++it) {
+    double mv = bk[0];
+    int32_t mi = bi[0];
+#pragma unroll
+    for (int o = 1; o < LANES; o <<= 1) {
+      const double ov = __shfl_xor(mv, o, 64);
+      const int32_t oi = __shfl_xor(mi, o, 64);
+      if (ov < mv || (ov == mv && oi < mi)) {
+        mv = ov;
+        mi = oi;
+      }
+    }
+    if (bk[0] == mv && bi[0] == mi) {  // this lane's head was the smallest: pop it
+#pragma unroll
+      for (int s = 0; s < KMAX; ++s) {
+        bk[s] = s + 1 < KMAX ? bk[s + 1] : INFINITY;
+        bi[s] = s + 1 < KMAX ? bi[s + 1] : INT32_MAX;
+      }
+    }
+    sum += sqrt(mv);
+    if (it == 0) d1 = mv == 0.0 ? 0.0f : fmaxf((float)mv, FLT_MIN);
+    if (idx && sub == 0) idx[it] = mi;
+  }
+  r_obs = (float)(sum / (double)k);
 }
 
 // Eq. 3 from the search result: r_obs = (1/k) sum of the k distances, added in

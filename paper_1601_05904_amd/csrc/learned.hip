@@ -345,6 +345,42 @@ __global__ __launch_bounds__(256) void k_mlp_repack(const float* __restrict__ ma
   if (t < kH) w3r[t] = bf16_round(master[kOffW3 + t]);
 }
 
+// MFMA operands (see mlp_tile): lane = 16 g + r of tile tt holds 8 bf16 of row 16 tt + r.
+//   W1: columns (inputs) 8 g .. 8 g + 7 (zero beyond the 27 inputs);
+//   W2, k-step s: columns h(32 s + 8 g + j) = 16 (2 s + j / 4) + 4 g + j % 4.
+__global__ __launch_bounds__(256) void k_mlp_repack_mfma(const float* __restrict__ master, uint32_t* __restrict__ w1a,
+                                                         uint32_t* __restrict__ w2a, float* __restrict__ b1f,
+                                                         float* __restrict__ b2f, float* __restrict__ w3f) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;  // one bf16 pair of an operand
+  if (t < 4 * 64 * 4) {  // W1: [tile][lane][pair]
+    const int tt = t / 256, lane = (t / 4) % 64, pr = t % 4;
+    const int row = 16 * tt + lane % 16, g = lane / 16;
+    float v[2];
+    for (int e = 0; e < 2; ++e) {
+      const int col = 8 * g + 2 * pr + e;
+      v[e] = col < kIn ? master[kOffW1 + row * kIn + col] : 0.0f;
+    }
+    w1a[t] = pack_bf16(v[0], v[1]);
+  }
+  if (t < 8 * 64 * 4) {  // W2: [tile][step][lane][pair]
+    const int ts = t / 256, lane = (t / 4) % 64, pr = t % 4;
+    const int tt = ts / 2, st = ts % 2;
+    const int row = 16 * tt + lane % 16, g = lane / 16;
+    float v[2];
+    for (int e = 0; e < 2; ++e) {
+      const int j = 2 * pr + e;
+      const int h = 16 * (2 * st + j / 4) + 4 * g + j % 4;
+      v[e] = master[kOffW2 + row * kH + h];
+    }
+    w2a[t] = pack_bf16(v[0], v[1]);
+  }
+  if (t < kH) {
+    b1f[t] = master[kOffB1 + t];
+    b2f[t] = master[kOffB2 + t];
+    w3f[t] = bf16_round(master[kOffW3 + t]);
+  }
+}
+
 // Loss of batch `step` into epoch_loss[epoch] (a single thread: fixed order).
 __global__ void k_accumulate_loss(const float* __restrict__ grad, float* __restrict__ epoch_loss, int epoch,
                                   float scale) {
@@ -375,6 +411,26 @@ __device__ inline double level_alpha_l(double mu, const double* a) {
   return a[4];
 }
 
+// The rule for one query: true = fall back to exact kNN; else *alpha is the rule's alpha.
+__device__ inline bool decide_one(double R, float d1, const AlphaParams& ap, int rule, double delta, double r_sat_lo,
+                                  double r_sat_hi, double* alpha) {
+  *alpha = 0.0;
+  if (d1 == 0.0f || !isfinite(R)) return true;
+  if (rule == 0) {
+    *alpha = level_alpha_l(fuzzy_mu_l(R, ap.r_min, ap.r_max), ap.levels);
+    return fabs(R - ap.r_min) < delta || fabs(R - ap.r_max) < delta;
+  }
+  if (R >= r_sat_hi + delta) {
+    *alpha = ap.levels[4];
+    return false;
+  }
+  if (R <= r_sat_lo - delta) {
+    *alpha = ap.levels[0];
+    return false;
+  }
+  return true;
+}
+
 __global__ __launch_bounds__(256) void k_decide(const float* __restrict__ r_hat, const float* __restrict__ d1pos,
                                                 const uint32_t* __restrict__ perm, int m, AlphaParams ap, int rule,
                                                 double delta, double r_sat_lo, double r_sat_hi,
@@ -385,20 +441,8 @@ __global__ __launch_bounds__(256) void k_decide(const float* __restrict__ r_hat,
   const uint32_t q = perm[t];
   const double R = r_hat[t];
   const float d1 = d1pos[t];
-  bool fall = d1 == 0.0f || !isfinite(R);
-  double alpha = 0.0;
-  if (!fall) {
-    if (rule == 0) {
-      fall = fabs(R - ap.r_min) < delta || fabs(R - ap.r_max) < delta;
-      alpha = level_alpha_l(fuzzy_mu_l(R, ap.r_min, ap.r_max), ap.levels);
-    } else if (R >= r_sat_hi + delta) {
-      alpha = ap.levels[4];
-    } else if (R <= r_sat_lo - delta) {
-      alpha = ap.levels[0];
-    } else {
-      fall = true;
-    }
-  }
+  double alpha;
+  const bool fall = decide_one(R, d1, ap, rule, delta, r_sat_lo, r_sat_hi, &alpha);
   flag[t] = fall ? 1u : 0u;
   if (!fall) {
     alpha_f[q] = (float)alpha;
@@ -427,6 +471,201 @@ __global__ __launch_bounds__(256) void k_alpha_fallback(const uint32_t* __restri
   alpha_f[q] = (float)level_alpha_l(fuzzy_mu_l(R, ap.r_min, ap.r_max), ap.levels);
 }
 
+// ---- inference on the matrix cores -----------------------------------------------------
+//
+// v_mfma_f32_16x16x32_bf16 computes D (16 x 16) = A (16 x 32) B (32 x 16) + C with, for
+// lane l = 16 g + r of the wavefront: A row r, columns 8 g .. 8 g + 7; B column r, rows
+// 8 g .. 8 g + 7; D column r, rows 4 g .. 4 g + 3.  The network runs transposed on a tile
+// of 16 queries, H^T = W X^T, so that lane 16 g + c holds the inputs 8 g .. 8 g + 7 of query
+// c (the B operand) and receives hidden units 16 t + 4 g + i (i = 0..3) of query c from
+// tile t.  Layer 2 takes those as its B operand directly: its k-step s reads hidden units
+// h(32 s + 8 g + j) = 16 (2 s + j / 4) + 4 g + j % 4, the order in which k_mlp_repack_mfma
+// stores the columns of W2.  Layer 3 is a float32 dot over each lane's 16 hidden units and
+// a sum over the 4 lanes of a query.  Operands are bf16, accumulation float32, as in the
+// VALU kernels (the summation order differs).
+
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+typedef float floatx4_t __attribute__((ext_vector_type(4)));
+
+// The W1 and W2 operands of a workgroup, staged in LDS (12 KB): [tile][lane] and
+// [tile][k-step][lane], one 16-byte operand each.
+struct MfmaNet {
+  const uint4* w;  // LDS
+  __device__ inline bf16x8_t w1(int t, int lane) const { return __builtin_bit_cast(bf16x8_t, w[t * 64 + lane]); }
+  __device__ inline bf16x8_t w2(int t, int st, int lane) const {
+    return __builtin_bit_cast(bf16x8_t, w[256 + (t * 2 + st) * 64 + lane]);
+  }
+};
+constexpr int kNetOperands = 4 * 64 + 8 * 64;
+
+__device__ inline bf16x8_t as_bf16x8(uint4 v) { return __builtin_bit_cast(bf16x8_t, v); }
+
+// Copies the operands into the workgroup's LDS (every thread of the workgroup calls it).
+__device__ inline MfmaNet stage_net(const MlpDevice& d, uint4* lds) {
+  const uint4* w1 = reinterpret_cast<const uint4*>(d.w1a);
+  const uint4* w2 = reinterpret_cast<const uint4*>(d.w2a);
+  for (int i = threadIdx.x; i < kNetOperands; i += blockDim.x) lds[i] = i < 256 ? w1[i] : w2[i - 256];
+  __syncthreads();
+  return MfmaNet{lds};
+}
+
+// R_hat of query (lane & 15) from its 8 packed bf16 inputs held by lane (the 4 lanes of a
+// query return the same value).
+__device__ inline float mlp_tile(const MlpDevice& d, const MfmaNet& net, int lane, uint4 x) {
+  const int g = lane >> 4;
+  floatx4_t a1[4];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    const float4 b = *reinterpret_cast<const float4*>(d.b1f + 16 * t + 4 * g);
+    a1[t] = floatx4_t{b.x, b.y, b.z, b.w};
+    a1[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(net.w1(t, lane), as_bf16x8(x), a1[t], 0, 0, 0);
+  }
+  uint4 h[2];
+#pragma unroll
+  for (int st = 0; st < 2; ++st) {
+    h[st].x = pack_bf16(gelu_f(a1[2 * st][0]), gelu_f(a1[2 * st][1]));
+    h[st].y = pack_bf16(gelu_f(a1[2 * st][2]), gelu_f(a1[2 * st][3]));
+    h[st].z = pack_bf16(gelu_f(a1[2 * st + 1][0]), gelu_f(a1[2 * st + 1][1]));
+    h[st].w = pack_bf16(gelu_f(a1[2 * st + 1][2]), gelu_f(a1[2 * st + 1][3]));
+  }
+  float part = 0.0f;
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    const float4 b = *reinterpret_cast<const float4*>(d.b2f + 16 * t + 4 * g);
+    floatx4_t a2 = floatx4_t{b.x, b.y, b.z, b.w};
+#pragma unroll
+    for (int st = 0; st < 2; ++st)
+      a2 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(net.w2(t, st, lane), as_bf16x8(h[st]), a2, 0, 0, 0);
+    const float4 w = *reinterpret_cast<const float4*>(d.w3f + 16 * t + 4 * g);
+    part = __builtin_fmaf(bf16_round(gelu_f(a2[0])), w.x, part);
+    part = __builtin_fmaf(bf16_round(gelu_f(a2[1])), w.y, part);
+    part = __builtin_fmaf(bf16_round(gelu_f(a2[2])), w.z, part);
+    part = __builtin_fmaf(bf16_round(gelu_f(a2[3])), w.w, part);
+  }
+  part += __shfl_xor(part, 16, 64);
+  part += __shfl_xor(part, 32, 64);
+  return part + d.master[kOffB3];
+}
+
+__device__ inline uint4 pack8(const float (&f)[8]) {
+  return uint4{pack_bf16(f[0], f[1]), pack_bf16(f[2], f[3]), pack_bf16(f[4], f[5]), pack_bf16(f[6], f[7])};
+}
+
+// aidw_mlp_forward on the matrix cores: features [m][27] -> out [m].  Each wavefront takes
+// tiles of 16 queries until the queries are exhausted.
+__global__ __launch_bounds__(256) void k_mlp_forward_mfma(MlpDevice d, const float* __restrict__ feat, int m,
+                                                          float* __restrict__ out) {
+  const int lane = threadIdx.x & 63, c = lane & 15, g = lane >> 4;
+  __shared__ uint4 lds[kNetOperands];
+  const MfmaNet net = stage_net(d, lds);
+  const int nwaves = (gridDim.x * blockDim.x) >> 6;
+  for (int tile = (blockIdx.x * blockDim.x + threadIdx.x) >> 6; tile * 16 < m; tile += nwaves) {
+    __asm__ volatile("" ::: "memory");  // keeps the operand reads from LDS inside the loop (registers)
+    const int q = tile * 16 + c;
+    float f[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int k = 8 * g + j;
+      f[j] = (q < m && k < kIn) ? feat[(size_t)q * kIn + k] : 0.0f;
+    }
+    const float y = mlp_tile(d, net, lane, pack8(f));
+    if (g == 0 && q < m) out[q] = y;
+  }
+}
+
+// Fused front of the learned run for the queries at positions t of the order perm (may be
+// null): the 27 features (as k_features), the network, and the rule (as k_decide).  Lane
+// 16 g + c works on the query at position 16 tile + c: it computes features 8 g .. 8 g + 7,
+// and lanes g = 0, 1, 2 scan row r0 - 1 + g of the 3 x 3 block for the nearest distance.
+__global__ __launch_bounds__(256) void k_learned_front(MlpDevice d, const GridScalars* __restrict__ gs,
+                                                       const int32_t* __restrict__ cell_start,
+                                                       const float* __restrict__ sx, const float* __restrict__ sy,
+                                                       const float* __restrict__ qx, const float* __restrict__ qy,
+                                                       const uint32_t* __restrict__ perm, int m, double inv_occ,
+                                                       double slack_cells, AlphaParams ap, int rule, double delta,
+                                                       double r_sat_lo, double r_sat_hi, uint32_t* __restrict__ flag,
+                                                       float* __restrict__ alpha_f, float* __restrict__ d1sq,
+                                                       float* __restrict__ r_hat_out) {
+  const int lane = threadIdx.x & 63, c = lane & 15, g = lane >> 4;
+  __shared__ uint4 lds[kNetOperands];
+  const MfmaNet net = stage_net(d, lds);
+  const float minx = gs->minx, miny = gs->miny, inv = gs->inv_cw;
+  const int ncol = gs->ncol, nrow = gs->nrow;
+  const double cwd = gs->cwd, minxd = minx, minyd = miny;
+  const int nwaves = (gridDim.x * blockDim.x) >> 6;
+  for (int tile = (blockIdx.x * blockDim.x + threadIdx.x) >> 6; tile * 16 < m; tile += nwaves) {
+    __asm__ volatile("" ::: "memory");  // keeps the operand reads from LDS inside the loop (registers)
+    const int t = tile * 16 + c;
+    const bool valid = t < m;
+    const int q = valid ? (perm ? (int)perm[t] : t) : 0;
+    const float fx = valid ? qx[q] : minx, fy = valid ? qy[q] : miny;
+    const float tx = (fx - minx) * inv, ty = (fy - miny) * inv;
+    const int c0 = clamp_cell(tx, ncol), r0 = clamp_cell(ty, nrow);
+    // features 8 g .. 8 g + 7: counts of the 5 x 5 block (row-major), then the in-cell offset
+    float f[8];
+    int last_idx = -1, last_val = 0;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int k = 8 * g + j;
+      float v = 0.0f;
+      if (k < 25) {
+        const int r = r0 + k / 5 - 2, cc = c0 + k % 5 - 2;
+        if (r >= 0 && r < nrow && cc >= 0 && cc < ncol) {
+          const int idx = r * ncol + cc;
+          const int a = idx == last_idx ? last_val : cell_start[idx];
+          const int b = cell_start[idx + 1];
+          last_idx = idx + 1;
+          last_val = b;
+          v = (float)((double)(b - a) * inv_occ);
+        }
+      } else if (k == 25) {
+        v = tx - (float)c0;
+      } else if (k == 26) {
+        v = ty - (float)r0;
+      }
+      f[j] = v;
+    }
+    const float y = mlp_tile(d, net, lane, pack8(f));
+    // nearest point in the 3 x 3 block: row r0 - 1 + g for g < 3, then the minimum over the 4 lanes
+    const double px = fx, py = fy;
+    double best = INFINITY;
+    const int r = r0 - 1 + g;
+    if (g < 3 && r >= 0 && r < nrow) {
+      const int ca = c0 > 0 ? c0 - 1 : 0, cb = c0 + 1 < ncol ? c0 + 1 : ncol - 1;
+      const int p1 = cell_start[r * ncol + cb + 1];
+      for (int p = cell_start[r * ncol + ca]; p < p1; ++p) {
+        const double dx = (double)sx[p] - px;
+        const double dy = (double)sy[p] - py;
+        const double d2 = dx * dx + dy * dy;
+        best = d2 < best ? d2 : best;
+      }
+    }
+    best = fmin(best, __shfl_xor(best, 16, 64));
+    best = fmin(best, __shfl_xor(best, 32, 64));
+    if (g != 0 || !valid) continue;
+    double dout = INFINITY;
+    if (c0 - 1 > 0) dout = fmin(dout, px - (minxd + (double)(c0 - 1) * cwd));
+    if (c0 + 1 < ncol - 1) dout = fmin(dout, (minxd + (double)(c0 + 2) * cwd) - px);
+    if (r0 - 1 > 0) dout = fmin(dout, py - (minyd + (double)(r0 - 1) * cwd));
+    if (r0 + 1 < nrow - 1) dout = fmin(dout, (minyd + (double)(r0 + 2) * cwd) - py);
+    dout -= slack_cells * cwd;
+    double v;
+    if (dout == INFINITY || best < dout * dout)
+      v = best;                        // exact nearest distance
+    else
+      v = dout > 0 ? dout * dout : 0;  // lower bound
+    const float d1 = v == 0.0 ? (best == 0.0 ? 0.0f : FLT_MIN) : fmaxf((float)v, FLT_MIN);
+    double alpha;
+    const bool fall = decide_one((double)y, d1, ap, rule, delta, r_sat_lo, r_sat_hi, &alpha);
+    flag[t] = fall ? 1u : 0u;
+    if (!fall) {
+      alpha_f[q] = (float)alpha;
+      d1sq[q] = d1;
+    }
+    if (r_hat_out) r_hat_out[q] = y;
+  }
+}
+
 }  // namespace
 
 hipError_t launch_features(const GridScalars* gs, const int32_t* cell_start, const float* sx, const float* sy,
@@ -445,12 +684,33 @@ static MlpWeights weights(const MlpDevice& d) {
 hipError_t launch_mlp_repack(const MlpDevice& d, hipStream_t s) {
   hipLaunchKernelGGL(k_mlp_repack, dim3((kH * kH + 255) / 256), dim3(256), 0, s, d.master, d.w1p, d.w2p, d.w3p, d.w2r,
                      d.w3r);
+  hipLaunchKernelGGL(k_mlp_repack_mfma, dim3(8), dim3(256), 0, s, d.master, d.w1a, d.w2a, d.b1f, d.b2f, d.w3f);
+  return hipGetLastError();
+}
+
+namespace {
+// Workgroups of the tile loops: enough wavefronts to fill the chip, at most one tile each.
+int tile_blocks(int m) {
+  const int tiles = (m + 15) / 16;
+  const int blocks = (tiles + 3) / 4;
+  return blocks < 2048 ? (blocks > 0 ? blocks : 1) : 2048;
+}
+}  // namespace
+
+hipError_t launch_learned_front(const MlpDevice& d, const GridScalars* gs, const int32_t* cell_start, const float* sx,
+                                const float* sy, const float* qx, const float* qy, const uint32_t* perm, int m,
+                                double inv_occ, double slack_cells, const AlphaParams& ap, int rule, double delta,
+                                double r_sat_lo, double r_sat_hi, uint32_t* flag, float* alpha_f, float* d1sq,
+                                float* r_hat_out, hipStream_t s) {
+  if (m <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_learned_front, dim3(tile_blocks(m)), dim3(256), 0, s, d, gs, cell_start, sx, sy, qx, qy, perm,
+                     m, inv_occ, slack_cells, ap, rule, delta, r_sat_lo, r_sat_hi, flag, alpha_f, d1sq, r_hat_out);
   return hipGetLastError();
 }
 
 hipError_t launch_mlp_forward(const MlpDevice& d, const float* feat, int m, float* out, hipStream_t s) {
   if (m <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_mlp_forward, dim3((m + 255) / 256), dim3(256), 0, s, weights(d), feat, m, out);
+  hipLaunchKernelGGL(k_mlp_forward_mfma, dim3(tile_blocks(m)), dim3(256), 0, s, d, feat, m, out);
   return hipGetLastError();
 }
 

@@ -149,3 +149,14 @@ def test_batch_totals_beyond_int32_are_capacity_errors(L):
     out = ctypes.c_void_p()
     st = L.aidw_batch_create(_jobs(3, n=600_000_000, m=600_000_000), 3, None, ctypes.byref(out))
     assert st == aidw.ECAPACITY
+
+
+def test_baseline_entry_points_validate(L):
+    assert L.aidw_knn_bruteforce(None, FAKE, 10, FAKE, FAKE, 5, 3, FAKE, None, None, None) == aidw.EINVAL
+    assert L.aidw_knn_bruteforce(FAKE, FAKE, 0, FAKE, FAKE, 5, 3, FAKE, None, None, None) == aidw.EINVAL
+    assert L.aidw_knn_bruteforce(FAKE, FAKE, 10, FAKE, FAKE, 5, 11, FAKE, None, None, None) == aidw.EINVAL
+    assert L.aidw_knn_bruteforce(FAKE, FAKE, 10, None, None, 0, 3, None, None, None, None) == aidw.OK
+    assert L.aidw_knn_bruteforce(FAKE, FAKE, 1 << 31, FAKE, FAKE, 5, 3, FAKE, None, None, None) == aidw.ECAPACITY
+    assert L.aidw_interpolate_naive(FAKE, FAKE, None, 10, FAKE, FAKE, 5, FAKE, FAKE, _p(), None, FAKE, None,
+                                    None) == aidw.EINVAL
+    assert L.aidw_knn_paper(None, FAKE, FAKE, 10, 5, FAKE, None, None, None) == aidw.EINVAL

@@ -158,6 +158,26 @@ def _plain_and_learned(T, ds, mlp, rule, delta, k):
             rh.cpu().numpy(), nfb)
 
 
+def test_learned_run_prediction_matches_fp64_network(T):
+    """The learned run computes features, network and decision in one kernel (network on the
+    matrix cores); its prediction R_hat equals the FP64 network on the oracle's features."""
+    aidw, L = mods()
+    ds = W.make(30000, 9000, 15, 241, "mixture", 16)
+    params = random_params(12, 0.3)
+    mlp = L.MLP(seed=6)
+    mlp.set_params(params)
+    x, y, z, qx, qy = (dev(T, getattr(ds, a)) for a in ("x", "y", "z", "qx", "qy"))
+    p = aidw.Params(k=15)
+    _, _, rh, _ = L.run_learned(x, y, z, qx, qy, p, mlp, L.ALPHA_EXACT, 0.3, want_rhat=True)
+    g = aidw.build_grid(x, y, qx, qy, p)
+    d = g.describe()
+    g.close()
+    feat = O.features(ds.x, ds.y, ds.qx, ds.qy, d["min_x"], d["min_y"], d["inv_cell_width"], d["ncol"], d["nrow"])
+    yo, _ = OM.forward(params.astype(np.float64), feat)
+    err = np.abs(rh.cpu().numpy().astype(np.float64) - yo) / (1.0 + np.abs(yo))
+    assert np.median(err) < 1e-5 and np.quantile(err, 0.99) < 1e-3 and err.max() < 2e-2
+
+
 def test_all_fallback_equals_plain_path(T):
     aidw, L = mods()
     ds = W.make(6000, 3000, 15, 231, "mixture", 8)

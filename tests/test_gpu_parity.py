@@ -314,3 +314,93 @@ def test_full_size_sampled(T, name):
     e = zerr(zall[sel], ref)
     assert e.max() <= Z_TOL, "max z error %.3e" % e.max()
     assert np.allclose(a[sel], ref["alpha"], atol=2e-6)
+
+
+# ------------------------------------------------------------------ the paper's stop rule
+
+@pytest.mark.parametrize("case", ["constructed_miss", "uniform_4k_cw_rexp", "mixture_cw_rexp", "uniform_occ2"])
+def test_knn_paper_rule_matches_oracle(T, case):
+    """aidw_knn_paper (level expansion to >= k points, one more level) against the oracle's
+    reading of the same rule: index sets bit-exact; the mismatch against exact kNN printed."""
+    aidw = aidw_mod()
+    if case == "constructed_miss":
+        x = np.array([0.0, 10.0, 5.99, 3.98, 4.9], np.float32)
+        y = np.array([0.0, 10.0, 5.99, 5.5, 7.2], np.float32)
+        ds = W.Dataset("miss", x, y, np.zeros(5, np.float32), np.array([5.01], np.float32),
+                       np.array([5.5], np.float32), 1, 0)
+        params = aidw.Params(k=1, cell_width=1.0)
+    elif case == "uniform_4k_cw_rexp":
+        ds, params = W.uniform_4k(), aidw.Params(k=10, occupancy=0.25)
+    elif case == "mixture_cw_rexp":
+        ds, params = W.make(20000, 3000, 15, 41, "mixture", 16), aidw.Params(k=15, occupancy=0.25)
+    else:
+        ds, params = W.make(8192, 2000, 10, 42), aidw.Params(k=10)
+    x, y, z, qx, qy = upload(T, ds)
+    g = aidw.build_grid(x, y, qx, qy, params)
+    d = g.describe()
+    r, d1, ix = aidw.knn(g, qx, qy, params.k, want_idx=True, paper_rule=True)
+    re, _, ixe = aidw.knn(g, qx, qy, params.k, want_idx=True)
+    g.close()
+    oi, od2 = O.knn_paper(ds.x, ds.y, ds.qx, ds.qy, params.k, d["min_x"], d["min_y"], d["inv_cell_width"], d["ncol"],
+                          d["nrow"])
+    assert np.array_equal(ix.cpu().numpy(), oi)
+    assert np.allclose(r.cpu().numpy(), O.robs(od2), rtol=1.2e-7, atol=0)
+    miss = np.any(ix.cpu().numpy() != ixe.cpu().numpy(), axis=1)
+    rel = np.abs(r.cpu().numpy().astype(np.float64) / re.cpu().numpy() - 1.0)
+    print("%s: %d of %d queries differ from exact kNN, max r_obs rel. error %.3g" % (case, miss.sum(), ds.m,
+                                                                                       rel.max()))
+    if case == "constructed_miss":
+        assert ix.cpu().numpy()[0, 0] == 2 and ixe.cpu().numpy()[0, 0] == 3
+
+
+# ------------------------------------------------------------------ the paper's baselines
+
+@pytest.mark.parametrize("case", ["uniform_4k", "lattice_ties", "mixture"])
+def test_knn_bruteforce_matches_oracle(T, case):
+    aidw = aidw_mod()
+    if case == "uniform_4k":
+        ds, k = W.uniform_4k(), 10
+    elif case == "lattice_ties":
+        ds, k = tiny_lattice(51, 300, 200), 8
+    else:
+        ds, k = W.make(20000, 2000, 15, 52, "mixture", 16), 15
+    x, y, z, qx, qy = upload(T, ds)
+    r, d1, ix = aidw.knn_bruteforce(x, y, qx, qy, k, want_idx=True)
+    oi, od2 = O.knn(ds.x, ds.y, ds.qx, ds.qy, k)
+    assert np.array_equal(ix.cpu().numpy(), oi)
+    assert np.allclose(r.cpu().numpy(), O.robs(od2), rtol=1.2e-7, atol=0)
+    d1_ref = np.where(od2[:, 0] == 0, 0.0, np.maximum(od2[:, 0].astype(np.float32), np.finfo(np.float32).tiny))
+    assert np.array_equal(d1.cpu().numpy(), d1_ref.astype(np.float32))
+
+
+def test_grid_knn_equals_bruteforce_at_scale(T):
+    """The grid search against the O(nm) definition on the GPU: 2^18 uniform data points,
+    2^15 queries, and the same on clustered data -- index sets, r_obs and d1sq bit for bit."""
+    aidw = aidw_mod()
+    for ds, k in ((W.make(1 << 18, 1 << 15, 10, 53), 10), (W.make(1 << 18, 1 << 15, 15, 54, "mixture", 16), 15)):
+        x, y, z, qx, qy = upload(T, ds)
+        g = aidw.build_grid(x, y, qx, qy, aidw.Params(k=k))
+        r, d1, ix = aidw.knn(g, qx, qy, k, want_idx=True)
+        g.close()
+        rb, d1b, ixb = aidw.knn_bruteforce(x, y, qx, qy, k, want_idx=True)
+        assert T.equal(ix, ixb) and T.equal(r, rb) and T.equal(d1, d1b)
+
+
+def test_naive_interpolation_matches(T):
+    aidw = aidw_mod()
+    ds = W.uniform_4k()
+    x, y, z, qx, qy = upload(T, ds)
+    p = aidw.Params(k=10)
+    g = aidw.build_grid(x, y, qx, qy, p)
+    r, d1, _ = aidw.knn(g, qx, qy, 10)
+    qn, an = aidw.interpolate(x, y, z, qx, qy, r, d1, p, grid=g, want_alpha=True, naive=True)
+    try:
+        aidw.set_interp_config(1, 1, 0)
+        qt, at = aidw.interpolate(x, y, z, qx, qy, r, d1, p, grid=g, want_alpha=True)
+    finally:
+        aidw.set_interp_config(0, 0, -1)
+    g.close()
+    T.cuda.synchronize()
+    assert T.equal(qn, qt) and T.equal(an, at)
+    ref = O.aidw(ds.x, ds.y, ds.z, ds.qx, ds.qy, k=10)
+    assert zerr(qn.cpu().numpy(), ref).max() <= Z_TOL

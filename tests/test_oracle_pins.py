@@ -322,3 +322,88 @@ def test_coincident_query_inside_whole_method():
     res = O.aidw(ds.x, ds.y, ds.z, qx, qy, k=5)
     assert res["knn_d2"][3, 0] == 0.0 and res["knn_idx"][3, 0] == 42
     assert res["z"][3] == np.float64(ds.z[42])
+
+
+# ------------------------------------------------------------------ the paper's "+1 level" rule
+
+def _unit_grid_case():
+    # bounds [0, 10]^2 (corner points), cell side 1 -> 11 x 11 cells, inv_cw = 1
+    x = np.array([0.0, 10.0, 5.99, 3.98], np.float32)   # A, B, P (in the query's cell), R (two columns left)
+    y = np.array([0.0, 10.0, 5.99, 5.5], np.float32)
+    qx = np.array([5.01], np.float32)
+    qy = np.array([5.5], np.float32)
+    b = O.bounds(x, y, qx, qy)
+    gp = O.grid_params(b, x.size, 0.0, 1.0, 2.0)
+    assert (gp["ncol"], gp["nrow"], gp["inv_cw"]) == (11, 11, 1.0)
+    return x, y, qx, qy, b, gp
+
+
+def test_paper_rule_misses_a_nearer_point_outside_the_final_block():
+    """k = 1: the query's own cell holds P, so the search stops at level 0 + 1 = 1 (cells 4..6);
+    R lies in column 3, outside that block, yet nearer (1.03 against 1.096)."""
+    x, y, qx, qy, b, gp = _unit_grid_case()
+    idx, d2 = O.knn_paper(x, y, qx, qy, 1, b[0], b[1], gp["inv_cw"], gp["ncol"], gp["nrow"])
+    eidx, ed2 = O.knn(x, y, qx, qy, 1)
+    assert idx[0, 0] == 2 and eidx[0, 0] == 3
+    assert d2[0, 0] == pytest.approx((5.99 - 5.01) ** 2 + (5.99 - 5.5) ** 2, rel=1e-6)
+    assert ed2[0, 0] == pytest.approx((5.01 - 3.98) ** 2, rel=1e-6)
+    # k = 2: levels 0 and 1 hold only P, level 2 (cells 3..7) holds P and R -> final level 3 -> exact
+    idx2, _ = O.knn_paper(x, y, qx, qy, 2, b[0], b[1], gp["inv_cw"], gp["ncol"], gp["nrow"])
+    eidx2, _ = O.knn(x, y, qx, qy, 2)
+    assert idx2.tolist() == eidx2.tolist() == [[3, 2]]
+    # the extra level matters: a point in the next column (level 1) is found although the
+    # query's own cell already held one
+    x3 = np.append(x, np.float32(4.9))
+    y3 = np.append(y, np.float32(5.5))
+    idx3, _ = O.knn_paper(x3, y3, qx, qy, 1, b[0], b[1], gp["inv_cw"], gp["ncol"], gp["nrow"])
+    assert idx3[0, 0] == 4
+
+
+def test_paper_rule_on_one_cell_is_brute_force():
+    rng = np.random.default_rng(31)
+    x, y = W.quantise(rng.random(300)), W.quantise(rng.random(300))
+    qx, qy = W.quantise(rng.random(50)), W.quantise(rng.random(50))
+    b = O.bounds(x, y, qx, qy)
+    gp = O.grid_params(b, x.size, 0.0, 4.0, 2.0)  # one cell covers the unit square
+    assert gp["ncol"] == gp["nrow"] == 1
+    for k in (1, 7, 300):
+        idx, d2 = O.knn_paper(x, y, qx, qy, k, b[0], b[1], gp["inv_cw"], gp["ncol"], gp["nrow"])
+        eidx, ed2 = O.knn(x, y, qx, qy, k)
+        assert np.array_equal(idx, eidx) and np.array_equal(d2, ed2)
+
+
+@pytest.mark.parametrize("occ", [0.25, 2.0])
+def test_paper_rule_never_beats_exact_and_is_exact_when_it_must_be(occ):
+    """Its k distances are those of k points, so each is >= the exact one; and a query whose
+    k-th found distance is within the distance to the final block's edge has the exact set."""
+    ds = W.make(4096, 1500, 10, 33)
+    b = O.bounds(ds.x, ds.y, ds.qx, ds.qy)
+    gp = O.grid_params(b, ds.n, 0.0, 0.0, occ)
+    idx, d2 = O.knn_paper(ds.x, ds.y, ds.qx, ds.qy, 10, b[0], b[1], gp["inv_cw"], gp["ncol"], gp["nrow"])
+    eidx, ed2 = O.knn(ds.x, ds.y, ds.qx, ds.qy, 10)
+    assert np.all(d2 >= ed2)
+    same = np.all(idx == eidx, axis=1)
+    assert same.mean() > 0.99  # the rule rarely fails on uniform data (the Remark's claim)
+    # recompute the final level and the distance to its edge, and check exactness where it is implied
+    cq = O.cell_index(ds.qx, ds.qy, b[0], b[1], gp["inv_cw"], gp["ncol"], gp["nrow"])
+    cd = O.cell_index(ds.x, ds.y, b[0], b[1], gp["inv_cw"], gp["ncol"], gp["nrow"])
+    dc, dr = cd % gp["ncol"], cd // gp["ncol"]
+    cw = 1.0 / float(np.float32(gp["inv_cw"]))
+    for j in range(0, ds.m, 7):
+        c0, r0 = cq[j] % gp["ncol"], cq[j] // gp["ncol"]
+        L = 0
+        while np.count_nonzero((abs(dc - c0) <= L) & (abs(dr - r0) <= L)) < 10:
+            L += 1
+        Lf = L + 1
+        edges = []
+        if c0 - Lf > 0:
+            edges.append(float(ds.qx[j]) - (b[0] + (c0 - Lf) * cw))
+        if c0 + Lf < gp["ncol"] - 1:
+            edges.append(b[0] + (c0 + Lf + 1) * cw - float(ds.qx[j]))
+        if r0 - Lf > 0:
+            edges.append(float(ds.qy[j]) - (b[1] + (r0 - Lf) * cw))
+        if r0 + Lf < gp["nrow"] - 1:
+            edges.append(b[1] + (r0 + Lf + 1) * cw - float(ds.qy[j]))
+        e = min(edges) - 1e-6 if edges else np.inf
+        if d2[j, -1] < e * e:
+            assert same[j], j
