@@ -470,6 +470,12 @@ aidw_status aidw_run_batch(const aidw_job* jobs, int32_t njobs, const aidw_batch
 aidw_status aidw_batch_tune(const aidw_job* jobs, int32_t njobs, const aidw_batch_config* candidates,
                             int32_t ncandidates, int32_t reps, float* ms_out, hipStream_t stream);
 
+/* Temporaries of the calls above come from a cache of device blocks that the
+ * library keeps between calls (reused in stream order, or after an event wait
+ * on another stream).  This waits for the current device and frees the cached
+ * blocks not in use on it.  Errors: AIDW_EDEVICE. */
+aidw_status aidw_release_cached_memory(void);
+
 /* Static text for a status code. */
 const char* aidw_status_string(aidw_status st);
 

@@ -145,6 +145,7 @@ def load(build_if_missing: bool = True):
     L.aidw_set_timing.argtypes = [ctypes.c_int]
     L.aidw_last_timing.argtypes = [P(_Timing)]
     L.aidw_set_interp_config.argtypes = [i32, i32, i32]
+    L.aidw_release_cached_memory.argtypes = []
     L.aidw_status_string.argtypes = [ctypes.c_int]
     L.aidw_status_string.restype = ctypes.c_char_p
     L.aidw_last_error_detail.argtypes = []
@@ -184,7 +185,8 @@ def load(build_if_missing: bool = True):
                  "aidw_mlp_create", "aidw_mlp_set_params", "aidw_mlp_get_params", "aidw_mlp_save", "aidw_mlp_load",
                  "aidw_features", "aidw_mlp_forward", "aidw_mlp_gradients", "aidw_mlp_train", "aidw_run_learned",
                  "aidw_batch_create", "aidw_batch_run", "aidw_batch_job_status", "aidw_batch_describe",
-                 "aidw_batch_set_timing", "aidw_batch_last_timing", "aidw_run_batch", "aidw_batch_tune"):
+                 "aidw_batch_set_timing", "aidw_batch_last_timing", "aidw_run_batch", "aidw_batch_tune",
+                 "aidw_release_cached_memory"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -344,6 +346,11 @@ def set_interp_config(q: int = 0, split: int = 0, integer_powers: int = -1):
     """Pair-kernel launch shape for later calls on this thread (0 = built-in choice);
     integer_powers = 0 forces the general exp2/log2 weight for every query."""
     _check(load().aidw_set_interp_config(int(q), int(split), int(integer_powers)))
+
+
+def release_cached_memory():
+    """aidw_release_cached_memory: frees the library's idle cached device blocks (waits for the device)."""
+    _check(load().aidw_release_cached_memory())
 
 
 def version() -> str:

@@ -166,7 +166,8 @@ hipError_t launch_features(const GridScalars* gs, const int32_t* cell_start, con
 hipError_t launch_mlp_repack(const MlpDevice& d, hipStream_t s);
 hipError_t launch_mlp_forward(const MlpDevice& d, const float* feat, int m, float* out, hipStream_t s);
 // Fused inference front of the learned run, per position t of the order perm (may be null):
-// features, the network (MFMA) and the fallback decision of launch_decide in one kernel.
+// features, the network (MFMA) and the fallback decision in one kernel; flag[t] = 1 marks a
+// query that takes the exact kNN.
 hipError_t launch_learned_front(const MlpDevice& d, const GridScalars* gs, const int32_t* cell_start, const float* sx,
                                 const float* sy, const float* qx, const float* qy, const uint32_t* perm, int m,
                                 double inv_occ, double slack_cells, const AlphaParams& ap, int rule, double delta,
@@ -179,11 +180,6 @@ hipError_t launch_mlp_gradients(const MlpDevice& d, const float* feat, const flo
 hipError_t launch_adam(const MlpDevice& d, const float* grad, float lr, float b1, float b2, float eps, float bc1,
                        float bc2, hipStream_t s);
 hipError_t launch_accumulate_loss(const float* grad, float* epoch_loss, int epoch, float scale, hipStream_t s);
-// Per position t of the binned order (query perm[t]): flag[t] = 1 for exact-kNN fallback; skipped
-// queries get alpha_f[q] from the rule and d1sq[q] = d1pos[t]; r_hat_out[q] = r_hat[t] (if non-null).
-hipError_t launch_decide(const float* r_hat, const float* d1pos, const uint32_t* perm, int m, const AlphaParams& ap,
-                         int rule, double delta, double r_sat_lo, double r_sat_hi, uint32_t* flag, float* alpha_f,
-                         float* d1sq, float* r_hat_out, hipStream_t s);
 // list[idx[t]] = perm[t] for flagged positions (idx = exclusive scan of flag).
 hipError_t launch_compact(const uint32_t* flag, const uint32_t* idx, const uint32_t* perm, int m, uint32_t* list,
                           hipStream_t s);

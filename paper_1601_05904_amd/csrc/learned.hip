@@ -431,26 +431,6 @@ __device__ inline bool decide_one(double R, float d1, const AlphaParams& ap, int
   return true;
 }
 
-__global__ __launch_bounds__(256) void k_decide(const float* __restrict__ r_hat, const float* __restrict__ d1pos,
-                                                const uint32_t* __restrict__ perm, int m, AlphaParams ap, int rule,
-                                                double delta, double r_sat_lo, double r_sat_hi,
-                                                uint32_t* __restrict__ flag, float* __restrict__ alpha_f,
-                                                float* __restrict__ d1sq, float* __restrict__ r_hat_out) {
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= m) return;
-  const uint32_t q = perm[t];
-  const double R = r_hat[t];
-  const float d1 = d1pos[t];
-  double alpha;
-  const bool fall = decide_one(R, d1, ap, rule, delta, r_sat_lo, r_sat_hi, &alpha);
-  flag[t] = fall ? 1u : 0u;
-  if (!fall) {
-    alpha_f[q] = (float)alpha;
-    d1sq[q] = d1;
-  }
-  if (r_hat_out) r_hat_out[q] = (float)R;
-}
-
 __global__ __launch_bounds__(256) void k_compact(const uint32_t* __restrict__ flag, const uint32_t* __restrict__ idx,
                                                  const uint32_t* __restrict__ perm, int m,
                                                  uint32_t* __restrict__ list) {
@@ -464,11 +444,12 @@ __global__ __launch_bounds__(256) void k_alpha_fallback(const uint32_t* __restri
                                                         const uint32_t* __restrict__ count,
                                                         const float* __restrict__ r_obs, AlphaParams ap,
                                                         float* __restrict__ alpha_f) {
-  const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= *count) return;
-  const uint32_t q = perm[t];
-  const double R = (double)r_obs[q] / ap.r_exp;
-  alpha_f[q] = (float)level_alpha_l(fuzzy_mu_l(R, ap.r_min, ap.r_max), ap.levels);
+  const uint32_t cnt = *count;
+  for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < cnt; t += gridDim.x * blockDim.x) {
+    const uint32_t q = perm[t];
+    const double R = (double)r_obs[q] / ap.r_exp;
+    alpha_f[q] = (float)level_alpha_l(fuzzy_mu_l(R, ap.r_min, ap.r_max), ap.levels);
+  }
 }
 
 // ---- inference on the matrix cores -----------------------------------------------------
@@ -574,7 +555,8 @@ __global__ __launch_bounds__(256) void k_mlp_forward_mfma(MlpDevice d, const flo
 }
 
 // Fused front of the learned run for the queries at positions t of the order perm (may be
-// null): the 27 features (as k_features), the network, and the rule (as k_decide).  Lane
+// null): the 27 features (as k_features), the network, and the fallback rule; flag[t] = 1
+// marks a query that takes the exact kNN.  Lane
 // 16 g + c works on the query at position 16 tile + c: it computes features 8 g .. 8 g + 7,
 // and lanes g = 0, 1, 2 scan row r0 - 1 + g of the 3 x 3 block for the nearest distance.
 __global__ __launch_bounds__(256) void k_learned_front(MlpDevice d, const GridScalars* __restrict__ gs,
@@ -689,11 +671,22 @@ hipError_t launch_mlp_repack(const MlpDevice& d, hipStream_t s) {
 }
 
 namespace {
-// Workgroups of the tile loops: enough wavefronts to fill the chip, at most one tile each.
-int tile_blocks(int m) {
+// Workgroups of a tile loop over m queries: as many as the chip holds at once for
+// this kernel (a second, partial round would leave most of the chip idle), at most
+// one tile per wavefront.
+int tile_blocks(const void* kernel, int m) {
+  int dev = 0, cus = 0, per_cu = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, 256, 0) != hipSuccess || cus <= 0 ||
+      per_cu <= 0) {
+    cus = 256;
+    per_cu = 2;
+  }
   const int tiles = (m + 15) / 16;
   const int blocks = (tiles + 3) / 4;
-  return blocks < 2048 ? (blocks > 0 ? blocks : 1) : 2048;
+  const int cap = cus * per_cu;
+  return blocks < cap ? (blocks > 0 ? blocks : 1) : cap;
 }
 }  // namespace
 
@@ -703,14 +696,16 @@ hipError_t launch_learned_front(const MlpDevice& d, const GridScalars* gs, const
                                 double r_sat_lo, double r_sat_hi, uint32_t* flag, float* alpha_f, float* d1sq,
                                 float* r_hat_out, hipStream_t s) {
   if (m <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_learned_front, dim3(tile_blocks(m)), dim3(256), 0, s, d, gs, cell_start, sx, sy, qx, qy, perm,
-                     m, inv_occ, slack_cells, ap, rule, delta, r_sat_lo, r_sat_hi, flag, alpha_f, d1sq, r_hat_out);
+  hipLaunchKernelGGL(k_learned_front, dim3(tile_blocks((const void*)k_learned_front, m)), dim3(256), 0, s, d, gs,
+                     cell_start, sx, sy, qx, qy, perm, m, inv_occ, slack_cells, ap, rule, delta, r_sat_lo, r_sat_hi,
+                     flag, alpha_f, d1sq, r_hat_out);
   return hipGetLastError();
 }
 
 hipError_t launch_mlp_forward(const MlpDevice& d, const float* feat, int m, float* out, hipStream_t s) {
   if (m <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_mlp_forward_mfma, dim3(tile_blocks(m)), dim3(256), 0, s, d, feat, m, out);
+  hipLaunchKernelGGL(k_mlp_forward_mfma, dim3(tile_blocks((const void*)k_mlp_forward_mfma, m)), dim3(256), 0, s, d,
+                     feat, m, out);
   return hipGetLastError();
 }
 
@@ -746,15 +741,6 @@ hipError_t launch_accumulate_loss(const float* grad, float* epoch_loss, int epoc
   return hipGetLastError();
 }
 
-hipError_t launch_decide(const float* r_hat, const float* d1pos, const uint32_t* perm, int m, const AlphaParams& ap,
-                         int rule, double delta, double r_sat_lo, double r_sat_hi, uint32_t* flag, float* alpha_f,
-                         float* d1sq, float* r_hat_out, hipStream_t s) {
-  if (m <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_decide, dim3((m + 255) / 256), dim3(256), 0, s, r_hat, d1pos, perm, m, ap, rule, delta,
-                     r_sat_lo, r_sat_hi, flag, alpha_f, d1sq, r_hat_out);
-  return hipGetLastError();
-}
-
 hipError_t launch_compact(const uint32_t* flag, const uint32_t* idx, const uint32_t* perm, int m, uint32_t* list,
                           hipStream_t s) {
   if (m <= 0) return hipSuccess;
@@ -765,7 +751,9 @@ hipError_t launch_compact(const uint32_t* flag, const uint32_t* idx, const uint3
 hipError_t launch_alpha_fallback(const uint32_t* perm, const uint32_t* count, int m, const float* r_obs,
                                  const AlphaParams& ap, float* alpha_f, hipStream_t s) {
   if (m <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_alpha_fallback, dim3((m + 255) / 256), dim3(256), 0, s, perm, count, r_obs, ap, alpha_f);
+  const int blocks = (m + 255) / 256;
+  hipLaunchKernelGGL(k_alpha_fallback, dim3(blocks < 1024 ? blocks : 1024), dim3(256), 0, s, perm, count, r_obs, ap,
+                     alpha_f);
   return hipGetLastError();
 }
 

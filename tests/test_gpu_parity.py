@@ -404,3 +404,28 @@ def test_naive_interpolation_matches(T):
     assert T.equal(qn, qt) and T.equal(an, at)
     ref = O.aidw(ds.x, ds.y, ds.z, ds.qx, ds.qy, k=10)
     assert zerr(qn.cpu().numpy(), ref).max() <= Z_TOL
+
+
+def test_cached_temporaries_across_streams(T):
+    """Temporaries are cached between calls: runs alternating between two streams (a block
+    released on one stream is reused on the other after an event wait), with the cache
+    released midway, all give the first run's result."""
+    aidw = aidw_mod()
+    ds = W.make(30000, 20000, 10, 61, "mixture", 8)
+    x, y, z, qx, qy = upload(T, ds)
+    p = aidw.Params(k=10)
+    ref = aidw.run(x, y, z, qx, qy, p)
+    T.cuda.synchronize()
+    streams = [T.cuda.Stream(), T.cuda.Stream()]
+    outs = []
+    for i in range(6):
+        s = streams[i % 2]
+        s.wait_stream(T.cuda.current_stream())
+        with T.cuda.stream(s):
+            outs.append(aidw.run(x, y, z, qx, qy, p, stream=s))
+        if i == 3:
+            T.cuda.synchronize()
+            aidw.release_cached_memory()
+    T.cuda.synchronize()
+    for o in outs:
+        assert T.equal(o, ref)
