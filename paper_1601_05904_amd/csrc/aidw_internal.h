@@ -78,6 +78,11 @@ size_t radix_hist_words(int n);
 size_t radix_scan_tmp_words(int n);
 hipError_t radix_sort_pairs(uint32_t* keys, uint32_t* vals, uint32_t* tmp_keys, uint32_t* tmp_vals, int n, int bits,
                             uint32_t* hist, uint32_t* scan_tmp, hipStream_t s);
+// The same without the copy-back: *out_keys / *out_vals receive the buffers (keys / vals or
+// the temporaries) that hold the sorted result.
+hipError_t radix_sort_pairs_to(uint32_t* keys, uint32_t* vals, uint32_t* tmp_keys, uint32_t* tmp_vals, int n, int bits,
+                               uint32_t* hist, uint32_t* scan_tmp, hipStream_t s, uint32_t** out_keys,
+                               uint32_t** out_vals);
 // out[i] = in[0] + ... + in[i-1] (in and out may alias); *total (device, may be null) = the sum.
 // tmp needs scan_tmp_words(len) words.
 size_t scan_tmp_words(size_t len);

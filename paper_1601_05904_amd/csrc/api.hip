@@ -258,9 +258,10 @@ aidw_status build_grid_impl(const float* x, const float* y, int64_t n, const flo
       return cleanup(hip_fail(e, "allocating sort buffers"));
     if ((e = launch_cell_keys(x, y, (int)n, g->dev, keys, vals, s)) != hipSuccess)
       return cleanup(hip_fail(e, "cell key kernel"));
-    if ((e = radix_sort_pairs(keys, vals, tk, tv, (int)n, bits_for(ncells), hist, scan, s)) != hipSuccess)
+    uint32_t *sk, *sv;  // the sorted pairs (in keys / vals or in the temporaries)
+    if ((e = radix_sort_pairs_to(keys, vals, tk, tv, (int)n, bits_for(ncells), hist, scan, s, &sk, &sv)) != hipSuccess)
       return cleanup(hip_fail(e, "radix sort"));
-    if ((e = launch_cell_start_gather(keys, vals, (int)n, ncells, x, y, g->cell_start, g->sx, g->sy, g->sidx, s)) !=
+    if ((e = launch_cell_start_gather(sk, sv, (int)n, ncells, x, y, g->cell_start, g->sx, g->sy, g->sidx, s)) !=
         hipSuccess)
       return cleanup(hip_fail(e, "cell offsets / gather"));
   }
@@ -289,16 +290,18 @@ aidw_status knn_impl(const aidw_grid* g, const float* qx, const float* qy, int64
     return hip_fail(e, "allocating query-binning buffers");
   // bin the queries with the data's cell formula, then sort them by cell
   HIP_TRY(launch_cell_keys(qx, qy, (int)m, g->dev, keys, vals, s), "query key kernel");
-  HIP_TRY(radix_sort_pairs(keys, vals, tk, tv, (int)m, bits_for(g->host.ncells), hist, scan, s), "query sort");
+  uint32_t *sk, *order;  // sorted keys and the queries in cell order
+  HIP_TRY(radix_sort_pairs_to(keys, vals, tk, tv, (int)m, bits_for(g->host.ncells), hist, scan, s, &sk, &order),
+          "query sort");
   if (paper_rule) {
-    HIP_TRY(launch_knn_paper(g->dev, g->cell_start, g->sx, g->sy, g->sidx, qx, qy, vals, (int)m, k, r_obs, d1sq,
+    HIP_TRY(launch_knn_paper(g->dev, g->cell_start, g->sx, g->sy, g->sidx, qx, qy, order, (int)m, k, r_obs, d1sq,
                              nn_idx, s),
             "kNN kernel (paper rule)");
     return AIDW_OK;
   }
   // below 2^17 queries one lane per query leaves the chip idle: four lanes share each query
   auto knn = m < (1 << 17) ? launch_knn4 : launch_knn;
-  HIP_TRY(knn(g->dev, g->cell_start, g->sx, g->sy, g->sidx, qx, qy, vals, nullptr, (int)m, k, slack_cells(g->host), r_obs,
+  HIP_TRY(knn(g->dev, g->cell_start, g->sx, g->sy, g->sidx, qx, qy, order, nullptr, (int)m, k, slack_cells(g->host), r_obs,
               d1sq, nn_idx, s),
           "kNN kernel");
   return AIDW_OK;
@@ -370,12 +373,14 @@ aidw_status interp_impl(const float* x, const float* y, const float* z, int64_t 
   } else {
     HIP_TRY(launch_alpha_class(r_obs, (int)m, ap, alpha_f, alpha_out, keys, perm, s), "alpha kernel");
   }
-  if (fast_mask && !naive) HIP_TRY(radix_sort_pairs(keys, perm, tk, tv, (int)m, 4, hist, scan, s), "class sort");
+  uint32_t *ckeys = keys, *cperm = perm;  // the class order (in keys / perm or in the temporaries)
+  if (fast_mask && !naive)
+    HIP_TRY(radix_sort_pairs_to(keys, perm, tk, tv, (int)m, 4, hist, scan, s, &ckeys, &cperm), "class sort");
   if (ev_begin) HIP_TRY(hipEventRecord(ev_begin, s), "event");
   if (naive) {
     HIP_TRY(launch_interp_naive(x, y, z, (int)n, qx, qy, alpha_f, d1sq, (int)m, qz, s), "interpolation kernel (untiled)");
   } else {
-    HIP_TRY(launch_interp(xp, yp, zp, (int)n, qx, qy, alpha_f, d1sq, perm, keys, (int)m, fast_mask, q, split, qz,
+    HIP_TRY(launch_interp(xp, yp, zp, (int)n, qx, qy, alpha_f, d1sq, cperm, ckeys, (int)m, fast_mask, q, split, qz,
                           partial, s),
             "interpolation kernel");
   }
@@ -910,13 +915,15 @@ aidw_status aidw_run_learned(const float* x, const float* y, const float* z, int
 #define STEP(expr, what) \
   if (st == AIDW_OK && (e = (expr)) != hipSuccess) st = hip_fail(e, what)
     STEP(launch_cell_keys(qx, qy, mm, g->dev, keys, perm, stream), "query key kernel");
-    STEP(radix_sort_pairs(keys, perm, tk, tv, mm, bits_for(g->host.ncells), hist, scan, stream), "query sort");
-    STEP(launch_learned_front(mlp->d, g->dev, g->cell_start, g->sx, g->sy, qx, qy, perm, mm, inv_occ,
+    uint32_t *sk = keys, *order = perm;  // the queries in cell order
+    STEP(radix_sort_pairs_to(keys, perm, tk, tv, mm, bits_for(g->host.ncells), hist, scan, stream, &sk, &order),
+         "query sort");
+    STEP(launch_learned_front(mlp->d, g->dev, g->cell_start, g->sx, g->sy, qx, qy, order, mm, inv_occ,
                               slack_cells(g->host), ap, rule, delta, r_sat_lo, r_sat_hi, flag, alpha_f, d1sq, r_hat_out,
                               stream),
          "features / network / decision kernel");
     STEP(exclusive_scan_u32(flag, idx, mm, stmp, count, stream), "fallback scan");
-    STEP(launch_compact(flag, idx, perm, mm, list, stream), "fallback compaction");
+    STEP(launch_compact(flag, idx, order, mm, list, stream), "fallback compaction");
     STEP(launch_knn4(g->dev, g->cell_start, g->sx, g->sy, g->sidx, qx, qy, list, count, mm, p->k, slack_cells(g->host),
                     r_obs, d1sq, nullptr, stream),
          "kNN kernel");

@@ -303,15 +303,17 @@ size_t radix_hist_words(int n) { return (size_t)kRadix * (size_t)div_up(n > 0 ? 
 
 size_t radix_scan_tmp_words(int n) { return (size_t)div_up((int64_t)radix_hist_words(n), kScanChunk) + 1; }
 
-hipError_t radix_sort_pairs(uint32_t* keys, uint32_t* vals, uint32_t* tmp_keys, uint32_t* tmp_vals, int n, int bits,
-                            uint32_t* hist, uint32_t* scan_tmp, hipStream_t s) {
+hipError_t radix_sort_pairs_to(uint32_t* keys, uint32_t* vals, uint32_t* tmp_keys, uint32_t* tmp_vals, int n, int bits,
+                               uint32_t* hist, uint32_t* scan_tmp, hipStream_t s, uint32_t** out_keys,
+                               uint32_t** out_vals) {
+  *out_keys = keys;
+  *out_vals = vals;
   if (n <= 1 || bits <= 0) return hipSuccess;
   const int nblocks = div_up(n, kSortTile);
   const size_t hlen = (size_t)kRadix * nblocks;
   const int nsb = div_up((int64_t)hlen, kScanChunk);
   uint32_t *ki = keys, *vi = vals, *ko = tmp_keys, *vo = tmp_vals;
-  int passes = 0;
-  for (int shift = 0; shift < bits; shift += kRadixBits, ++passes) {
+  for (int shift = 0; shift < bits; shift += kRadixBits) {
     hipLaunchKernelGGL(k_radix_hist, dim3(nblocks), dim3(kSortThreads), 0, s, ki, n, shift, hist, nblocks);
     hipLaunchKernelGGL(k_scan_reduce, dim3(nsb), dim3(kScanThreads), 0, s, hist, hlen, scan_tmp);
     hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kScanThreads), 0, s, scan_tmp, nsb);
@@ -327,13 +329,20 @@ hipError_t radix_sort_pairs(uint32_t* keys, uint32_t* vals, uint32_t* tmp_keys, 
     vi = vo;
     vo = t;
   }
-  if (passes & 1) {  // result is in the temporaries: copy back
-    hipError_t e = hipMemcpyAsync(keys, ki, sizeof(uint32_t) * n, hipMemcpyDeviceToDevice, s);
-    if (e != hipSuccess) return e;
-    e = hipMemcpyAsync(vals, vi, sizeof(uint32_t) * n, hipMemcpyDeviceToDevice, s);
-    if (e != hipSuccess) return e;
-  }
+  *out_keys = ki;
+  *out_vals = vi;
   return hipSuccess;
+}
+
+hipError_t radix_sort_pairs(uint32_t* keys, uint32_t* vals, uint32_t* tmp_keys, uint32_t* tmp_vals, int n, int bits,
+                            uint32_t* hist, uint32_t* scan_tmp, hipStream_t s) {
+  uint32_t *rk, *rv;
+  hipError_t e = radix_sort_pairs_to(keys, vals, tmp_keys, tmp_vals, n, bits, hist, scan_tmp, s, &rk, &rv);
+  if (e != hipSuccess || rk == keys) return e;
+  // an odd number of passes: the result is in the temporaries; copy it back
+  e = hipMemcpyAsync(keys, rk, sizeof(uint32_t) * n, hipMemcpyDeviceToDevice, s);
+  if (e != hipSuccess) return e;
+  return hipMemcpyAsync(vals, rv, sizeof(uint32_t) * n, hipMemcpyDeviceToDevice, s);
 }
 
 namespace {

@@ -575,14 +575,38 @@ __global__ __launch_bounds__(256) void k_learned_front(MlpDevice d, const GridSc
   const int ncol = gs->ncol, nrow = gs->nrow;
   const double cwd = gs->cwd, minxd = minx, minyd = miny;
   const int nwaves = (gridDim.x * blockDim.x) >> 6;
-  for (int tile = (blockIdx.x * blockDim.x + threadIdx.x) >> 6; tile * 16 < m; tile += nwaves) {
+  // The loads of a tile's query index and coordinates are issued one and two tiles ahead
+  // (a wavefront works through its tiles in sequence), so that a tile starts with its
+  // coordinates at hand; the scan's row bounds are loaded together with the features.
+  auto query_of = [&](int tl) -> int {
+    const int tt = tl * 16 + c;
+    return tt < m ? (perm ? (int)perm[tt] : tt) : -1;
+  };
+  int tile = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  int q_next = query_of(tile);                 // tile + 1 in the loop below
+  int q_next2 = query_of(tile + nwaves);       // tile + 2
+  float fx_next = q_next >= 0 ? qx[q_next] : minx, fy_next = q_next >= 0 ? qy[q_next] : miny;
+  for (; tile * 16 < m; tile += nwaves) {
     __asm__ volatile("" ::: "memory");  // keeps the operand reads from LDS inside the loop (registers)
     const int t = tile * 16 + c;
     const bool valid = t < m;
-    const int q = valid ? (perm ? (int)perm[t] : t) : 0;
-    const float fx = valid ? qx[q] : minx, fy = valid ? qy[q] : miny;
+    const int q = valid ? q_next : 0;
+    const float fx = fx_next, fy = fy_next;
+    q_next = q_next2;
+    q_next2 = query_of(tile + 2 * nwaves);
+    fx_next = q_next >= 0 ? qx[q_next] : minx;
+    fy_next = q_next >= 0 ? qy[q_next] : miny;
     const float tx = (fx - minx) * inv, ty = (fy - miny) * inv;
     const int c0 = clamp_cell(tx, ncol), r0 = clamp_cell(ty, nrow);
+    // the 3 x 3 scan's bounds: row r0 - 1 + g, columns c0 - 1 .. c0 + 1 (clipped), for g < 3
+    const int rs = r0 - 1 + g;
+    const bool scan_row = g < 3 && rs >= 0 && rs < nrow;
+    int p0 = 0, p1 = 0;
+    if (scan_row) {
+      const int ca = c0 > 0 ? c0 - 1 : 0, cb = c0 + 1 < ncol ? c0 + 1 : ncol - 1;
+      p0 = cell_start[rs * ncol + ca];
+      p1 = cell_start[rs * ncol + cb + 1];
+    }
     // features 8 g .. 8 g + 7: counts of the 5 x 5 block (row-major), then the in-cell offset
     float f[8];
     int last_idx = -1, last_val = 0;
@@ -611,11 +635,8 @@ __global__ __launch_bounds__(256) void k_learned_front(MlpDevice d, const GridSc
     // nearest point in the 3 x 3 block: row r0 - 1 + g for g < 3, then the minimum over the 4 lanes
     const double px = fx, py = fy;
     double best = INFINITY;
-    const int r = r0 - 1 + g;
-    if (g < 3 && r >= 0 && r < nrow) {
-      const int ca = c0 > 0 ? c0 - 1 : 0, cb = c0 + 1 < ncol ? c0 + 1 : ncol - 1;
-      const int p1 = cell_start[r * ncol + cb + 1];
-      for (int p = cell_start[r * ncol + ca]; p < p1; ++p) {
+    if (scan_row) {
+      for (int p = p0; p < p1; ++p) {
         const double dx = (double)sx[p] - px;
         const double dy = (double)sy[p] - py;
         const double d2 = dx * dx + dy * dy;
