@@ -61,8 +61,9 @@ constexpr int kBoundsThreads = 256;
 constexpr int kSortThreads = 256;
 constexpr int kSortItems = 16;                       // elements per thread per block
 constexpr int kSortTile = kSortThreads * kSortItems; // elements per block
-constexpr int kRadixBits = 8;
-constexpr int kRadix = 1 << kRadixBits;
+constexpr int kRadixBits = 8;                        // digit width of the sort passes
+constexpr int kRadixBitsWide = 10;                   // used where it saves a pass
+constexpr int kRadixMax = 1 << kRadixBitsWide;
 
 // Host-side launchers (all asynchronous on `s`; return the first HIP error).
 hipError_t launch_bounds(const float* x, const float* y, int n, const float* qx, const float* qy, int m,
@@ -105,7 +106,12 @@ hipError_t launch_knn_brute(const float* x, const float* y, int n, const float* 
 hipError_t launch_knn_paper(const GridScalars* gs, const int32_t* cell_start, const float* sx, const float* sy,
                             const int32_t* sidx, const float* qx, const float* qy, const uint32_t* qperm, int m, int k,
                             float* r_obs, float* d1sq, int32_t* nn_idx, hipStream_t s);
-// The same with four lanes per query (for small or sparse query sets); identical results.
+// The same with `lanes` (2, 4 or 8) lanes per query (for small or sparse query sets); identical results.
+hipError_t launch_knn_lanes(const GridScalars* gs, const int32_t* cell_start, const float* sx, const float* sy,
+                            const int32_t* sidx, const float* qx, const float* qy, const uint32_t* qperm,
+                            const uint32_t* active, int m, int k, double slack_cells, float* r_obs, float* d1sq,
+                            int32_t* nn_idx, int lanes, hipStream_t s);
+// Four lanes per query.
 hipError_t launch_knn4(const GridScalars* gs, const int32_t* cell_start, const float* sx, const float* sy,
                        const int32_t* sidx, const float* qx, const float* qy, const uint32_t* qperm,
                        const uint32_t* active, int m, int k, double slack_cells, float* r_obs, float* d1sq,

@@ -924,8 +924,9 @@ aidw_status aidw_run_learned(const float* x, const float* y, const float* z, int
          "features / network / decision kernel");
     STEP(exclusive_scan_u32(flag, idx, mm, stmp, count, stream), "fallback scan");
     STEP(launch_compact(flag, idx, order, mm, list, stream), "fallback compaction");
-    STEP(launch_knn4(g->dev, g->cell_start, g->sx, g->sy, g->sidx, qx, qy, list, count, mm, p->k, slack_cells(g->host),
-                    r_obs, d1sq, nullptr, stream),
+    // the fallback queries are few and hard (cluster edges): eight lanes per query measured best
+    STEP(launch_knn_lanes(g->dev, g->cell_start, g->sx, g->sy, g->sidx, qx, qy, list, count, mm, p->k,
+                          slack_cells(g->host), r_obs, d1sq, nullptr, 8, stream),
          "kNN kernel");
     STEP(launch_alpha_fallback(list, count, mm, r_obs, ap, alpha_f, stream), "alpha kernel");
 #undef STEP

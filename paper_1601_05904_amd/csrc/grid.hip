@@ -93,18 +93,20 @@ __global__ __launch_bounds__(256) void k_cell_keys(const float* __restrict__ x, 
 
 // ---- stable LSD radix sort ------------------------------------------------------
 
+template <int BITS>
 __global__ __launch_bounds__(kSortThreads) void k_radix_hist(const uint32_t* __restrict__ keys, int n, int shift,
                                                              uint32_t* __restrict__ hist, int nblocks) {
-  __shared__ uint32_t h[kRadix];
-  for (int i = threadIdx.x; i < kRadix; i += kSortThreads) h[i] = 0;
+  constexpr int R = 1 << BITS;
+  __shared__ uint32_t h[R];
+  for (int i = threadIdx.x; i < R; i += kSortThreads) h[i] = 0;
   __syncthreads();
   const int base = blockIdx.x * kSortTile;
   for (int r = 0; r < kSortItems; ++r) {
     const int i = base + r * kSortThreads + threadIdx.x;
-    if (i < n) atomicAdd(&h[(keys[i] >> shift) & (kRadix - 1)], 1u);
+    if (i < n) atomicAdd(&h[(keys[i] >> shift) & (R - 1)], 1u);
   }
   __syncthreads();
-  for (int d = threadIdx.x; d < kRadix; d += kSortThreads) hist[(size_t)d * nblocks + blockIdx.x] = h[d];
+  for (int d = threadIdx.x; d < R; d += kSortThreads) hist[(size_t)d * nblocks + blockIdx.x] = h[d];
 }
 
 constexpr int kScanThreads = 256;
@@ -177,29 +179,31 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_down(const uint32_t* __re
 // Stable scatter of one digit: within a block, elements are taken in index order,
 // one per thread per round; a wavefront ranks equal digits with ballots, waves
 // are ordered by an LDS prefix, rounds by a running per-digit base.
+template <int BITS>
 __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(const uint32_t* __restrict__ kin,
                                                                 const uint32_t* __restrict__ vin,
                                                                 uint32_t* __restrict__ kout,
                                                                 uint32_t* __restrict__ vout, int n, int shift,
                                                                 const uint32_t* __restrict__ offs, int nblocks) {
   constexpr int W = kSortThreads / 64;
-  __shared__ uint32_t base[kRadix];
-  __shared__ uint32_t wcnt[W][kRadix];
+  constexpr int R = 1 << BITS;
+  __shared__ uint32_t base[R];
+  __shared__ uint32_t wcnt[W][R];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  for (int d = tid; d < kRadix; d += kSortThreads) base[d] = offs[(size_t)d * nblocks + blockIdx.x];
+  for (int d = tid; d < R; d += kSortThreads) base[d] = offs[(size_t)d * nblocks + blockIdx.x];
   const uint64_t lt_mask = lane == 0 ? 0ull : (~0ull >> (64 - lane));
   const int tile = blockIdx.x * kSortTile;
   for (int r = 0; r < kSortItems; ++r) {
-    for (int d = lane; d < kRadix; d += 64) wcnt[wave][d] = 0;
+    for (int d = lane; d < R; d += 64) wcnt[wave][d] = 0;
     __syncthreads();
     const int i = tile + r * kSortThreads + tid;
     const bool valid = i < n;
     const uint32_t key = valid ? kin[i] : 0u;
     const uint32_t val = valid ? vin[i] : 0u;
-    const uint32_t d = (key >> shift) & (kRadix - 1);
+    const uint32_t d = (key >> shift) & (R - 1);
     uint64_t match = __ballot(valid);
 #pragma unroll
-    for (int b = 0; b < kRadixBits; ++b) {
+    for (int b = 0; b < BITS; ++b) {
       const bool bit = (d >> b) & 1u;
       const uint64_t bb = __ballot(bit);
       match &= bit ? bb : ~bb;
@@ -215,7 +219,7 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(const uint32_t* 
       vout[pos] = val;
     }
     __syncthreads();
-    for (int dd = tid; dd < kRadix; dd += kSortThreads) {
+    for (int dd = tid; dd < R; dd += kSortThreads) {
       uint32_t tot = 0;
       for (int w = 0; w < W; ++w) tot += wcnt[w][dd];
       base[dd] += tot;
@@ -299,26 +303,23 @@ hipError_t launch_cell_keys(const float* x, const float* y, int n, const GridSca
   return hipGetLastError();
 }
 
-size_t radix_hist_words(int n) { return (size_t)kRadix * (size_t)div_up(n > 0 ? n : 1, kSortTile); }
+size_t radix_hist_words(int n) { return (size_t)kRadixMax * (size_t)div_up(n > 0 ? n : 1, kSortTile); }
 
 size_t radix_scan_tmp_words(int n) { return (size_t)div_up((int64_t)radix_hist_words(n), kScanChunk) + 1; }
 
-hipError_t radix_sort_pairs_to(uint32_t* keys, uint32_t* vals, uint32_t* tmp_keys, uint32_t* tmp_vals, int n, int bits,
-                               uint32_t* hist, uint32_t* scan_tmp, hipStream_t s, uint32_t** out_keys,
-                               uint32_t** out_vals) {
-  *out_keys = keys;
-  *out_vals = vals;
-  if (n <= 1 || bits <= 0) return hipSuccess;
+namespace {
+template <int BITS>
+hipError_t radix_sort_passes(uint32_t*& ki, uint32_t*& vi, uint32_t*& ko, uint32_t*& vo, int n, int bits,
+                             uint32_t* hist, uint32_t* scan_tmp, hipStream_t s) {
   const int nblocks = div_up(n, kSortTile);
-  const size_t hlen = (size_t)kRadix * nblocks;
+  const size_t hlen = ((size_t)1 << BITS) * nblocks;
   const int nsb = div_up((int64_t)hlen, kScanChunk);
-  uint32_t *ki = keys, *vi = vals, *ko = tmp_keys, *vo = tmp_vals;
-  for (int shift = 0; shift < bits; shift += kRadixBits) {
-    hipLaunchKernelGGL(k_radix_hist, dim3(nblocks), dim3(kSortThreads), 0, s, ki, n, shift, hist, nblocks);
+  for (int shift = 0; shift < bits; shift += BITS) {
+    hipLaunchKernelGGL(k_radix_hist<BITS>, dim3(nblocks), dim3(kSortThreads), 0, s, ki, n, shift, hist, nblocks);
     hipLaunchKernelGGL(k_scan_reduce, dim3(nsb), dim3(kScanThreads), 0, s, hist, hlen, scan_tmp);
     hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kScanThreads), 0, s, scan_tmp, nsb);
     hipLaunchKernelGGL(k_scan_down, dim3(nsb), dim3(kScanThreads), 0, s, hist, hlen, scan_tmp, hist);
-    hipLaunchKernelGGL(k_radix_scatter, dim3(nblocks), dim3(kSortThreads), 0, s, ki, vi, ko, vo, n, shift, hist,
+    hipLaunchKernelGGL(k_radix_scatter<BITS>, dim3(nblocks), dim3(kSortThreads), 0, s, ki, vi, ko, vo, n, shift, hist,
                        nblocks);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
@@ -329,9 +330,24 @@ hipError_t radix_sort_pairs_to(uint32_t* keys, uint32_t* vals, uint32_t* tmp_key
     vi = vo;
     vo = t;
   }
+  return hipSuccess;
+}
+}  // namespace
+
+hipError_t radix_sort_pairs_to(uint32_t* keys, uint32_t* vals, uint32_t* tmp_keys, uint32_t* tmp_vals, int n, int bits,
+                               uint32_t* hist, uint32_t* scan_tmp, hipStream_t s, uint32_t** out_keys,
+                               uint32_t** out_vals) {
+  *out_keys = keys;
+  *out_vals = vals;
+  if (n <= 1 || bits <= 0) return hipSuccess;
+  uint32_t *ki = keys, *vi = vals, *ko = tmp_keys, *vo = tmp_vals;
+  // 10-bit digits where they save a pass (each pass is five launches), 8-bit ones otherwise
+  const bool wide = (bits + kRadixBitsWide - 1) / kRadixBitsWide < (bits + kRadixBits - 1) / kRadixBits;
+  hipError_t e = wide ? radix_sort_passes<kRadixBitsWide>(ki, vi, ko, vo, n, bits, hist, scan_tmp, s)
+                      : radix_sort_passes<kRadixBits>(ki, vi, ko, vo, n, bits, hist, scan_tmp, s);
   *out_keys = ki;
   *out_vals = vi;
-  return hipSuccess;
+  return e;
 }
 
 hipError_t radix_sort_pairs(uint32_t* keys, uint32_t* vals, uint32_t* tmp_keys, uint32_t* tmp_vals, int n, int bits,

@@ -59,11 +59,11 @@ __global__ __launch_bounds__(256) void k_knn(const GridScalars* __restrict__ gs,
   }
 }
 
-// Four lanes per query (knn::search with LANES = 4), for query sets too small to fill
-// the chip with one query per lane: four times the wavefronts to hide the gathers'
-// latency, and a quarter of the candidates per lane.
-template <int KMAX>
-__global__ __launch_bounds__(256) void k_knn4(const GridScalars* __restrict__ gs, const int32_t* __restrict__ cell_start,
+// LANES lanes per query (knn::search with LANES > 1), for query sets too small to fill
+// the chip with one query per lane: LANES times the wavefronts to hide the gathers'
+// latency, and 1 / LANES of the candidates per lane.
+template <int KMAX, int LANES>
+__global__ __launch_bounds__(256) void k_knn_lanes(const GridScalars* __restrict__ gs, const int32_t* __restrict__ cell_start,
                                               const float* __restrict__ sx, const float* __restrict__ sy,
                                               const int32_t* __restrict__ sidx, const float* __restrict__ qx,
                                               const float* __restrict__ qy, const uint32_t* __restrict__ qperm,
@@ -71,15 +71,15 @@ __global__ __launch_bounds__(256) void k_knn4(const GridScalars* __restrict__ gs
                                               float* __restrict__ r_obs, float* __restrict__ d1sq,
                                               int32_t* __restrict__ nn_idx) {
   const int gt = blockIdx.x * blockDim.x + threadIdx.x;
-  const int t = gt >> 2, sub = gt & 3;
-  if (t >= m || (active && (uint32_t)t >= *active)) return;  // the four lanes of a query leave together
+  const int t = gt / LANES, sub = gt % LANES;
+  if (t >= m || (active && (uint32_t)t >= *active)) return;  // the lanes of a query leave together
   const int q = qperm ? (int)qperm[t] : t;
   const knn::View g{gs->minx, gs->miny, gs->inv_cw, gs->ncol, gs->nrow, gs->cwd};
   double bk[KMAX];
   int32_t bi[KMAX];
-  knn::search<KMAX, 4>(g, cell_start, sx, sy, sidx, qx[q], qy[q], k, slack_cells, bk, bi, sub);
+  knn::search<KMAX, LANES>(g, cell_start, sx, sy, sidx, qx[q], qy[q], k, slack_cells, bk, bi, sub);
   float ro, d1;
-  knn::merge_lanes<KMAX, 4>(bk, bi, k, sub, ro, d1, nn_idx ? nn_idx + (size_t)q * k : nullptr);
+  knn::merge_lanes<KMAX, LANES>(bk, bi, k, sub, ro, d1, nn_idx ? nn_idx + (size_t)q * k : nullptr);
   if (sub == 0) {
     r_obs[q] = ro;
     if (d1sq) d1sq[q] = d1;
@@ -180,27 +180,45 @@ hipError_t launch_knn_paper(const GridScalars* gs, const int32_t* cell_start, co
   return hipGetLastError();
 }
 
+hipError_t launch_knn_lanes(const GridScalars* gs, const int32_t* cell_start, const float* sx, const float* sy,
+                            const int32_t* sidx, const float* qx, const float* qy, const uint32_t* qperm,
+                            const uint32_t* active, int m, int k, double slack_cells, float* r_obs, float* d1sq,
+                            int32_t* nn_idx, int lanes, hipStream_t s) {
+  if (m <= 0) return hipSuccess;
+  if (lanes != 2 && lanes != 4 && lanes != 8) return hipErrorInvalidValue;
+  // one workgroup per 256 / lanes queries; with an active count the workgroups beyond it exit at
+  // once (a grid-stride loop instead costs the search registers: 161 -> 198 VGPRs, measured slower)
+  const dim3 grid((int)(((int64_t)m * lanes + 255) / 256)), block(256);
+#define AIDW_KNNL(K, LN)                                                                                         \
+  hipLaunchKernelGGL((k_knn_lanes<K, LN>), grid, block, 0, s, gs, cell_start, sx, sy, sidx, qx, qy, qperm, active, \
+                     m, k, slack_cells, r_obs, d1sq, nn_idx)
+#define AIDW_KNNL_K(LN)   \
+  if (k <= 8)             \
+    AIDW_KNNL(8, LN);     \
+  else if (k <= 16)       \
+    AIDW_KNNL(16, LN);    \
+  else if (k <= 32)       \
+    AIDW_KNNL(32, LN);    \
+  else                    \
+    AIDW_KNNL(64, LN)
+  if (lanes == 2) {
+    AIDW_KNNL_K(2);
+  } else if (lanes == 4) {
+    AIDW_KNNL_K(4);
+  } else {
+    AIDW_KNNL_K(8);
+  }
+#undef AIDW_KNNL_K
+#undef AIDW_KNNL
+  return hipGetLastError();
+}
+
 hipError_t launch_knn4(const GridScalars* gs, const int32_t* cell_start, const float* sx, const float* sy,
                        const int32_t* sidx, const float* qx, const float* qy, const uint32_t* qperm,
                        const uint32_t* active, int m, int k, double slack_cells, float* r_obs, float* d1sq,
                        int32_t* nn_idx, hipStream_t s) {
-  if (m <= 0) return hipSuccess;
-  // one workgroup per 64 queries; with an active count the workgroups beyond it exit at once
-  // (a grid-stride loop instead costs the search registers: 161 -> 198 VGPRs, measured slower)
-  const dim3 grid((int)(((int64_t)m * 4 + 255) / 256)), block(256);
-#define AIDW_KNN4(K)                                                                                              \
-  hipLaunchKernelGGL(k_knn4<K>, grid, block, 0, s, gs, cell_start, sx, sy, sidx, qx, qy, qperm, active, m, k, \
-                     slack_cells, r_obs, d1sq, nn_idx)
-  if (k <= 8)
-    AIDW_KNN4(8);
-  else if (k <= 16)
-    AIDW_KNN4(16);
-  else if (k <= 32)
-    AIDW_KNN4(32);
-  else
-    AIDW_KNN4(64);
-#undef AIDW_KNN4
-  return hipGetLastError();
+  return launch_knn_lanes(gs, cell_start, sx, sy, sidx, qx, qy, qperm, active, m, k, slack_cells, r_obs, d1sq, nn_idx,
+                          4, s);
 }
 
 hipError_t launch_knn(const GridScalars* gs, const int32_t* cell_start, const float* sx, const float* sy,
