@@ -89,6 +89,10 @@ hipError_t radix_sort_pairs_to(uint32_t* keys, uint32_t* vals, uint32_t* tmp_key
 size_t scan_tmp_words(size_t len);
 hipError_t exclusive_scan_u32(const uint32_t* in, uint32_t* out, size_t len, uint32_t* tmp, uint32_t* total,
                               hipStream_t s);
+// The queries in cell order (any order within a cell): order[m] lists them; cnt needs
+// ncells + 1 words, key and slot m words each, scan_tmp scan_tmp_words(ncells + 1).
+hipError_t bin_queries(const GridScalars* gs, const float* qx, const float* qy, int m, int64_t ncells, uint32_t* cnt,
+                       uint32_t* key, uint32_t* slot, uint32_t* scan_tmp, uint32_t* order, hipStream_t s);
 hipError_t launch_cell_start_gather(const uint32_t* keys, const uint32_t* vals, int n, int64_t ncells, const float* x,
                                     const float* y, int32_t* cell_start, float* sx, float* sy, int32_t* sidx,
                                     hipStream_t s);

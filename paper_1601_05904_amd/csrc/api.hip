@@ -282,17 +282,15 @@ aidw_status check_data(const float* x, const float* y, int64_t n, const float* q
 aidw_status knn_impl(const aidw_grid* g, const float* qx, const float* qy, int64_t m, int32_t k, float* r_obs,
                      float* d1sq, int32_t* nn_idx, hipStream_t s, bool paper_rule = false) {
   Temps t(s);
-  uint32_t *keys, *vals, *tk, *tv, *hist, *scan;
+  const int64_t ncells = g->host.ncells;
+  uint32_t *cnt, *key, *slot, *scan, *order;
   hipError_t e;
-  if ((e = t.get(&keys, m)) != hipSuccess || (e = t.get(&vals, m)) != hipSuccess || (e = t.get(&tk, m)) != hipSuccess ||
-      (e = t.get(&tv, m)) != hipSuccess || (e = t.get(&hist, radix_hist_words((int)m))) != hipSuccess ||
-      (e = t.get(&scan, radix_scan_tmp_words((int)m))) != hipSuccess)
+  if ((e = t.get(&cnt, ncells + 1)) != hipSuccess || (e = t.get(&key, m)) != hipSuccess ||
+      (e = t.get(&slot, m)) != hipSuccess || (e = t.get(&scan, scan_tmp_words(ncells + 1))) != hipSuccess ||
+      (e = t.get(&order, m)) != hipSuccess)
     return hip_fail(e, "allocating query-binning buffers");
-  // bin the queries with the data's cell formula, then sort them by cell
-  HIP_TRY(launch_cell_keys(qx, qy, (int)m, g->dev, keys, vals, s), "query key kernel");
-  uint32_t *sk, *order;  // sorted keys and the queries in cell order
-  HIP_TRY(radix_sort_pairs_to(keys, vals, tk, tv, (int)m, bits_for(g->host.ncells), hist, scan, s, &sk, &order),
-          "query sort");
+  // bin the queries with the data's cell formula: order lists them in cell order
+  HIP_TRY(bin_queries(g->dev, qx, qy, (int)m, ncells, cnt, key, slot, scan, order, s), "query binning");
   if (paper_rule) {
     HIP_TRY(launch_knn_paper(g->dev, g->cell_start, g->sx, g->sy, g->sidx, qx, qy, order, (int)m, k, r_obs, d1sq,
                              nn_idx, s),
@@ -885,18 +883,18 @@ aidw_status aidw_run_learned(const float* x, const float* y, const float* z, int
     // order; the fallback list is the flagged positions, compacted in order by a prefix sum,
     // so the kNN kernel sees them binned as well (its locality depends on that order).
     float *d1sq = nullptr, *alpha_f = nullptr, *r_obs = nullptr;
-    uint32_t *keys = nullptr, *perm = nullptr, *tk = nullptr, *tv = nullptr, *hist = nullptr, *scan = nullptr,
-             *flag = nullptr, *idx = nullptr, *list = nullptr, *stmp = nullptr, *count = nullptr;
+    uint32_t *cnt = nullptr, *key = nullptr, *slot = nullptr, *scan = nullptr, *order = nullptr, *flag = nullptr,
+             *idx = nullptr, *list = nullptr, *stmp = nullptr, *count = nullptr;
     const int mm = (int)m;
+    const int64_t ncells = g->host.ncells;
     if (e == hipSuccess) e = t.get(&d1sq, mm);
     if (e == hipSuccess) e = t.get(&alpha_f, mm);
     if (e == hipSuccess) e = t.get(&r_obs, mm);
-    if (e == hipSuccess) e = t.get(&keys, mm);
-    if (e == hipSuccess) e = t.get(&perm, mm);
-    if (e == hipSuccess) e = t.get(&tk, mm);
-    if (e == hipSuccess) e = t.get(&tv, mm);
-    if (e == hipSuccess) e = t.get(&hist, radix_hist_words(mm));
-    if (e == hipSuccess) e = t.get(&scan, radix_scan_tmp_words(mm));
+    if (e == hipSuccess) e = t.get(&cnt, ncells + 1);
+    if (e == hipSuccess) e = t.get(&key, mm);
+    if (e == hipSuccess) e = t.get(&slot, mm);
+    if (e == hipSuccess) e = t.get(&scan, scan_tmp_words(ncells + 1));
+    if (e == hipSuccess) e = t.get(&order, mm);
     if (e == hipSuccess) e = t.get(&flag, mm);
     if (e == hipSuccess) e = t.get(&idx, mm);
     if (e == hipSuccess) e = t.get(&list, mm);
@@ -914,10 +912,7 @@ aidw_status aidw_run_learned(const float* x, const float* y, const float* z, int
     const double inv_occ = (double)g->host.ncells / (double)n;
 #define STEP(expr, what) \
   if (st == AIDW_OK && (e = (expr)) != hipSuccess) st = hip_fail(e, what)
-    STEP(launch_cell_keys(qx, qy, mm, g->dev, keys, perm, stream), "query key kernel");
-    uint32_t *sk = keys, *order = perm;  // the queries in cell order
-    STEP(radix_sort_pairs_to(keys, perm, tk, tv, mm, bits_for(g->host.ncells), hist, scan, stream, &sk, &order),
-         "query sort");
+    STEP(bin_queries(g->dev, qx, qy, mm, ncells, cnt, key, slot, scan, order, stream), "query binning");
     STEP(launch_learned_front(mlp->d, g->dev, g->cell_start, g->sx, g->sy, qx, qy, order, mm, inv_occ,
                               slack_cells(g->host), ap, rule, delta, r_sat_lo, r_sat_hi, flag, alpha_f, d1sq, r_hat_out,
                               stream),

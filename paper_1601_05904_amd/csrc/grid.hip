@@ -91,6 +91,40 @@ __global__ __launch_bounds__(256) void k_cell_keys(const float* __restrict__ x, 
   vals[i] = (uint32_t)i;
 }
 
+// ---- query binning -------------------------------------------------------------
+// The kNN kernels and the learned front take the queries in cell order, so that a
+// wavefront's queries scan neighbouring cells.  Each query's results depend on that
+// query alone, so the order within a cell is free: a counting sort whose slot within
+// a cell is the value a global atomic hands out (cell counts, their exclusive scan,
+// placement) replaces a stable sort.
+
+__global__ __launch_bounds__(256) void k_fill_u32(uint32_t* __restrict__ p, int64_t len, uint32_t v) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < len) p[i] = v;
+}
+
+__global__ __launch_bounds__(256) void k_query_slots(const float* __restrict__ qx, const float* __restrict__ qy, int m,
+                                                     const GridScalars* __restrict__ gs, uint32_t* __restrict__ cnt,
+                                                     uint32_t* __restrict__ key, uint32_t* __restrict__ slot) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= m) return;
+  const float minx = gs->minx, miny = gs->miny, inv = gs->inv_cw;
+  const int ncol = gs->ncol, nrow = gs->nrow;
+  int col = (int)((qx[i] - minx) * inv), row = (int)((qy[i] - miny) * inv);
+  col = col > ncol - 1 ? ncol - 1 : (col < 0 ? 0 : col);
+  row = row > nrow - 1 ? nrow - 1 : (row < 0 ? 0 : row);
+  const uint32_t c = (uint32_t)(row * ncol + col);
+  key[i] = c;
+  slot[i] = atomicAdd(&cnt[c], 1u);
+}
+
+__global__ __launch_bounds__(256) void k_query_place(const uint32_t* __restrict__ key, const uint32_t* __restrict__ slot,
+                                                     int m, const uint32_t* __restrict__ start,
+                                                     uint32_t* __restrict__ order) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < m) order[start[key[i]] + slot[i]] = (uint32_t)i;
+}
+
 // ---- stable LSD radix sort ------------------------------------------------------
 
 template <int BITS>
@@ -99,12 +133,18 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_hist(const uint32_t* __r
   constexpr int R = 1 << BITS;
   __shared__ uint32_t h[R];
   for (int i = threadIdx.x; i < R; i += kSortThreads) h[i] = 0;
-  __syncthreads();
+  // all of a thread's keys are loaded before the first count, so the block waits for memory once
   const int base = blockIdx.x * kSortTile;
+  uint32_t key[kSortItems];
+#pragma unroll
   for (int r = 0; r < kSortItems; ++r) {
     const int i = base + r * kSortThreads + threadIdx.x;
-    if (i < n) atomicAdd(&h[(keys[i] >> shift) & (R - 1)], 1u);
+    key[r] = i < n ? keys[i] : 0u;
   }
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < kSortItems; ++r)
+    if (base + r * kSortThreads + (int)threadIdx.x < n) atomicAdd(&h[(key[r] >> shift) & (R - 1)], 1u);
   __syncthreads();
   for (int d = threadIdx.x; d < R; d += kSortThreads) hist[(size_t)d * nblocks + blockIdx.x] = h[d];
 }
@@ -178,7 +218,13 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_down(const uint32_t* __re
 
 // Stable scatter of one digit: within a block, elements are taken in index order,
 // one per thread per round; a wavefront ranks equal digits with ballots, waves
-// are ordered by an LDS prefix, rounds by a running per-digit base.
+// are ordered by an LDS prefix, rounds by a running per-digit base.  A thread's
+// elements are all loaded before the first round.  wcnt[w][d] holds wave w's
+// count of digit d in the current round and is zero otherwise: the lane that
+// wrote it (the digit's first lane in the wave) clears it once the round's
+// positions are taken and adds the count to base[d].  Two barriers per round:
+// after the counts are written, and after they are read; a wave's clear and its
+// next write of the same entry are ordered by the wave's own program order.
 template <int BITS>
 __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(const uint32_t* __restrict__ kin,
                                                                 const uint32_t* __restrict__ vin,
@@ -190,17 +236,22 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(const uint32_t* 
   __shared__ uint32_t base[R];
   __shared__ uint32_t wcnt[W][R];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  for (int d = tid; d < R; d += kSortThreads) base[d] = offs[(size_t)d * nblocks + blockIdx.x];
-  const uint64_t lt_mask = lane == 0 ? 0ull : (~0ull >> (64 - lane));
   const int tile = blockIdx.x * kSortTile;
+  uint32_t key[kSortItems], val[kSortItems];
+#pragma unroll
   for (int r = 0; r < kSortItems; ++r) {
-    for (int d = lane; d < R; d += 64) wcnt[wave][d] = 0;
-    __syncthreads();
     const int i = tile + r * kSortThreads + tid;
-    const bool valid = i < n;
-    const uint32_t key = valid ? kin[i] : 0u;
-    const uint32_t val = valid ? vin[i] : 0u;
-    const uint32_t d = (key >> shift) & (R - 1);
+    key[r] = i < n ? kin[i] : 0u;
+    val[r] = i < n ? vin[i] : 0u;
+  }
+  for (int d = tid; d < R; d += kSortThreads) base[d] = offs[(size_t)d * nblocks + blockIdx.x];
+  for (int d = tid; d < W * R; d += kSortThreads) (&wcnt[0][0])[d] = 0;
+  const uint64_t lt_mask = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < kSortItems; ++r) {
+    const bool valid = tile + r * kSortThreads + tid < n;
+    const uint32_t d = (key[r] >> shift) & (R - 1);
     uint64_t match = __ballot(valid);
 #pragma unroll
     for (int b = 0; b < BITS; ++b) {
@@ -209,22 +260,22 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(const uint32_t* 
       match &= bit ? bb : ~bb;
     }
     const uint32_t rank = __popcll(match & lt_mask);
-    if (valid && rank == 0) wcnt[wave][d] = __popcll(match);
+    const uint32_t cnt = __popcll(match);
+    const bool leader = valid && rank == 0;
+    if (leader) wcnt[wave][d] = cnt;
     __syncthreads();
     if (valid) {
       uint32_t pre = 0;
       for (int w = 0; w < wave; ++w) pre += wcnt[w][d];
       const uint32_t pos = base[d] + pre + rank;
-      kout[pos] = key;
-      vout[pos] = val;
+      kout[pos] = key[r];
+      vout[pos] = val[r];
     }
     __syncthreads();
-    for (int dd = tid; dd < R; dd += kSortThreads) {
-      uint32_t tot = 0;
-      for (int w = 0; w < W; ++w) tot += wcnt[w][dd];
-      base[dd] += tot;
+    if (leader) {
+      atomicAdd(&base[d], cnt);
+      wcnt[wave][d] = 0;
     }
-    __syncthreads();
   }
 }
 
@@ -300,6 +351,18 @@ hipError_t launch_cell_keys(const float* x, const float* y, int n, const GridSca
                             uint32_t* vals, hipStream_t s) {
   if (n <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_cell_keys, dim3(div_up(n, 256)), dim3(256), 0, s, x, y, n, gs, keys, vals);
+  return hipGetLastError();
+}
+
+hipError_t bin_queries(const GridScalars* gs, const float* qx, const float* qy, int m, int64_t ncells, uint32_t* cnt,
+                       uint32_t* key, uint32_t* slot, uint32_t* scan_tmp, uint32_t* order, hipStream_t s) {
+  if (m <= 0) return hipSuccess;
+  const int64_t len = ncells + 1;
+  hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)div_up(len, 256)), dim3(256), 0, s, cnt, len, 0u);
+  hipLaunchKernelGGL(k_query_slots, dim3(div_up(m, 256)), dim3(256), 0, s, qx, qy, m, gs, cnt, key, slot);
+  hipError_t e = exclusive_scan_u32(cnt, cnt, (size_t)len, scan_tmp, nullptr, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_query_place, dim3(div_up(m, 256)), dim3(256), 0, s, key, slot, m, cnt, order);
   return hipGetLastError();
 }
 

@@ -44,6 +44,21 @@ struct View {
 // PAPER = true: the paper's stop rule instead (Section 3.2.4 and its Remark):
 // grow the level until the block holds >= k points, search one more level, stop.
 // Not exact in general; kept to measure that rule.
+// The largest over the LANES lanes of a query (an aligned group of LANES consecutive lanes)
+// of each lane's ceil(k / LANES)-th best d2 (+inf where a lane holds fewer):
+// the group holds at least k candidates at or below it, so the k-th nearest is no larger.
+template <int KMAX, int LANES>
+__device__ __forceinline__ double group_kth(const double (&bk)[KMAX], int k) {
+  const int kq = (k + LANES - 1) / LANES;  // the lane's kq-th best: slot KMAX - k + kq - 1
+  double v = bk[KMAX - 1];
+#pragma unroll
+  for (int s = 0; s < KMAX; ++s)
+    if (s == KMAX - k + kq - 1) v = bk[s];
+#pragma unroll
+  for (int o = 1; o < LANES; o <<= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
 template <int KMAX, int LANES = 1, bool PAPER = false>
 __device__ __forceinline__ void search(const View& g, const int32_t* __restrict__ cell_start,
                                        const float* __restrict__ sx, const float* __restrict__ sy,
@@ -65,6 +80,11 @@ __device__ __forceinline__ void search(const View& g, const int32_t* __restrict_
     bi[s] = pad ? -1 : INT32_MAX;
   }
   int count = 0;
+  // LANES > 1: an upper bound of the query's k-th (d2) over all lanes -- the largest of the
+  // lanes' ceil(k / LANES)-th values once every lane holds that many -- refreshed after each
+  // segment and never raised; a candidate above it cannot be among the k nearest, so it is
+  // not offered (a lane then keeps fewer than k, which the merge allows).
+  double bound = INFINITY;
   int final_level = -1;  // PAPER: the level after the one where the block first held >= k points
 
   for (int L = 0;; ++L) {
@@ -105,7 +125,7 @@ __device__ __forceinline__ void search(const View& g, const int32_t* __restrict_
         const double dy = (double)sy[p] - py;
         const double d2 = dx * dx + dy * dy;
         const int32_t id = sidx[p];
-        if (d2 < bk[KMAX - 1] || (d2 == bk[KMAX - 1] && id < bi[KMAX - 1])) {
+        if ((LANES == 1 || d2 <= bound) && (d2 < bk[KMAX - 1] || (d2 == bk[KMAX - 1] && id < bi[KMAX - 1]))) {
           bk[KMAX - 1] = d2;
           bi[KMAX - 1] = id;
 #pragma unroll
@@ -119,6 +139,10 @@ __device__ __forceinline__ void search(const View& g, const int32_t* __restrict_
             bi[s] = sw ? ihi : ilo;
           }
         }
+      }
+      if constexpr (LANES > 1) {
+        // the lanes of a query agree on p0, p1 and count, so this is uniform across them
+        if (p1 > p0 && count >= k) bound = fmin(bound, group_kth<KMAX, LANES>(bk, k));
       }
     }
     const bool open_l = cl > 0, open_r = cr < ncol - 1, open_b = rb > 0, open_t = rt < nrow - 1;
@@ -135,15 +159,7 @@ __device__ __forceinline__ void search(const View& g, const int32_t* __restrict_
       if (open_b) dout = fmin(dout, py - (minyd + (double)rb * cwd));
       if (open_t) dout = fmin(dout, (minyd + (double)(rt + 1) * cwd) - py);
       dout -= slack;
-      double kth = bk[KMAX - 1];
-      if constexpr (LANES > 1) {
-        const int kq = (k + LANES - 1) / LANES;  // the lane's kq-th best: slot KMAX - k + kq - 1
-#pragma unroll
-        for (int s = 0; s < KMAX; ++s)
-          if (s == KMAX - k + kq - 1) kth = bk[s];
-#pragma unroll
-        for (int o = 1; o < LANES; o <<= 1) kth = fmax(kth, __shfl_xor(kth, o, 64));
-      }
+      const double kth = LANES > 1 ? bound : bk[KMAX - 1];
       if (dout > 0.0 && kth < dout * dout) break;
     }
   }

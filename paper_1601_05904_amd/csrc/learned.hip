@@ -29,13 +29,14 @@ constexpr int kInPairs = 14;  // 27 inputs + one zero pad
 constexpr int kH = 64;
 constexpr int kHPairs = 32;
 
-__device__ inline uint32_t bf16_bits(float f) {
-  uint32_t u = __float_as_uint(f);
-  u += 0x7FFFu + ((u >> 16) & 1u);  // round to nearest, ties to even
-  return u >> 16;
+typedef float float2v_t __attribute__((ext_vector_type(2)));
+
+// float32 -> bfloat16, round to nearest, ties to even (the hardware conversion)
+__device__ inline uint32_t bf16_bits(float f) { return (uint32_t)__builtin_bit_cast(unsigned short, (__bf16)f); }
+__device__ inline float bf16_round(float f) { return (float)(__bf16)f; }
+__device__ inline uint32_t pack_bf16(float lo, float hi) {
+  return __builtin_bit_cast(uint32_t, __builtin_convertvector(float2v_t{lo, hi}, bf16x2_t));
 }
-__device__ inline float bf16_round(float f) { return __uint_as_float(bf16_bits(f) << 16); }
-__device__ inline uint32_t pack_bf16(float lo, float hi) { return bf16_bits(lo) | (bf16_bits(hi) << 16); }
 __device__ inline float dot2(uint32_t a, uint32_t b, float c) {
   return __builtin_amdgcn_fdot2_f32_bf16(__builtin_bit_cast(bf16x2_t, a), __builtin_bit_cast(bf16x2_t, b), c, false);
 }
@@ -48,9 +49,13 @@ __device__ inline float tanh_f(float v) {
   const float e = __builtin_amdgcn_exp2f(2.8853900817779268f * v);  // 2 / ln 2
   return 1.0f - 2.0f * __builtin_amdgcn_rcpf(e + 1.0f);
 }
+// 0.5 u (1 + tanh(v)), v = c (u + a u^3), evaluated as u - u / (1 + e^(2 v)) (the same
+// function): 2 v log2(e) = u (K1 + K2 u^2)
+constexpr float kGeluK1 = (float)(2.0 * 0.7978845608028654 * 1.4426950408889634);
+constexpr float kGeluK2 = (float)(2.0 * 0.7978845608028654 * 0.044715 * 1.4426950408889634);
 __device__ inline float gelu_f(float u) {
-  const float t = tanh_f(kGeluC * (u + kGeluA * u * u * u));
-  return 0.5f * u * (1.0f + t);
+  const float z = u * __builtin_fmaf(kGeluK2, u * u, kGeluK1);
+  return __builtin_fmaf(-u, __builtin_amdgcn_rcpf(__builtin_amdgcn_exp2f(z) + 1.0f), u);
 }
 __device__ inline float gelu_grad_f(float u) {
   const float t = tanh_f(kGeluC * (u + kGeluA * u * u * u));
@@ -556,9 +561,10 @@ __global__ __launch_bounds__(256) void k_mlp_forward_mfma(MlpDevice d, const flo
 
 // Fused front of the learned run for the queries at positions t of the order perm (may be
 // null): the 27 features (as k_features), the network, and the fallback rule; flag[t] = 1
-// marks a query that takes the exact kNN.  Lane
-// 16 g + c works on the query at position 16 tile + c: it computes features 8 g .. 8 g + 7,
-// and lanes g = 0, 1, 2 scan row r0 - 1 + g of the 3 x 3 block for the nearest distance.
+// marks a query that takes the exact kNN.  Lane 16 g + c works on the query at position
+// 16 tile + c: it computes features 8 g .. 8 g + 7, takes a quarter of the query's own cell
+// in the scan of the 3 x 3 block for the nearest distance, and one of its four neighbour
+// segments.
 __global__ __launch_bounds__(256) void k_learned_front(MlpDevice d, const GridScalars* __restrict__ gs,
                                                        const int32_t* __restrict__ cell_start,
                                                        const float* __restrict__ sx, const float* __restrict__ sy,
@@ -598,14 +604,19 @@ __global__ __launch_bounds__(256) void k_learned_front(MlpDevice d, const GridSc
     fy_next = q_next >= 0 ? qy[q_next] : miny;
     const float tx = (fx - minx) * inv, ty = (fy - miny) * inv;
     const int c0 = clamp_cell(tx, ncol), r0 = clamp_cell(ty, nrow);
-    // the 3 x 3 scan's bounds: row r0 - 1 + g, columns c0 - 1 .. c0 + 1 (clipped), for g < 3
-    const int rs = r0 - 1 + g;
-    const bool scan_row = g < 3 && rs >= 0 && rs < nrow;
+    // bounds of the nearest-point scan over the 3 x 3 block: the query's own cell (all four
+    // lanes), and neighbour segment g of lane g -- g = 0 / 1: row r0 - 1 / r0 + 1 (columns
+    // c0 - 1 .. c0 + 1, clipped), g = 2 / 3: the cell left / right of the query's
+    const int own = r0 * ncol + c0;
+    const int o0 = cell_start[own], o1 = cell_start[own + 1];
+    const int srow = g < 2 ? r0 - 1 + 2 * g : r0;
+    const int sa = g < 2 ? (c0 > 0 ? c0 - 1 : 0) : c0 + (g == 2 ? -1 : 1);
+    const int sb = g < 2 ? (c0 + 1 < ncol ? c0 + 1 : ncol - 1) : sa;
+    const bool seg = g < 2 ? (srow >= 0 && srow < nrow) : (sa >= 0 && sa < ncol);
     int p0 = 0, p1 = 0;
-    if (scan_row) {
-      const int ca = c0 > 0 ? c0 - 1 : 0, cb = c0 + 1 < ncol ? c0 + 1 : ncol - 1;
-      p0 = cell_start[rs * ncol + ca];
-      p1 = cell_start[rs * ncol + cb + 1];
+    if (seg) {
+      p0 = cell_start[srow * ncol + sa];
+      p1 = cell_start[srow * ncol + sb + 1];
     }
     // features 8 g .. 8 g + 7: counts of the 5 x 5 block (row-major), then the in-cell offset
     float f[8];
@@ -632,19 +643,50 @@ __global__ __launch_bounds__(256) void k_learned_front(MlpDevice d, const GridSc
       f[j] = v;
     }
     const float y = mlp_tile(d, net, lane, pack8(f));
-    // nearest point in the 3 x 3 block: row r0 - 1 + g for g < 3, then the minimum over the 4 lanes
+    // nearest point in the 3 x 3 block: the own cell split over the 4 lanes, then each lane's
+    // neighbour segment without the columns that cannot beat the own cell's nearest (cells
+    // widened by the binning slack), then the minimum over the 4 lanes.  float32 suffices:
+    // the value only sets the power-of-two scale of the pair weights; a coincident point
+    // (which lies in the own cell) is found exactly, as a zero difference.
     const double px = fx, py = fy;
-    double best = INFINITY;
-    if (scan_row) {
-      for (int p = p0; p < p1; ++p) {
-        const double dx = (double)sx[p] - px;
-        const double dy = (double)sy[p] - py;
-        const double d2 = dx * dx + dy * dy;
-        best = d2 < best ? d2 : best;
+    float best = INFINITY;
+    int hit = 0;
+    for (int p = o0 + g; p < o1; p += 4) {
+      const float dx = sx[p] - fx, dy = sy[p] - fy;
+      hit |= (dx == 0.0f) & (dy == 0.0f);
+      best = fminf(best, __builtin_fmaf(dx, dx, dy * dy));
+    }
+    best = fminf(best, __shfl_xor(best, 16, 64));
+    best = fminf(best, __shfl_xor(best, 32, 64));
+    if (seg && p1 > p0 && best < INFINITY) {
+      const double y0 = minyd + ((double)srow - slack_cells) * cwd;
+      const double y1 = minyd + ((double)srow + 1.0 + slack_cells) * cwd;
+      const double ey = py < y0 ? y0 - py : (py > y1 ? py - y1 : 0.0);
+      const double rem = (double)best - ey * ey;
+      if (!(rem >= 0.0)) {
+        p1 = p0;
+      } else {
+        const double r = sqrt(rem);
+        const double lo = floor((px - r - minxd) / cwd - 1.0 - slack_cells);
+        const double hi = ceil((px + r - minxd) / cwd + slack_cells);
+        if (!(lo <= (double)sb && hi >= (double)sa)) {
+          p1 = p0;
+        } else {
+          if (lo > (double)sa) p0 = cell_start[srow * ncol + (int)lo];
+          if (hi < (double)sb) p1 = cell_start[srow * ncol + (int)hi + 1];
+        }
       }
     }
-    best = fmin(best, __shfl_xor(best, 16, 64));
-    best = fmin(best, __shfl_xor(best, 32, 64));
+    if (seg) {
+      for (int p = p0; p < p1; ++p) {
+        const float dx = sx[p] - fx, dy = sy[p] - fy;
+        best = fminf(best, __builtin_fmaf(dx, dx, dy * dy));
+      }
+    }
+    best = fminf(best, __shfl_xor(best, 16, 64));
+    best = fminf(best, __shfl_xor(best, 32, 64));
+    hit |= __shfl_xor(hit, 16, 64);
+    hit |= __shfl_xor(hit, 32, 64);
     if (g != 0 || !valid) continue;
     double dout = INFINITY;
     if (c0 - 1 > 0) dout = fmin(dout, px - (minxd + (double)(c0 - 1) * cwd));
@@ -653,11 +695,11 @@ __global__ __launch_bounds__(256) void k_learned_front(MlpDevice d, const GridSc
     if (r0 + 1 < nrow - 1) dout = fmin(dout, (minyd + (double)(r0 + 2) * cwd) - py);
     dout -= slack_cells * cwd;
     double v;
-    if (dout == INFINITY || best < dout * dout)
-      v = best;                        // exact nearest distance
+    if (dout == INFINITY || (double)best < dout * dout)
+      v = best;                        // the nearest distance
     else
       v = dout > 0 ? dout * dout : 0;  // lower bound
-    const float d1 = v == 0.0 ? (best == 0.0 ? 0.0f : FLT_MIN) : fmaxf((float)v, FLT_MIN);
+    const float d1 = hit ? 0.0f : fmaxf((float)v, FLT_MIN);
     double alpha;
     const bool fall = decide_one((double)y, d1, ap, rule, delta, r_sat_lo, r_sat_hi, &alpha);
     flag[t] = fall ? 1u : 0u;
