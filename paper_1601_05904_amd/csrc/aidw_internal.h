@@ -84,6 +84,12 @@ hipError_t radix_sort_pairs(uint32_t* keys, uint32_t* vals, uint32_t* tmp_keys, 
 hipError_t radix_sort_pairs_to(uint32_t* keys, uint32_t* vals, uint32_t* tmp_keys, uint32_t* tmp_vals, int n, int bits,
                                uint32_t* hist, uint32_t* scan_tmp, hipStream_t s, uint32_t** out_keys,
                                uint32_t** out_vals);
+// The 10-bit passes of the same sort for the digits at shift0, shift0 + 10, ... below `bits`
+// (shift0 = 0 and bits = 10 is one pass; a later call with shift0 = 10 continues it on the
+// buffers the first call returned).
+hipError_t radix_sort_wide_from(uint32_t* keys, uint32_t* vals, uint32_t* tmp_keys, uint32_t* tmp_vals, int n,
+                                int shift0, int bits, uint32_t* hist, uint32_t* scan_tmp, hipStream_t s,
+                                uint32_t** out_keys, uint32_t** out_vals);
 // out[i] = in[0] + ... + in[i-1] (in and out may alias); *total (device, may be null) = the sum.
 // tmp needs scan_tmp_words(len) words.
 size_t scan_tmp_words(size_t len);
@@ -93,6 +99,10 @@ hipError_t exclusive_scan_u32(const uint32_t* in, uint32_t* out, size_t len, uin
 // ncells + 1 words, key and slot m words each, scan_tmp scan_tmp_words(ncells + 1).
 hipError_t bin_queries(const GridScalars* gs, const float* qx, const float* qy, int m, int64_t ncells, uint32_t* cnt,
                        uint32_t* key, uint32_t* slot, uint32_t* scan_tmp, uint32_t* order, hipStream_t s);
+// Order-preserving compaction of 0 / 1 flags: list[j] = vals[i] for the j-th flagged i;
+// *total (device) = the count.  tmp needs scan_tmp_words(len) words.
+hipError_t compact_flags(const uint32_t* flag, const uint32_t* vals, size_t len, uint32_t* tmp, uint32_t* list,
+                         uint32_t* total, hipStream_t s);
 hipError_t launch_cell_start_gather(const uint32_t* keys, const uint32_t* vals, int n, int64_t ncells, const float* x,
                                     const float* y, int32_t* cell_start, float* sx, float* sy, int32_t* sidx,
                                     hipStream_t s);
@@ -195,9 +205,6 @@ hipError_t launch_mlp_gradients(const MlpDevice& d, const float* feat, const flo
 hipError_t launch_adam(const MlpDevice& d, const float* grad, float lr, float b1, float b2, float eps, float bc1,
                        float bc2, hipStream_t s);
 hipError_t launch_accumulate_loss(const float* grad, float* epoch_loss, int epoch, float scale, hipStream_t s);
-// list[idx[t]] = perm[t] for flagged positions (idx = exclusive scan of flag).
-hipError_t launch_compact(const uint32_t* flag, const uint32_t* idx, const uint32_t* perm, int m, uint32_t* list,
-                          hipStream_t s);
 hipError_t launch_alpha_fallback(const uint32_t* perm, const uint32_t* count, int m, const float* r_obs,
                                  const AlphaParams& ap, float* alpha_f, hipStream_t s);
 // Pair-kernel class keys from a given alpha (alpha == p in 1..8 -> p, else 0) and the identity permutation.

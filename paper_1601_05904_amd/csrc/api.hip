@@ -206,6 +206,24 @@ int bits_for(int64_t ncells) {
 
 namespace {
 
+// Per host thread and device: a pinned landing slot for the grid scalars and an event.
+// Calls on one thread run one at a time, so the slot is free when a call starts.
+hipError_t scalar_staging(GridScalars** slot, hipEvent_t* ev) {
+  constexpr int kMaxDevices = 64;
+  thread_local GridScalars* pinned[kMaxDevices] = {};
+  thread_local hipEvent_t events[kMaxDevices] = {};
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  if (!pinned[dev] && (e = hipHostMalloc((void**)&pinned[dev], sizeof(GridScalars), hipHostMallocDefault)) != hipSuccess)
+    return e;
+  if (!events[dev] && (e = hipEventCreateWithFlags(&events[dev], hipEventDisableTiming)) != hipSuccess) return e;
+  *slot = pinned[dev];
+  *ev = events[dev];
+  return hipSuccess;
+}
+
 aidw_status build_grid_impl(const float* x, const float* y, int64_t n, const float* qx, const float* qy, int64_t m,
                             const aidw_params* p, hipStream_t s, bool async, aidw_grid** out) {
   aidw_grid* g = new aidw_grid();
@@ -219,18 +237,35 @@ aidw_status build_grid_impl(const float* x, const float* y, int64_t n, const flo
   hipError_t e = async ? dmalloc_async((void**)&g->dev, sizeof(GridScalars), s)
                        : dmalloc((void**)&g->dev, sizeof(GridScalars));
   if (e != hipSuccess) return cleanup(hip_fail(e, "allocating grid scalars"));
-  {
-    Temps t(s);
-    BoundsPartial* part = nullptr;
-    if ((e = t.get(&part, kBoundsBlocks)) != hipSuccess) return cleanup(hip_fail(e, "allocating bounds partials"));
-    if ((e = launch_bounds(x, y, (int)n, qx, qy, (int)m, part, s)) != hipSuccess)
-      return cleanup(hip_fail(e, "bounds kernel"));
-    if ((e = launch_finalize(part, kBoundsBlocks, n, p->area, p->cell_width, p->occupancy, g->dev, s)) != hipSuccess)
-      return cleanup(hip_fail(e, "finalize kernel"));
-    if ((e = hipMemcpyAsync(&g->host, g->dev, sizeof(GridScalars), hipMemcpyDeviceToHost, s)) != hipSuccess)
-      return cleanup(hip_fail(e, "reading grid scalars"));
-  }
-  if ((e = hipStreamSynchronize(s)) != hipSuccess) return cleanup(hip_fail(e, "synchronising grid scalars"));
+  // The host needs the cell count (to size the CSR array and the sort's passes) and the
+  // status.  The scalars are copied into pinned memory behind an event; the cell keys and
+  // the sort's first 10-bit pass, which do not depend on them, are queued before the host
+  // waits for that event, so the device keeps working while the host reads them.
+  GridScalars* pinned = nullptr;
+  hipEvent_t ready = nullptr;
+  if ((e = scalar_staging(&pinned, &ready)) != hipSuccess) return cleanup(hip_fail(e, "scalar staging"));
+  Temps t(s);
+  BoundsPartial* part = nullptr;
+  uint32_t *keys, *vals, *tk, *tv, *hist, *scan;
+  if ((e = t.get(&part, kBoundsBlocks)) != hipSuccess || (e = t.get(&keys, n)) != hipSuccess ||
+      (e = t.get(&vals, n)) != hipSuccess || (e = t.get(&tk, n)) != hipSuccess || (e = t.get(&tv, n)) != hipSuccess ||
+      (e = t.get(&hist, radix_hist_words((int)n))) != hipSuccess ||
+      (e = t.get(&scan, radix_scan_tmp_words((int)n))) != hipSuccess)
+    return cleanup(hip_fail(e, "allocating grid-build buffers"));
+  if ((e = launch_bounds(x, y, (int)n, qx, qy, (int)m, part, s)) != hipSuccess)
+    return cleanup(hip_fail(e, "bounds kernel"));
+  if ((e = launch_finalize(part, kBoundsBlocks, n, p->area, p->cell_width, p->occupancy, g->dev, s)) != hipSuccess)
+    return cleanup(hip_fail(e, "finalize kernel"));
+  if ((e = hipMemcpyAsync(pinned, g->dev, sizeof(GridScalars), hipMemcpyDeviceToHost, s)) != hipSuccess ||
+      (e = hipEventRecord(ready, s)) != hipSuccess)
+    return cleanup(hip_fail(e, "reading grid scalars"));
+  if ((e = launch_cell_keys(x, y, (int)n, g->dev, keys, vals, s)) != hipSuccess)
+    return cleanup(hip_fail(e, "cell key kernel"));
+  uint32_t *sk, *sv;  // the pairs sorted so far (in keys / vals or in the temporaries)
+  if ((e = radix_sort_wide_from(keys, vals, tk, tv, (int)n, 0, kRadixBitsWide, hist, scan, s, &sk, &sv)) != hipSuccess)
+    return cleanup(hip_fail(e, "radix sort"));
+  if ((e = hipEventSynchronize(ready)) != hipSuccess) return cleanup(hip_fail(e, "synchronising grid scalars"));
+  g->host = *pinned;
   const GridScalars& h = g->host;
   if (h.status == AIDW_ENONFINITE) return cleanup(fail(AIDW_ENONFINITE, "a coordinate is NaN or infinite"));
   if (h.status == AIDW_EDEGENERATE)
@@ -248,23 +283,15 @@ aidw_status build_grid_impl(const float* x, const float* y, int64_t n, const flo
       (e = alloc((void**)&g->sy, sizeof(float) * n)) != hipSuccess ||
       (e = alloc((void**)&g->sidx, sizeof(int32_t) * n)) != hipSuccess)
     return cleanup(hip_fail(e, "allocating grid arrays"));
-  {
-    Temps t(s);
-    uint32_t *keys, *vals, *tk, *tv, *hist, *scan;
-    if ((e = t.get(&keys, n)) != hipSuccess || (e = t.get(&vals, n)) != hipSuccess ||
-        (e = t.get(&tk, n)) != hipSuccess || (e = t.get(&tv, n)) != hipSuccess ||
-        (e = t.get(&hist, radix_hist_words((int)n))) != hipSuccess ||
-        (e = t.get(&scan, radix_scan_tmp_words((int)n))) != hipSuccess)
-      return cleanup(hip_fail(e, "allocating sort buffers"));
-    if ((e = launch_cell_keys(x, y, (int)n, g->dev, keys, vals, s)) != hipSuccess)
-      return cleanup(hip_fail(e, "cell key kernel"));
-    uint32_t *sk, *sv;  // the sorted pairs (in keys / vals or in the temporaries)
-    if ((e = radix_sort_pairs_to(keys, vals, tk, tv, (int)n, bits_for(ncells), hist, scan, s, &sk, &sv)) != hipSuccess)
-      return cleanup(hip_fail(e, "radix sort"));
-    if ((e = launch_cell_start_gather(sk, sv, (int)n, ncells, x, y, g->cell_start, g->sx, g->sy, g->sidx, s)) !=
-        hipSuccess)
-      return cleanup(hip_fail(e, "cell offsets / gather"));
-  }
+  // the remaining passes, on the buffers the first one left the pairs in
+  uint32_t* ok = sk == keys ? tk : keys;
+  uint32_t* ov = sv == vals ? tv : vals;
+  if ((e = radix_sort_wide_from(sk, sv, ok, ov, (int)n, kRadixBitsWide, bits_for(ncells), hist, scan, s, &sk, &sv)) !=
+      hipSuccess)
+    return cleanup(hip_fail(e, "radix sort"));
+  if ((e = launch_cell_start_gather(sk, sv, (int)n, ncells, x, y, g->cell_start, g->sx, g->sy, g->sidx, s)) !=
+      hipSuccess)
+    return cleanup(hip_fail(e, "cell offsets / gather"));
   *out = g;
   return AIDW_OK;
 }
@@ -884,7 +911,7 @@ aidw_status aidw_run_learned(const float* x, const float* y, const float* z, int
     // so the kNN kernel sees them binned as well (its locality depends on that order).
     float *d1sq = nullptr, *alpha_f = nullptr, *r_obs = nullptr;
     uint32_t *cnt = nullptr, *key = nullptr, *slot = nullptr, *scan = nullptr, *order = nullptr, *flag = nullptr,
-             *idx = nullptr, *list = nullptr, *stmp = nullptr, *count = nullptr;
+             *list = nullptr, *stmp = nullptr, *count = nullptr;
     const int mm = (int)m;
     const int64_t ncells = g->host.ncells;
     if (e == hipSuccess) e = t.get(&d1sq, mm);
@@ -896,7 +923,6 @@ aidw_status aidw_run_learned(const float* x, const float* y, const float* z, int
     if (e == hipSuccess) e = t.get(&scan, scan_tmp_words(ncells + 1));
     if (e == hipSuccess) e = t.get(&order, mm);
     if (e == hipSuccess) e = t.get(&flag, mm);
-    if (e == hipSuccess) e = t.get(&idx, mm);
     if (e == hipSuccess) e = t.get(&list, mm);
     if (e == hipSuccess) e = t.get(&stmp, scan_tmp_words(mm));
     if (e == hipSuccess) e = t.get(&count, 1);
@@ -917,8 +943,7 @@ aidw_status aidw_run_learned(const float* x, const float* y, const float* z, int
                               slack_cells(g->host), ap, rule, delta, r_sat_lo, r_sat_hi, flag, alpha_f, d1sq, r_hat_out,
                               stream),
          "features / network / decision kernel");
-    STEP(exclusive_scan_u32(flag, idx, mm, stmp, count, stream), "fallback scan");
-    STEP(launch_compact(flag, idx, order, mm, list, stream), "fallback compaction");
+    STEP(compact_flags(flag, order, mm, stmp, list, count, stream), "fallback compaction");
     // the fallback queries are few and hard (cluster edges): eight lanes per query measured best
     STEP(launch_knn_lanes(g->dev, g->cell_start, g->sx, g->sy, g->sidx, qx, qy, list, count, mm, p->k,
                           slack_cells(g->host), r_obs, d1sq, nullptr, 8, stream),

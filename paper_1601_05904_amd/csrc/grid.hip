@@ -216,6 +216,30 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_down(const uint32_t* __re
   }
 }
 
+// The last pass of an exclusive scan of 0 / 1 flags fused with the compaction it serves:
+// list[number of flagged positions before i] = vals[i] for each flagged i, in order, and
+// *total = the number of flagged positions.
+__global__ __launch_bounds__(kScanThreads) void k_scan_compact(const uint32_t* __restrict__ flag, size_t len,
+                                                               const uint32_t* __restrict__ sums,
+                                                               const uint32_t* __restrict__ vals,
+                                                               uint32_t* __restrict__ list,
+                                                               uint32_t* __restrict__ total) {
+  const size_t base = (size_t)blockIdx.x * kScanChunk + (size_t)threadIdx.x * kScanItems;
+  uint32_t v[kScanItems];
+  uint32_t s = 0;
+  for (int i = 0; i < kScanItems; ++i) {
+    v[i] = base + i < len ? flag[base + i] : 0u;
+    s += v[i];
+  }
+  uint32_t tot;
+  uint32_t run = sums[blockIdx.x] + block_exclusive_scan(s, &tot);
+  for (int i = 0; i < kScanItems; ++i) {
+    if (v[i]) list[run] = vals[base + i];
+    run += v[i];
+  }
+  if (base < len && len <= base + kScanItems) *total = run;  // the thread holding the last flag
+}
+
 // Stable scatter of one digit: within a block, elements are taken in index order,
 // one per thread per round; a wavefront ranks equal digits with ballots, waves
 // are ordered by an LDS prefix, rounds by a running per-digit base.  A thread's
@@ -372,18 +396,24 @@ size_t radix_scan_tmp_words(int n) { return (size_t)div_up((int64_t)radix_hist_w
 
 namespace {
 template <int BITS>
-hipError_t radix_sort_passes(uint32_t*& ki, uint32_t*& vi, uint32_t*& ko, uint32_t*& vo, int n, int bits,
-                             uint32_t* hist, uint32_t* scan_tmp, hipStream_t s) {
+void radix_pass(const uint32_t* ki, const uint32_t* vi, uint32_t* ko, uint32_t* vo, int n, int shift, uint32_t* hist,
+                uint32_t* scan_tmp, hipStream_t s) {
   const int nblocks = div_up(n, kSortTile);
   const size_t hlen = ((size_t)1 << BITS) * nblocks;
   const int nsb = div_up((int64_t)hlen, kScanChunk);
-  for (int shift = 0; shift < bits; shift += BITS) {
-    hipLaunchKernelGGL(k_radix_hist<BITS>, dim3(nblocks), dim3(kSortThreads), 0, s, ki, n, shift, hist, nblocks);
-    hipLaunchKernelGGL(k_scan_reduce, dim3(nsb), dim3(kScanThreads), 0, s, hist, hlen, scan_tmp);
-    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kScanThreads), 0, s, scan_tmp, nsb);
-    hipLaunchKernelGGL(k_scan_down, dim3(nsb), dim3(kScanThreads), 0, s, hist, hlen, scan_tmp, hist);
-    hipLaunchKernelGGL(k_radix_scatter<BITS>, dim3(nblocks), dim3(kSortThreads), 0, s, ki, vi, ko, vo, n, shift, hist,
-                       nblocks);
+  hipLaunchKernelGGL(k_radix_hist<BITS>, dim3(nblocks), dim3(kSortThreads), 0, s, ki, n, shift, hist, nblocks);
+  hipLaunchKernelGGL(k_scan_reduce, dim3(nsb), dim3(kScanThreads), 0, s, hist, hlen, scan_tmp);
+  hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kScanThreads), 0, s, scan_tmp, nsb);
+  hipLaunchKernelGGL(k_scan_down, dim3(nsb), dim3(kScanThreads), 0, s, hist, hlen, scan_tmp, hist);
+  hipLaunchKernelGGL(k_radix_scatter<BITS>, dim3(nblocks), dim3(kSortThreads), 0, s, ki, vi, ko, vo, n, shift, hist,
+                     nblocks);
+}
+
+template <int BITS>
+hipError_t radix_sort_passes(uint32_t*& ki, uint32_t*& vi, uint32_t*& ko, uint32_t*& vo, int n, int shift0, int bits,
+                             uint32_t* hist, uint32_t* scan_tmp, hipStream_t s) {
+  for (int shift = shift0; shift < bits; shift += BITS) {
+    radix_pass<BITS>(ki, vi, ko, vo, n, shift, hist, scan_tmp, s);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     uint32_t* t = ki;
@@ -397,6 +427,19 @@ hipError_t radix_sort_passes(uint32_t*& ki, uint32_t*& vi, uint32_t*& ko, uint32
 }
 }  // namespace
 
+hipError_t radix_sort_wide_from(uint32_t* keys, uint32_t* vals, uint32_t* tmp_keys, uint32_t* tmp_vals, int n,
+                                int shift0, int bits, uint32_t* hist, uint32_t* scan_tmp, hipStream_t s,
+                                uint32_t** out_keys, uint32_t** out_vals) {
+  *out_keys = keys;
+  *out_vals = vals;
+  if (n <= 1) return hipSuccess;
+  uint32_t *ki = keys, *vi = vals, *ko = tmp_keys, *vo = tmp_vals;
+  hipError_t e = radix_sort_passes<kRadixBitsWide>(ki, vi, ko, vo, n, shift0, bits, hist, scan_tmp, s);
+  *out_keys = ki;
+  *out_vals = vi;
+  return e;
+}
+
 hipError_t radix_sort_pairs_to(uint32_t* keys, uint32_t* vals, uint32_t* tmp_keys, uint32_t* tmp_vals, int n, int bits,
                                uint32_t* hist, uint32_t* scan_tmp, hipStream_t s, uint32_t** out_keys,
                                uint32_t** out_vals) {
@@ -406,8 +449,8 @@ hipError_t radix_sort_pairs_to(uint32_t* keys, uint32_t* vals, uint32_t* tmp_key
   uint32_t *ki = keys, *vi = vals, *ko = tmp_keys, *vo = tmp_vals;
   // 10-bit digits where they save a pass (each pass is five launches), 8-bit ones otherwise
   const bool wide = (bits + kRadixBitsWide - 1) / kRadixBitsWide < (bits + kRadixBits - 1) / kRadixBits;
-  hipError_t e = wide ? radix_sort_passes<kRadixBitsWide>(ki, vi, ko, vo, n, bits, hist, scan_tmp, s)
-                      : radix_sort_passes<kRadixBits>(ki, vi, ko, vo, n, bits, hist, scan_tmp, s);
+  hipError_t e = wide ? radix_sort_passes<kRadixBitsWide>(ki, vi, ko, vo, n, 0, bits, hist, scan_tmp, s)
+                      : radix_sort_passes<kRadixBits>(ki, vi, ko, vo, n, 0, bits, hist, scan_tmp, s);
   *out_keys = ki;
   *out_vals = vi;
   return e;
@@ -432,6 +475,16 @@ __global__ void k_scan_total(const uint32_t* __restrict__ in, const uint32_t* __
 }  // namespace
 
 size_t scan_tmp_words(size_t len) { return (len + kScanChunk - 1) / kScanChunk + 1; }
+
+hipError_t compact_flags(const uint32_t* flag, const uint32_t* vals, size_t len, uint32_t* tmp, uint32_t* list,
+                         uint32_t* total, hipStream_t s) {
+  if (len == 0) return hipSuccess;
+  const int nsb = (int)((len + kScanChunk - 1) / kScanChunk);
+  hipLaunchKernelGGL(k_scan_reduce, dim3(nsb), dim3(kScanThreads), 0, s, flag, len, tmp);
+  hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kScanThreads), 0, s, tmp, nsb);
+  hipLaunchKernelGGL(k_scan_compact, dim3(nsb), dim3(kScanThreads), 0, s, flag, len, tmp, vals, list, total);
+  return hipGetLastError();
+}
 
 hipError_t exclusive_scan_u32(const uint32_t* in, uint32_t* out, size_t len, uint32_t* tmp, uint32_t* total,
                               hipStream_t s) {

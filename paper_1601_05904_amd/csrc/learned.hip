@@ -436,14 +436,6 @@ __device__ inline bool decide_one(double R, float d1, const AlphaParams& ap, int
   return true;
 }
 
-__global__ __launch_bounds__(256) void k_compact(const uint32_t* __restrict__ flag, const uint32_t* __restrict__ idx,
-                                                 const uint32_t* __restrict__ perm, int m,
-                                                 uint32_t* __restrict__ list) {
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= m) return;
-  if (flag[t]) list[idx[t]] = perm[t];
-}
-
 // Eq. 4-6 for the fallback queries (the first *count entries of perm) from their exact r_obs.
 __global__ __launch_bounds__(256) void k_alpha_fallback(const uint32_t* __restrict__ perm,
                                                         const uint32_t* __restrict__ count,
@@ -801,13 +793,6 @@ hipError_t launch_adam(const MlpDevice& d, const float* grad, float lr, float b1
 
 hipError_t launch_accumulate_loss(const float* grad, float* epoch_loss, int epoch, float scale, hipStream_t s) {
   hipLaunchKernelGGL(k_accumulate_loss, dim3(1), dim3(64), 0, s, grad, epoch_loss, epoch, scale);
-  return hipGetLastError();
-}
-
-hipError_t launch_compact(const uint32_t* flag, const uint32_t* idx, const uint32_t* perm, int m, uint32_t* list,
-                          hipStream_t s) {
-  if (m <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_compact, dim3((m + 255) / 256), dim3(256), 0, s, flag, idx, perm, m, list);
   return hipGetLastError();
 }
 
