@@ -557,15 +557,13 @@ __global__ __launch_bounds__(256) void k_mlp_forward_mfma(MlpDevice d, const flo
 // 16 tile + c: it computes features 8 g .. 8 g + 7, takes a quarter of the query's own cell
 // in the scan of the 3 x 3 block for the nearest distance, and one of its four neighbour
 // segments.
-__global__ __launch_bounds__(256) void k_learned_front(MlpDevice d, const GridScalars* __restrict__ gs,
-                                                       const int32_t* __restrict__ cell_start,
-                                                       const float* __restrict__ sx, const float* __restrict__ sy,
-                                                       const float* __restrict__ qx, const float* __restrict__ qy,
-                                                       const uint32_t* __restrict__ perm, int m, double inv_occ,
-                                                       double slack_cells, AlphaParams ap, int rule, double delta,
-                                                       double r_sat_lo, double r_sat_hi, uint32_t* __restrict__ flag,
-                                                       float* __restrict__ alpha_f, float* __restrict__ d1sq,
-                                                       float* __restrict__ r_hat_out) {
+// Four wavefronts per SIMD (at most 128 registers per lane) hide more of the loads' latency.
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_learned_front(
+    MlpDevice d, const GridScalars* __restrict__ gs, const int32_t* __restrict__ cell_start,
+    const float* __restrict__ sx, const float* __restrict__ sy, const float* __restrict__ qx,
+    const float* __restrict__ qy, const uint32_t* __restrict__ perm, int m, double inv_occ, double slack_cells,
+    AlphaParams ap, int rule, double delta, double r_sat_lo, double r_sat_hi, uint32_t* __restrict__ flag,
+    float* __restrict__ alpha_f, float* __restrict__ d1sq, float* __restrict__ r_hat_out) {
   const int lane = threadIdx.x & 63, c = lane & 15, g = lane >> 4;
   __shared__ uint4 lds[kNetOperands];
   const MfmaNet net = stage_net(d, lds);
@@ -636,10 +634,10 @@ __global__ __launch_bounds__(256) void k_learned_front(MlpDevice d, const GridSc
     }
     const float y = mlp_tile(d, net, lane, pack8(f));
     // nearest point in the 3 x 3 block: the own cell split over the 4 lanes, then each lane's
-    // neighbour segment without the columns that cannot beat the own cell's nearest (cells
-    // widened by the binning slack), then the minimum over the 4 lanes.  float32 suffices:
-    // the value only sets the power-of-two scale of the pair weights; a coincident point
-    // (which lies in the own cell) is found exactly, as a zero difference.
+    // neighbour segment unless all of it lies farther than the own cell's nearest, then the
+    // minimum over the 4 lanes.  float32 suffices: the value only sets the power-of-two
+    // scale of the pair weights; a coincident point (which lies in the own cell) is found
+    // exactly, as a zero difference.
     const double px = fx, py = fy;
     float best = INFINITY;
     int hit = 0;
@@ -650,24 +648,15 @@ __global__ __launch_bounds__(256) void k_learned_front(MlpDevice d, const GridSc
     }
     best = fminf(best, __shfl_xor(best, 16, 64));
     best = fminf(best, __shfl_xor(best, 32, 64));
-    if (seg && p1 > p0 && best < INFINITY) {
-      const double y0 = minyd + ((double)srow - slack_cells) * cwd;
-      const double y1 = minyd + ((double)srow + 1.0 + slack_cells) * cwd;
-      const double ey = py < y0 ? y0 - py : (py > y1 ? py - y1 : 0.0);
-      const double rem = (double)best - ey * ey;
-      if (!(rem >= 0.0)) {
-        p1 = p0;
-      } else {
-        const double r = sqrt(rem);
-        const double lo = floor((px - r - minxd) / cwd - 1.0 - slack_cells);
-        const double hi = ceil((px + r - minxd) / cwd + slack_cells);
-        if (!(lo <= (double)sb && hi >= (double)sa)) {
-          p1 = p0;
-        } else {
-          if (lo > (double)sa) p0 = cell_start[srow * ncol + (int)lo];
-          if (hi < (double)sb) p1 = cell_start[srow * ncol + (int)hi + 1];
-        }
-      }
+    if (seg && best < INFINITY) {
+      // every point of lane g's segment lies beyond one side of the own cell, the segment's
+      // near edge moved toward the query by the binning slack: below it (g = 0), above (1),
+      // left (2) or right (3); e = the distance from the query to that edge
+      const double e = g == 0   ? py - (minyd + ((double)r0 + slack_cells) * cwd)
+                       : g == 1 ? (minyd + ((double)r0 + 1.0 - slack_cells) * cwd) - py
+                       : g == 2 ? px - (minxd + ((double)c0 + slack_cells) * cwd)
+                                : (minxd + ((double)c0 + 1.0 - slack_cells) * cwd) - px;
+      if (e > 0.0 && e * e > (double)best) p1 = p0;
     }
     if (seg) {
       for (int p = p0; p < p1; ++p) {
