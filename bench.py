@@ -11,11 +11,14 @@ Printed: one JSON line with the metric, the pair kernel's roofline fraction
 CPU oracle timed on a bounded sample of the same workload on this host, and
 the z error of the timed run on that sample.  Two more measurements ride on
 the same line: "learned_r" (plain vs learned-R on the clustered 2^20
-workload, after training the network on held-out sets) and "batch" (256
-independent jobs as one autotuned plan replayed as a HIP graph).
+workload, after training the network on held-out sets), "batch" (256
+independent jobs as one autotuned plan replayed as a HIP graph) and "clustered" (the
+2^18 mixture workload); the plain run also reports its grid and kNN stages against
+HBM ("stage_bandwidth") and a rate with host-memory copies included ("host_inclusive").
 
     python bench.py [--steps K] [--warmup W] [--workload uniform_1m] [--cpu-sample S] [--no-cpu-baseline]
-                    [--no-learned] [--no-batch] [--no-plain] [--batch-loop]
+                    [--no-learned] [--no-batch] [--no-plain] [--batch-loop] [--no-clustered]
+                    [--no-host-inclusive]
 """
 import argparse
 import json
@@ -61,7 +64,9 @@ def class_mix_peak(alpha, levels):
     return 1.0 / inv.mean(), {("alpha=%d" % p): float(np.mean(a == p)) for p in range(1, 9) if np.any(a == p)}
 
 
-PAIR_SOURCES = {"k_interp": ("interp.hip", "pair_core.h"), "k_b_interp": ("batch.hip", "pair_core.h")}
+PAIR_SOURCES = {"k_interp": ("interp.hip", "pair_core.h", "api.hip"), "k_b_interp": ("batch.hip", "pair_core.h"),
+                "grid_knn": ("grid.hip", "grid_core.h", "knn.hip", "knn_core.h", "interp.hip", "api.hip")}
+HBM_PEAK = 8.0e12  # MI355X HBM3E, bytes/s
 
 
 def source_hash(kernel):
@@ -81,15 +86,99 @@ def measured_traffic(kernel, workload):
     path = os.path.join(ROOT, "profiles", "%s_%s_counters.md" % (kernel, workload))
     if not os.path.exists(path):
         return None
+    fields = profile_fields(path)
+    if fields.get("source_sha256_16") != source_hash(kernel) or "traffic_bytes_per_launch" not in fields:
+        return None
+    return float(fields["traffic_bytes_per_launch"])
+
+
+def profile_fields(path):
+    """The "key: value" lines of a committed counter summary."""
     fields = {}
     with open(path) as f:
         for line in f:
             if ":" in line and not line.startswith(("|", "#", "`")):
                 k, v = line.split(":", 1)
                 fields[k.strip()] = v.strip()
-    if fields.get("source_sha256_16") != source_hash(kernel) or "traffic_bytes_per_launch" not in fields:
-        return None
-    return float(fields["traffic_bytes_per_launch"])
+    return fields
+
+
+def stage_bandwidth(grid, ds, stages):
+    """The grid and kNN stages against HBM.  Algorithmic bytes (minimum traffic of the step):
+    grid = 8 (n + m) bounds + 36 n (cell key and index written, sorted, gathered) + 8 nCells (CSR);
+    kNN = 8 m (queries) + 12 n (sorted x, y, index) + 4 nCells (cell offsets) + 12 m (r_obs, d1^2, alpha).
+    Both stages are latency-bound (sub-millisecond, dependent gathers); the measured bytes come from
+    the committed FETCH_SIZE / WRITE_SIZE summary when its sources are unchanged."""
+    n, m = ds.n, ds.m
+    ncells = grid["ncol"] * grid["nrow"]
+    alg = {"grid": 8 * (n + m) + 36 * n + 8 * ncells, "knn": 8 * m + 12 * n + 4 * ncells + 12 * m}
+    ms = {"grid": stages["grid_ms"], "knn": stages["knn_ms"]}
+    measured = {}
+    path = os.path.join(ROOT, "profiles", "grid_knn_%s_counters.md" % ds.name)
+    if os.path.exists(path):
+        f = profile_fields(path)
+        if f.get("source_sha256_16") == source_hash("grid_knn"):
+            measured = {"grid": float(f["grid_bytes_per_call"]), "knn": float(f["knn_bytes_per_call"])}
+    out = {"bound": "latency", "peak_GBps": HBM_PEAK / 1e9, "ncells": ncells,
+           "note": "the knn stage is query binning + kNN + Eq. 4-6 and the class keys"}
+    for st in ("grid", "knn"):
+        out[st] = {"ms": ms[st], "algorithmic_bytes": alg[st], "GBps": alg[st] / (ms[st] * 1e-3) / 1e9,
+                   "frac": alg[st] / (ms[st] * 1e-3) / HBM_PEAK,
+                   "measured_bytes": measured.get(st),
+                   "measured_GBps": measured[st] / (ms[st] * 1e-3) / 1e9 if st in measured else None}
+    return out
+
+
+def host_inclusive(ds, p, steps):
+    """points/s with the inputs in pinned host memory: copies in, aidw_run, the output copied back."""
+    import torch
+
+    import paper_1601_05904_amd as aidw
+    dev = torch.device("cuda", 0)
+    host = {k: torch.from_numpy(getattr(ds, k)).pin_memory() for k in ("x", "y", "z", "qx", "qy")}
+    back = torch.empty(ds.m, dtype=torch.float32).pin_memory()
+    stream = torch.cuda.current_stream()
+
+    def step():
+        d = {k: v.to(dev, non_blocking=True) for k, v in host.items()}
+        qz = aidw.run(d["x"], d["y"], d["z"], d["qx"], d["qy"], p, stream=stream)
+        back.copy_(qz, non_blocking=True)
+        torch.cuda.synchronize()
+    step()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    return {"value": ds.m / (ms * 1e-3), "unit": "points/s", "ms_per_step": ms, "steps": steps,
+            "note": "H2D of x, y, z, qx, qy and D2H of z from pinned host memory, included"}
+
+
+def clustered_measurement(args):
+    """The clustered workload (16-component mixture + background, uniform queries): points/s, the
+    pair kernels against their roofline, and the grid / kNN stages against HBM."""
+    import torch
+
+    import paper_1601_05904_amd as aidw
+    from paper_1601_05904_amd import workloads as W
+    ds = W.WORKLOADS["clustered_256k"]()
+    dev = torch.device("cuda", 0)
+    x, y, z, qx, qy = (torch.from_numpy(getattr(ds, k)).to(dev) for k in ("x", "y", "z", "qx", "qy"))
+    p = aidw.Params(k=ds.k, levels=ds.levels, r_min=ds.r_min, r_max=ds.r_max, occupancy=ds.occupancy)
+    qz = torch.empty(ds.m, dtype=torch.float32, device=dev)
+    stream = torch.cuda.current_stream()
+    ms, stages = timed_runs(lambda: aidw.run(x, y, z, qx, qy, p, out=qz, stream=stream), args.clustered_steps, 2)
+    _, alpha, _ = aidw.run(x, y, z, qx, qy, p, want_alpha=True, stream=stream)
+    peak, mix = class_mix_peak(alpha.cpu().numpy(), ds.levels)
+    pairs = float(ds.n) * float(ds.m)
+    achieved = pairs / (stages["interp_ms"] * 1e-3)
+    g = aidw.build_grid(x, y, qx, qy, p, stream=stream)
+    desc = g.describe()
+    g.close()
+    return {"workload": "clustered_256k", "n": ds.n, "m": ds.m, "k": ds.k, "value": ds.m / (ms * 1e-3),
+            "unit": "points/s", "ms_per_step": ms, "steps": args.clustered_steps, "stages_ms": stages,
+            "pairs_roofline": {"bound": "alu", "kernel": "k_interp", "achieved": achieved / 1e9, "peak": peak / 1e9,
+                               "unit": "Gpair/s", "frac": achieved / peak, "class_mix": mix},
+            "stage_bandwidth": stage_bandwidth(desc, ds, stages)}
 
 
 def parse():
@@ -108,6 +197,9 @@ def parse():
     ap.add_argument("--no-plain", action="store_true",
                     help="skip the headline plain run (profiling of the other legs only)")
     ap.add_argument("--batch-steps", type=int, default=10)
+    ap.add_argument("--no-clustered", action="store_true", help="skip the clustered 2^18 workload")
+    ap.add_argument("--clustered-steps", type=int, default=10)
+    ap.add_argument("--no-host-inclusive", action="store_true", help="skip the host-memory-inclusive timing")
     ap.add_argument("--batch-loop", action="store_true",
                     help="also time the same jobs as one aidw_run per job (context for the batched form)")
     ap.add_argument("--sweep", action="store_true",
@@ -353,6 +445,13 @@ def plain_measurement(args):
                      "peak_general_form": PEAK_GENERAL / 1e9, "units_per_launch": pairs},
     }
 
+    g = aidw.build_grid(x, y, qx, qy, p, stream=stream)
+    desc = g.describe()
+    g.close()
+    out["stage_bandwidth"] = stage_bandwidth(desc, ds, out["stages_ms"])
+    if not args.no_host_inclusive:
+        out["host_inclusive"] = host_inclusive(ds, p, 3)
+
     if not args.no_cpu_baseline:
         import oracle
         sel = W.sample_queries(ds.m, args.cpu_sample, ds.seed)
@@ -458,6 +557,8 @@ def main():
         out["learned_r"] = learned_comparison(args, with_oracle=not args.no_cpu_baseline)
     if not args.no_batch:
         out["batch"] = batch_measurement(args, with_oracle=not args.no_cpu_baseline)
+    if not args.no_clustered:
+        out["clustered"] = clustered_measurement(args)
     print(json.dumps(out))
 
 
