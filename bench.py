@@ -70,12 +70,17 @@ HBM_PEAK = 8.0e12  # MI355X HBM3E, bytes/s
 
 
 def source_hash(kernel):
-    """Fingerprint of the sources a pair kernel is built from (counter summaries record it)."""
+    """Fingerprint of the code a kernel is built from (counter summaries record it): the
+    sources with their // comments and blank lines removed, so comment edits keep it."""
     import hashlib
+    import re
     h = hashlib.sha256()
     for name in PAIR_SOURCES[kernel]:
-        with open(os.path.join(ROOT, "paper_1601_05904_amd", "csrc", name), "rb") as f:
-            h.update(f.read())
+        with open(os.path.join(ROOT, "paper_1601_05904_amd", "csrc", name)) as f:
+            for line in f:
+                code = re.sub(r"//.*", "", line).rstrip()
+                if code:
+                    h.update(code.encode() + b"\n")
     return h.hexdigest()[:16]
 
 
