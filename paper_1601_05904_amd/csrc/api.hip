@@ -337,9 +337,9 @@ void choose_interp_config(int64_t n, int64_t m, int* q, int* split) {
   // transcendental unit, and occupancy hides it better than in-lane ILP).  The data axis is
   // split as finely as the float64 partials allow: the largest power of two with at least
   // 2048 points per split, at most 256 splits and 16 split m bytes of partials <= 1 GiB.
-  // Each alpha class is its own launch over the class-sorted queries, so a small class
-  // fills the chip only through its splits (measured at 2^18 clustered: 8 splits 64 % of
-  // the roofline, 128 splits 82 %; at 2^20 uniform 32 -> 64 splits 86.0 -> 86.2 %).
+  // Fine splits keep the chip full when the queries are few (measured at 2^18 clustered
+  // with one launch per class: 8 splits 64 % of the roofline, 128 splits 82 %; at 2^20
+  // uniform 32 -> 64 splits 86.0 -> 86.2 %).
   const int qq = g_cfg_q ? g_cfg_q : 1;
   int sp = 1;
   if (g_cfg_split) {

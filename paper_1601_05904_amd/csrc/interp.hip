@@ -25,10 +25,10 @@
 // weight is w = (d1 / d)^p = r^p with r = rsq(t): one transcendental and a few
 // multiplies instead of log2 + exp2.  A prologue kernel evaluates Eq. 4-6 per
 // query and keys each query by its class (p in 1..8 when alpha == p exactly,
-// else 0); a stable sort by key groups the classes, and one launch per class
-// takes the blocks whose queries all share that class, the general kernel the
-// rest.  Which path a query takes depends only on the inputs, so results stay
-// deterministic.
+// else 0); a sort by key groups the classes, and in the one pair launch a block
+// whose queries all share an integer class runs that class's loop, any other
+// block the general loop.  Which path a query takes depends only on the inputs,
+// so results stay deterministic.
 #include <float.h>
 
 #include "aidw_internal.h"
@@ -73,26 +73,16 @@ __global__ __launch_bounds__(256) void k_class_keys(const float* __restrict__ al
   vals[q] = (uint32_t)q;
 }
 
-// Queries are taken in class order: slot (block, j, thread) -> position -> query perm[position].
-// A class launch (POW > 0) takes only blocks whose queries all have key POW; the general launch
-// (POW == 0) skips the blocks that a class launch takes (fast_mask bit set for that key).
+// One block: the Q * kThreads queries at positions pos0 ... of the class order (slot (j,
+// thread) -> position -> query perm[position]) against the data range of split blockIdx.y,
+// with the power-POW weight (POW = 0: general alpha).
 template <int Q, int POW>
-__global__ __launch_bounds__(kThreads) void k_interp(const float* __restrict__ x, const float* __restrict__ y,
-                                                     const float* __restrict__ z, int n, int chunk,
-                                                     const float* __restrict__ qx, const float* __restrict__ qy,
-                                                     const float* __restrict__ alpha_f,
-                                                     const float* __restrict__ d1sq,
-                                                     const uint32_t* __restrict__ perm,
-                                                     const uint32_t* __restrict__ skeys, int m, uint32_t fast_mask,
-                                                     float* __restrict__ qz, double2* __restrict__ partial) {
-  const int pos0 = blockIdx.x * kThreads * Q;
-  const int posl = min(m, pos0 + kThreads * Q) - 1;
-  const uint32_t k0 = skeys[pos0], kl = skeys[posl];
-  if constexpr (POW > 0) {
-    if (k0 != (uint32_t)POW || kl != (uint32_t)POW) return;
-  } else {
-    if (k0 == kl && ((fast_mask >> k0) & 1u)) return;
-  }
+__device__ __forceinline__ void interp_block(const float* __restrict__ x, const float* __restrict__ y,
+                                             const float* __restrict__ z, int n, int chunk,
+                                             const float* __restrict__ qx, const float* __restrict__ qy,
+                                             const float* __restrict__ alpha_f, const float* __restrict__ d1sq,
+                                             const uint32_t* __restrict__ perm, int m, int pos0,
+                                             float* __restrict__ qz, double2* __restrict__ partial) {
   Lane<Q, POW> L;
   const int split = blockIdx.y;
   uint32_t qid[Q];
@@ -120,6 +110,42 @@ __global__ __launch_bounds__(kThreads) void k_interp(const float* __restrict__ x
       qz[qid[j]] = (float)(num / den);
     else
       partial[(size_t)split * m + qid[j]] = make_double2(num, den);
+  }
+}
+
+// The pair kernel, one launch for every alpha class: a block whose queries all have the
+// integer class p (fast_mask bit p set) runs the power-p loop, any other block (general
+// alpha, or a block that spans two classes) the general loop.  Class 0 sorts first, so the
+// costlier general blocks are dispatched first.
+template <int Q>
+__global__ __launch_bounds__(kThreads) void k_interp(const float* __restrict__ x, const float* __restrict__ y,
+                                                     const float* __restrict__ z, int n, int chunk,
+                                                     const float* __restrict__ qx, const float* __restrict__ qy,
+                                                     const float* __restrict__ alpha_f,
+                                                     const float* __restrict__ d1sq,
+                                                     const uint32_t* __restrict__ perm,
+                                                     const uint32_t* __restrict__ skeys, int m, uint32_t fast_mask,
+                                                     float* __restrict__ qz, double2* __restrict__ partial) {
+  const int pos0 = blockIdx.x * kThreads * Q;
+  const int posl = min(m, pos0 + kThreads * Q) - 1;
+  const uint32_t k0 = skeys[pos0], kl = skeys[posl];
+  const uint32_t cls = (k0 == kl && ((fast_mask >> k0) & 1u)) ? k0 : 0u;
+  switch (cls) {
+#define AIDW_CASE(P)                                                                                        \
+  case P:                                                                                                   \
+    interp_block<Q, P>(x, y, z, n, chunk, qx, qy, alpha_f, d1sq, perm, m, pos0, qz, partial);               \
+    break;
+    AIDW_CASE(1)
+    AIDW_CASE(2)
+    AIDW_CASE(3)
+    AIDW_CASE(4)
+    AIDW_CASE(5)
+    AIDW_CASE(6)
+    AIDW_CASE(7)
+    AIDW_CASE(8)
+#undef AIDW_CASE
+    default:
+      interp_block<Q, 0>(x, y, z, n, chunk, qx, qy, alpha_f, d1sq, perm, m, pos0, qz, partial);
   }
 }
 
@@ -255,27 +281,12 @@ hipError_t launch_class_keys(const float* alpha_f, int m, uint32_t* keys, uint32
 
 namespace {
 
-template <int Q, int POW>
-void launch_one(dim3 grid, hipStream_t s, const float* x, const float* y, const float* z, int n, int chunk,
-                const float* qx, const float* qy, const float* alpha_f, const float* d1sq, const uint32_t* perm,
-                const uint32_t* skeys, int m, uint32_t mask, float* qz, double2* partial) {
-  hipLaunchKernelGGL((k_interp<Q, POW>), grid, dim3(kThreads), 0, s, x, y, z, n, chunk, qx, qy, alpha_f, d1sq, perm,
-                     skeys, m, mask, qz, partial);
-}
-
 template <int Q>
 hipError_t launch_q(dim3 grid, hipStream_t s, const float* x, const float* y, const float* z, int n, int chunk,
                     const float* qx, const float* qy, const float* alpha_f, const float* d1sq, const uint32_t* perm,
                     const uint32_t* skeys, int m, uint32_t mask, float* qz, double2* partial) {
-  launch_one<Q, 0>(grid, s, x, y, z, n, chunk, qx, qy, alpha_f, d1sq, perm, skeys, m, mask, qz, partial);
-  if (mask & (1u << 1)) launch_one<Q, 1>(grid, s, x, y, z, n, chunk, qx, qy, alpha_f, d1sq, perm, skeys, m, mask, qz, partial);
-  if (mask & (1u << 2)) launch_one<Q, 2>(grid, s, x, y, z, n, chunk, qx, qy, alpha_f, d1sq, perm, skeys, m, mask, qz, partial);
-  if (mask & (1u << 3)) launch_one<Q, 3>(grid, s, x, y, z, n, chunk, qx, qy, alpha_f, d1sq, perm, skeys, m, mask, qz, partial);
-  if (mask & (1u << 4)) launch_one<Q, 4>(grid, s, x, y, z, n, chunk, qx, qy, alpha_f, d1sq, perm, skeys, m, mask, qz, partial);
-  if (mask & (1u << 5)) launch_one<Q, 5>(grid, s, x, y, z, n, chunk, qx, qy, alpha_f, d1sq, perm, skeys, m, mask, qz, partial);
-  if (mask & (1u << 6)) launch_one<Q, 6>(grid, s, x, y, z, n, chunk, qx, qy, alpha_f, d1sq, perm, skeys, m, mask, qz, partial);
-  if (mask & (1u << 7)) launch_one<Q, 7>(grid, s, x, y, z, n, chunk, qx, qy, alpha_f, d1sq, perm, skeys, m, mask, qz, partial);
-  if (mask & (1u << 8)) launch_one<Q, 8>(grid, s, x, y, z, n, chunk, qx, qy, alpha_f, d1sq, perm, skeys, m, mask, qz, partial);
+  hipLaunchKernelGGL((k_interp<Q>), grid, dim3(kThreads), 0, s, x, y, z, n, chunk, qx, qy, alpha_f, d1sq, perm, skeys,
+                     m, mask, qz, partial);
   return hipGetLastError();
 }
 
