@@ -28,6 +28,24 @@ struct BoundsPartial {
   int32_t pad[3];
 };
 
+// Length of the register k-list of the kNN kernels for a given k: the insertion of a
+// candidate runs one compare-and-swap step per slot, so the list is kept close to k.
+__host__ __device__ inline int knn_slots(int k) {
+  return k <= 8 ? 8 : k <= 10 ? 10 : k <= 12 ? 12 : k <= 16 ? 16 : k <= 24 ? 24 : k <= 32 ? 32 : k <= 48 ? 48 : 64;
+}
+// M(KMAX) for the list length of k (a statement).
+#define AIDW_FOR_KNN_SLOTS(k, M)   \
+  switch (::aidw::knn_slots(k)) {  \
+    case 8: M(8); break;           \
+    case 10: M(10); break;         \
+    case 12: M(12); break;         \
+    case 16: M(16); break;         \
+    case 24: M(24); break;         \
+    case 32: M(32); break;         \
+    case 48: M(48); break;         \
+    default: M(64); break;         \
+  }
+
 // Slack, in cells, that covers the float32 binning error of a coordinate in a
 // grid of ncol x nrow cells: |fl(fl(x - minX) * inv) - (x - minX) * inv| <= (c + 1) * 2^-23
 // for column c, taken with a wide margin.

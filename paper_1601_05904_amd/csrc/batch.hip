@@ -492,7 +492,7 @@ aidw_status create_plan(const aidw_job* jobs, int32_t njobs, const aidw_batch_co
   uint32_t mask = 0;  // union of the jobs' integer levels
   double pairs = 0.0;
   const int qb = pair::kThreads * cfg.q;
-  auto kclass = [](int k) { return k <= 8 ? 8 : k <= 16 ? 16 : k <= 32 ? 32 : 64; };
+  auto kclass = [](int k) { return knn_slots(k); };
   for (int j = 0; j < njobs; ++j) {
     const aidw_job& a = jobs[j];
     if (a.n < 1) return fail(AIDW_EINVAL, "job %d: n must be >= 1", j);
@@ -740,12 +740,9 @@ aidw_status enqueue(aidw_batch* b, hipStream_t s, bool timed) {
     STEP(radix_sort_pairs(b->qkeys, b->qperm, b->tkeys, b->tvals, b->sum_m, b->cell_bits, b->hist, b->scan_tmp, s),
          "binning the queries");
     for (const auto& r : b->knn_ranges) {
-      switch (r.kmax) {
-        case 8: launch_b_knn<8>(b, r.t_begin, r.t_end, s); break;
-        case 16: launch_b_knn<16>(b, r.t_begin, r.t_end, s); break;
-        case 32: launch_b_knn<32>(b, r.t_begin, r.t_end, s); break;
-        default: launch_b_knn<64>(b, r.t_begin, r.t_end, s); break;
-      }
+#define AIDW_B_KNN(K) launch_b_knn<K>(b, r.t_begin, r.t_end, s)
+      AIDW_FOR_KNN_SLOTS(r.kmax, AIDW_B_KNN)
+#undef AIDW_B_KNN
     }
     STEP(hipSuccess, "kNN search");
     const bool classes = b->fast_mask != 0;

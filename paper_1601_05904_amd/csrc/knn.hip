@@ -192,15 +192,10 @@ hipError_t launch_knn_lanes(const GridScalars* gs, const int32_t* cell_start, co
 #define AIDW_KNNL(K, LN)                                                                                         \
   hipLaunchKernelGGL((k_knn_lanes<K, LN>), grid, block, 0, s, gs, cell_start, sx, sy, sidx, qx, qy, qperm, active, \
                      m, k, slack_cells, r_obs, d1sq, nn_idx)
-#define AIDW_KNNL_K(LN)   \
-  if (k <= 8)             \
-    AIDW_KNNL(8, LN);     \
-  else if (k <= 16)       \
-    AIDW_KNNL(16, LN);    \
-  else if (k <= 32)       \
-    AIDW_KNNL(32, LN);    \
-  else                    \
-    AIDW_KNNL(64, LN)
+#define AIDW_KNNL_2(K) AIDW_KNNL(K, 2)
+#define AIDW_KNNL_4(K) AIDW_KNNL(K, 4)
+#define AIDW_KNNL_8(K) AIDW_KNNL(K, 8)
+#define AIDW_KNNL_K(LN) AIDW_FOR_KNN_SLOTS(k, AIDW_KNNL_##LN)
   if (lanes == 2) {
     AIDW_KNNL_K(2);
   } else if (lanes == 4) {
@@ -209,6 +204,9 @@ hipError_t launch_knn_lanes(const GridScalars* gs, const int32_t* cell_start, co
     AIDW_KNNL_K(8);
   }
 #undef AIDW_KNNL_K
+#undef AIDW_KNNL_8
+#undef AIDW_KNNL_4
+#undef AIDW_KNNL_2
 #undef AIDW_KNNL
   return hipGetLastError();
 }
@@ -227,18 +225,11 @@ hipError_t launch_knn(const GridScalars* gs, const int32_t* cell_start, const fl
                       int32_t* nn_idx, hipStream_t s) {
   if (m <= 0) return hipSuccess;
   const dim3 grid((m + 255) / 256), block(256);
-  if (k <= 8)
-    hipLaunchKernelGGL(k_knn<8>, grid, block, 0, s, gs, cell_start, sx, sy, sidx, qx, qy, qperm, active, m, k, slack_cells,
-                       r_obs, d1sq, nn_idx);
-  else if (k <= 16)
-    hipLaunchKernelGGL(k_knn<16>, grid, block, 0, s, gs, cell_start, sx, sy, sidx, qx, qy, qperm, active, m, k, slack_cells,
-                       r_obs, d1sq, nn_idx);
-  else if (k <= 32)
-    hipLaunchKernelGGL(k_knn<32>, grid, block, 0, s, gs, cell_start, sx, sy, sidx, qx, qy, qperm, active, m, k, slack_cells,
-                       r_obs, d1sq, nn_idx);
-  else
-    hipLaunchKernelGGL(k_knn<64>, grid, block, 0, s, gs, cell_start, sx, sy, sidx, qx, qy, qperm, active, m, k, slack_cells,
-                       r_obs, d1sq, nn_idx);
+#define AIDW_KNN1(K)                                                                                              \
+  hipLaunchKernelGGL(k_knn<K>, grid, block, 0, s, gs, cell_start, sx, sy, sidx, qx, qy, qperm, active, m, k, \
+                     slack_cells, r_obs, d1sq, nn_idx)
+  AIDW_FOR_KNN_SLOTS(k, AIDW_KNN1)
+#undef AIDW_KNN1
   return hipGetLastError();
 }
 
