@@ -108,8 +108,10 @@ typedef struct {
  * so that each cell is one contiguous segment ordered by original index and
  * is described by two integers (Section 3.2.3: head and size, stored here as
  * CSR offsets cell_start[c] .. cell_start[c + 1]).
- * Synchronises the stream once (to size the grid from the device-computed
- * bounds).  On success *out owns device memory until aidw_grid_destroy.
+ * Waits once for the device-computed scalars (an event behind their copy to the
+ * host: the grid's size depends on the bounds); the cell keys and the sort's
+ * first pass are queued before that wait.  On success *out owns device memory
+ * until aidw_grid_destroy.
  * Errors: AIDW_EINVAL (null pointers, n < 1, m < 0, sizes > INT32_MAX, invalid p),
  * AIDW_ENONFINITE (a NaN / inf coordinate), AIDW_EDEGENERATE (A <= 0),
  * AIDW_ECAPACITY (more than AIDW_MAX_CELLS cells), AIDW_ENOMEM, AIDW_EDEVICE.
@@ -119,6 +121,12 @@ aidw_status aidw_build_grid(const float* x, const float* y, int64_t n, const flo
 
 /* Copies the grid's description to *out (host only, no GPU work). */
 aidw_status aidw_grid_describe(const aidw_grid* g, aidw_grid_desc* out);
+
+/* The scalars of Eq. 2 and the grid's shape (host only, no GPU work): A, r_exp,
+ * the cell width (float64) and nCol, nRow.  Any output pointer may be NULL.
+ * Errors: AIDW_EINVAL (g NULL). */
+aidw_status aidw_grid_info(const aidw_grid* g, double* area, double* r_exp, double* cell_width, int32_t* ncol,
+                           int32_t* nrow);
 
 /* Device pointers of the grid's arrays (library-owned, read-only, valid until
  * aidw_grid_destroy): cell_start [ncol*nrow + 1] int32 CSR offsets;

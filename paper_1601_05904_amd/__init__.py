@@ -131,6 +131,7 @@ def load(build_if_missing: bool = True):
     L.aidw_params_default.restype = None
     L.aidw_build_grid.argtypes = [_VP, _VP, i64, _VP, _VP, i64, P(_Params), _VP, P(_VP)]
     L.aidw_grid_describe.argtypes = [_VP, P(_GridDesc)]
+    L.aidw_grid_info.argtypes = [_VP, P(ctypes.c_double), P(ctypes.c_double), P(ctypes.c_double), P(i32), P(i32)]
     L.aidw_grid_arrays.argtypes = [_VP, P(_VP), P(_VP), P(_VP), P(_VP)]
     L.aidw_grid_copy_arrays.argtypes = [_VP, _VP, _VP, _VP, _VP, _VP]
     L.aidw_grid_destroy.argtypes = [_VP]
@@ -179,7 +180,7 @@ def load(build_if_missing: bool = True):
     L.aidw_batch_destroy.restype = None
     L.aidw_run_batch.argtypes = [P(_Job), i32, P(_BatchConfig), P(i32), _VP]
     L.aidw_batch_tune.argtypes = [P(_Job), i32, P(_BatchConfig), i32, i32, P(ctypes.c_float), _VP]
-    for name in ("aidw_build_grid", "aidw_grid_describe", "aidw_grid_arrays", "aidw_grid_copy_arrays", "aidw_knn",
+    for name in ("aidw_build_grid", "aidw_grid_describe", "aidw_grid_info", "aidw_grid_arrays", "aidw_grid_copy_arrays", "aidw_knn",
                  "aidw_interpolate", "aidw_run", "aidw_knn_paper", "aidw_knn_bruteforce", "aidw_interpolate_naive",
                  "aidw_set_timing", "aidw_last_timing", "aidw_set_interp_config",
                  "aidw_mlp_create", "aidw_mlp_set_params", "aidw_mlp_get_params", "aidw_mlp_save", "aidw_mlp_load",
@@ -237,6 +238,14 @@ class Grid:
         d = _GridDesc()
         _check(load().aidw_grid_describe(self.handle, ctypes.byref(d)))
         return {f: getattr(d, f) for f, _ in _GridDesc._fields_}
+
+    def info(self) -> dict:
+        """aidw_grid_info: A, r_exp, the cell width and the grid's shape."""
+        a, r, c = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+        nc, nr = ctypes.c_int32(), ctypes.c_int32()
+        _check(load().aidw_grid_info(self.handle, ctypes.byref(a), ctypes.byref(r), ctypes.byref(c), ctypes.byref(nc),
+                                     ctypes.byref(nr)))
+        return {"area": a.value, "r_exp": r.value, "cell_width": c.value, "ncol": nc.value, "nrow": nr.value}
 
     def arrays(self, stream=None):
         """Copies (cell_start, sx, sy, sidx) into new device tensors."""

@@ -533,6 +533,17 @@ aidw_status aidw_grid_describe(const aidw_grid* g, aidw_grid_desc* out) {
   return AIDW_OK;
 }
 
+aidw_status aidw_grid_info(const aidw_grid* g, double* area, double* r_exp, double* cell_width, int32_t* ncol,
+                           int32_t* nrow) {
+  if (!g) return fail(AIDW_EINVAL, "grid is NULL");
+  if (area) *area = g->host.area;
+  if (r_exp) *r_exp = g->host.r_exp;
+  if (cell_width) *cell_width = g->host.cw;
+  if (ncol) *ncol = g->host.ncol;
+  if (nrow) *nrow = g->host.nrow;
+  return AIDW_OK;
+}
+
 aidw_status aidw_grid_arrays(const aidw_grid* g, const int32_t** cell_start, const float** sx, const float** sy,
                              const int32_t** sidx) {
   if (!g) return fail(AIDW_EINVAL, "grid is NULL");

@@ -74,6 +74,7 @@ def test_other_entry_points_validate(L):
     assert L.aidw_interpolate(FAKE, FAKE, FAKE, 10, FAKE, FAKE, 5, None, FAKE, _p(), None, FAKE, None,
                               None) == aidw.EINVAL
     assert L.aidw_grid_describe(None, None) == aidw.EINVAL
+    assert L.aidw_grid_info(None, None, None, None, None, None) == aidw.EINVAL
     assert L.aidw_set_interp_config(3, 0, -1) == aidw.EINVAL
     assert L.aidw_set_interp_config(0, 0, 2) == aidw.EINVAL
     assert L.aidw_set_interp_config(0, 0, -1) == aidw.OK

@@ -68,6 +68,8 @@ def _check_grid(T, ds, params):
     assert d["area"] == gp["area"] and d["r_exp"] == gp["r_exp"] and d["cell_width"] == gp["cw"]
     assert np.float32(d["inv_cell_width"]) == gp["inv_cw"]
     assert (d["ncol"], d["nrow"]) == (gp["ncol"], gp["nrow"])
+    assert g.info() == {"area": gp["area"], "r_exp": gp["r_exp"], "cell_width": gp["cw"], "ncol": gp["ncol"],
+                        "nrow": gp["nrow"]}
     cs, sx, sy, si = (a.cpu().numpy() for a in g.arrays())
     cells = O.cell_index(ds.x, ds.y, b[0], b[1], gp["inv_cw"], gp["ncol"], gp["nrow"])
     counts = np.bincount(cells, minlength=gp["ncol"] * gp["nrow"])
