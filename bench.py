@@ -12,13 +12,14 @@ CPU oracle timed on a bounded sample of the same workload on this host, and
 the z error of the timed run on that sample.  Two more measurements ride on
 the same line: "learned_r" (plain vs learned-R on the clustered 2^20
 workload, after training the network on held-out sets), "batch" (256
-independent jobs as one autotuned plan replayed as a HIP graph) and "clustered" (the
-2^18 mixture workload); the plain run also reports its grid and kNN stages against
+independent jobs as one autotuned plan replayed as a HIP graph) "clustered" (the
+2^18 mixture workload) and "paper_rule" (the paper's kNN stop rule against exact kNN);
+the plain run also reports its grid and kNN stages against
 HBM ("stage_bandwidth") and a rate with host-memory copies included ("host_inclusive").
 
     python bench.py [--steps K] [--warmup W] [--workload uniform_1m] [--cpu-sample S] [--no-cpu-baseline]
                     [--no-learned] [--no-batch] [--no-plain] [--batch-loop] [--no-clustered]
-                    [--no-host-inclusive]
+                    [--no-host-inclusive] [--no-paper-rule]
 """
 import argparse
 import json
@@ -186,6 +187,40 @@ def clustered_measurement(args):
             "stage_bandwidth": stage_bandwidth(desc, ds, stages)}
 
 
+def paper_rule_measurement(args):
+    """The paper's "+1 level" stop rule (aidw_knn_paper) against the exact kNN (aidw_knn, equal to
+    brute force bit for bit) on the uniform 4096, uniform 2^20 and clustered 2^18 workloads, at the
+    paper's cell width (cw = r_exp: 0.25 points per cell) and at 2 points per cell: queries whose
+    neighbour set differs, the largest relative r_obs error, and both kernels' stage times."""
+    import torch
+
+    import paper_1601_05904_amd as aidw
+    from paper_1601_05904_amd import workloads as W
+    rows = []
+    for wl in ("uniform_4k", "uniform_1m", "clustered_256k"):
+        ds = W.WORKLOADS[wl]()
+        x, y, qx, qy = (torch.from_numpy(getattr(ds, a)).cuda() for a in ("x", "y", "qx", "qy"))
+        for occ in (0.25, 2.0):
+            p = aidw.Params(k=ds.k, occupancy=occ)
+            g = aidw.build_grid(x, y, qx, qy, p)
+            ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+            aidw.knn(g, qx, qy, ds.k, want_idx=True)
+            aidw.knn(g, qx, qy, ds.k, want_idx=True, paper_rule=True)
+            ev[0].record()
+            re, _, ie = aidw.knn(g, qx, qy, ds.k, want_idx=True)
+            ev[1].record()
+            rp, _, ip = aidw.knn(g, qx, qy, ds.k, want_idx=True, paper_rule=True)
+            ev[2].record()
+            torch.cuda.synchronize()
+            g.close()
+            differ = (ie != ip).any(dim=1)
+            rel = ((rp.double() - re.double()).abs() / re.double()).max().item()
+            rows.append({"workload": wl, "n": ds.n, "m": ds.m, "k": ds.k, "occupancy": occ,
+                         "queries_differing": int(differ.sum().item()), "max_rel_r_obs_error": rel,
+                         "exact_ms": ev[0].elapsed_time(ev[1]), "paper_rule_ms": ev[1].elapsed_time(ev[2])})
+    return rows
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -203,6 +238,7 @@ def parse():
                     help="skip the headline plain run (profiling of the other legs only)")
     ap.add_argument("--batch-steps", type=int, default=10)
     ap.add_argument("--no-clustered", action="store_true", help="skip the clustered 2^18 workload")
+    ap.add_argument("--no-paper-rule", action="store_true", help="skip the paper's kNN stop rule against exact kNN")
     ap.add_argument("--clustered-steps", type=int, default=10)
     ap.add_argument("--no-host-inclusive", action="store_true", help="skip the host-memory-inclusive timing")
     ap.add_argument("--batch-loop", action="store_true",
@@ -564,6 +600,8 @@ def main():
         out["batch"] = batch_measurement(args, with_oracle=not args.no_cpu_baseline)
     if not args.no_clustered:
         out["clustered"] = clustered_measurement(args)
+    if not args.no_paper_rule:
+        out["paper_rule"] = paper_rule_measurement(args)
     print(json.dumps(out))
 
 
