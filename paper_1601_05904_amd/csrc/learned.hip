@@ -6,14 +6,14 @@
 // Network (27 -> 64 -> 64 -> 1):
 //   x  = bf16(features)                     (5 x 5 cell counts / mean occupancy, in-cell offsets)
 //   h1 = bf16(gelu(W1 x + b1)),  h2 = bf16(gelu(W2 h1 + b2)),  y = W3 h2 + b3
-// with bf16 weights and activations as operands and float32 accumulation
-// (v_dot2c_f32_bf16: two products per lane per instruction), gelu the tanh form
-// u / 2 (1 + tanh(sqrt(2 / pi) (u + 0.044715 u^3))).  All lanes of a wavefront
-// use the same weights, so the weights are read through the scalar cache into
-// SGPRs and every dot instruction takes its weight pair as a scalar operand.
-// Training: per-sample forward and backward in one kernel (one sample per lane),
-// the weight gradients summed over the batch in a fixed order, then Adam on the
-// float32 master weights and a repack of the bf16 copies.
+// with bf16 weights and activations as operands and float32 accumulation, gelu
+// the tanh form u / 2 (1 + tanh(sqrt(2 / pi) (u + 0.044715 u^3))).  Inference
+// (the learned run's fused front and aidw_mlp_forward) runs the network on the
+// matrix cores (see mlp_tile).  Training: per-sample forward and backward in one
+// kernel (one sample per lane, v_dot2c_f32_bf16 dot products whose weight pairs,
+// the same for every lane, are scalar operands), the weight gradients summed
+// over the batch in a fixed order, then Adam on the float32 master weights and a
+// repack of the bf16 copies.
 #include <float.h>
 
 #include "aidw_internal.h"
@@ -187,25 +187,6 @@ __device__ inline float layer3(const MlpWeights& w, const uint32_t* hp) {
 #pragma unroll
   for (int p = 0; p < kHPairs; ++p) acc = dot2(w.w3p[p], hp[p], acc);
   return acc;
-}
-
-__global__ __launch_bounds__(256) void k_mlp_forward(MlpWeights w, const float* __restrict__ feat, int m,
-                                                     float* __restrict__ out) {
-  const int q = blockIdx.x * blockDim.x + threadIdx.x;
-  if (q >= m) return;
-  uint32_t xp[kInPairs], h1p[kHPairs], h2p[kHPairs];
-  load_x(feat + (size_t)q * kIn, xp);
-#pragma unroll
-  for (int o = 0; o < kH; o += 2) {
-    const float a = gelu_f(layer1_row(w, xp, o)), b = gelu_f(layer1_row(w, xp, o + 1));
-    h1p[o / 2] = pack_bf16(a, b);
-  }
-#pragma unroll
-  for (int o = 0; o < kH; o += 2) {
-    const float a = gelu_f(layer2_row(w, h1p, o)), b = gelu_f(layer2_row(w, h1p, o + 1));
-    h2p[o / 2] = pack_bf16(a, b);
-  }
-  out[q] = layer3(w, h2p);
 }
 
 // One sample per lane: forward, loss term, and the per-sample backward down to the
