@@ -538,7 +538,10 @@ __global__ __launch_bounds__(256) void k_mlp_forward_mfma(MlpDevice d, const flo
 // 16 tile + c: it computes features 8 g .. 8 g + 7, takes a quarter of the query's own cell
 // in the scan of the 3 x 3 block for the nearest distance, and one of its four neighbour
 // segments.
-// Four wavefronts per SIMD (at most 128 registers per lane) hide more of the loads' latency.
+// Four wavefronts per SIMD (at most 128 registers per lane) hide more of the loads' latency;
+// there the registers of the loads in flight across the network spill 3 dwords to scratch,
+// which still measured faster than issuing those loads after the network (no spill) or
+// than three wavefronts per SIMD.
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_learned_front(
     MlpDevice d, const GridScalars* __restrict__ gs, const int32_t* __restrict__ cell_start,
     const float* __restrict__ sx, const float* __restrict__ sy, const float* __restrict__ qx,
@@ -552,66 +555,86 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
   const int ncol = gs->ncol, nrow = gs->nrow;
   const double cwd = gs->cwd, minxd = minx, minyd = miny;
   const int nwaves = (gridDim.x * blockDim.x) >> 6;
-  // The loads of a tile's query index and coordinates are issued one and two tiles ahead
-  // (a wavefront works through its tiles in sequence), so that a tile starts with its
-  // coordinates at hand; the scan's row bounds are loaded together with the features.
+  // A feature cell's count is the difference of two cell offsets.  Column indices are
+  // clamped to [0, ncol], which makes a cell beyond the left or right edge count 0, and
+  // the end of a cell is the start of the next one in its row: lane g loads the starts
+  // of its cells 8 g .. 8 g + 8 (a), plus the ends of the (at most two) cells among
+  // them that close a row of the 5 x 5 block, at j1 and j1 + 5 (e0, e1).
+  const int j1 = (4 + 2 * g) % 5;  // the first j with 8 g + j = 4 (mod 5)
+  struct Ahead {
+    int q;               // query (-1 for an empty slot)
+    float fx, fy;
+    int a[9], e0, e1;    // cell offsets of the feature counts (0 in rows outside the grid)
+  };
   auto query_of = [&](int tl) -> int {
     const int tt = tl * 16 + c;
     return tt < m ? (perm ? (int)perm[tt] : tt) : -1;
   };
+  // the neighbour segment of lane g: g = 0 / 1 the row r0 - 1 / r0 + 1 (columns c0 - 1 .. c0 + 1,
+  // clipped), g = 2 / 3 the cell left / right of the query's
+  auto segment = [&](int c0, int r0, int& srow, int& sa, int& sb) -> bool {
+    srow = g < 2 ? r0 - 1 + 2 * g : r0;
+    sa = g < 2 ? (c0 > 0 ? c0 - 1 : 0) : c0 + (g == 2 ? -1 : 1);
+    sb = g < 2 ? (c0 + 1 < ncol ? c0 + 1 : ncol - 1) : sa;
+    return g < 2 ? (srow >= 0 && srow < nrow) : (sa >= 0 && sa < ncol);
+  };
+  // offset of column cc (clamped to [0, ncol]) in row r0 + dr of the block, 0 outside the grid
+  auto offset = [&](int r0, int c0, int dr, int dc) -> int {
+    const int r = r0 + dr, cc = min(max(c0 + dc, 0), ncol);
+    return r >= 0 && r < nrow ? cell_start[r * ncol + cc] : 0;
+  };
+  auto issue = [&](int qq, Ahead& A) {
+    A.q = qq;
+    A.fx = qq >= 0 ? qx[qq] : minx;
+    A.fy = qq >= 0 ? qy[qq] : miny;
+    const int c0 = clamp_cell((A.fx - minx) * inv, ncol), r0 = clamp_cell((A.fy - miny) * inv, nrow);
+#pragma unroll
+    for (int j = 0; j < 9; ++j) {
+      const int k = 8 * g + j;
+      A.a[j] = k < 25 ? offset(r0, c0, k / 5 - 2, k % 5 - 2) : 0;
+    }
+    const int k1 = 8 * g + j1, k2 = k1 + 5;
+    A.e0 = k1 < 25 ? offset(r0, c0, k1 / 5 - 2, 3) : 0;
+    A.e1 = k2 < 8 * g + 8 && k2 < 25 ? offset(r0, c0, k2 / 5 - 2, 3) : 0;
+  };
+  // Software pipeline over a wavefront's tiles (it works through them in sequence): a
+  // tile's query index is loaded two tiles ahead, its coordinates and the offsets of its
+  // feature cells one tile ahead, so that those loads are in flight while the previous
+  // tile runs its network and scan; the scan's bounds are loaded before the network.
   int tile = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-  int q_next = query_of(tile);                 // tile + 1 in the loop below
-  int q_next2 = query_of(tile + nwaves);       // tile + 2
-  float fx_next = q_next >= 0 ? qx[q_next] : minx, fy_next = q_next >= 0 ? qy[q_next] : miny;
+  Ahead nx;
+  issue(query_of(tile), nx);
+  int q_next = query_of(tile + nwaves);  // the query of the tile after the one in nx
   for (; tile * 16 < m; tile += nwaves) {
     __asm__ volatile("" ::: "memory");  // keeps the operand reads from LDS inside the loop (registers)
+    const Ahead cur = nx;
     const int t = tile * 16 + c;
-    const bool valid = t < m;
-    const int q = valid ? q_next : 0;
-    const float fx = fx_next, fy = fy_next;
-    q_next = q_next2;
-    q_next2 = query_of(tile + 2 * nwaves);
-    fx_next = q_next >= 0 ? qx[q_next] : minx;
-    fy_next = q_next >= 0 ? qy[q_next] : miny;
+    const int q = cur.q;
+    const bool valid = q >= 0;
+    const float fx = cur.fx, fy = cur.fy;
     const float tx = (fx - minx) * inv, ty = (fy - miny) * inv;
     const int c0 = clamp_cell(tx, ncol), r0 = clamp_cell(ty, nrow);
-    // bounds of the nearest-point scan over the 3 x 3 block: the query's own cell (all four
-    // lanes), and neighbour segment g of lane g -- g = 0 / 1: row r0 - 1 / r0 + 1 (columns
-    // c0 - 1 .. c0 + 1, clipped), g = 2 / 3: the cell left / right of the query's
-    const int own = r0 * ncol + c0;
-    const int o0 = cell_start[own], o1 = cell_start[own + 1];
-    const int srow = g < 2 ? r0 - 1 + 2 * g : r0;
-    const int sa = g < 2 ? (c0 > 0 ? c0 - 1 : 0) : c0 + (g == 2 ? -1 : 1);
-    const int sb = g < 2 ? (c0 + 1 < ncol ? c0 + 1 : ncol - 1) : sa;
-    const bool seg = g < 2 ? (srow >= 0 && srow < nrow) : (sa >= 0 && sa < ncol);
-    int p0 = 0, p1 = 0;
+    // the scan's bounds: the own cell and lane g's neighbour segment
+    const int o0 = cell_start[r0 * ncol + c0], o1 = cell_start[r0 * ncol + c0 + 1];
+    int srow, sa, sb, p0 = 0, p1 = 0;
+    const bool seg = segment(c0, r0, srow, sa, sb);
     if (seg) {
       p0 = cell_start[srow * ncol + sa];
       p1 = cell_start[srow * ncol + sb + 1];
     }
+    {
+      const int qn = q_next;
+      q_next = query_of(tile + 2 * nwaves);
+      issue(qn, nx);
+    }
     // features 8 g .. 8 g + 7: counts of the 5 x 5 block (row-major), then the in-cell offset
     float f[8];
-    int last_idx = -1, last_val = 0;
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
       const int k = 8 * g + j;
-      float v = 0.0f;
-      if (k < 25) {
-        const int r = r0 + k / 5 - 2, cc = c0 + k % 5 - 2;
-        if (r >= 0 && r < nrow && cc >= 0 && cc < ncol) {
-          const int idx = r * ncol + cc;
-          const int a = idx == last_idx ? last_val : cell_start[idx];
-          const int b = cell_start[idx + 1];
-          last_idx = idx + 1;
-          last_val = b;
-          v = (float)((double)(b - a) * inv_occ);
-        }
-      } else if (k == 25) {
-        v = tx - (float)c0;
-      } else if (k == 26) {
-        v = ty - (float)r0;
-      }
-      f[j] = v;
+      const int end = j == j1 ? cur.e0 : (j == j1 + 5 ? cur.e1 : cur.a[j + 1]);
+      f[j] = k < 25 ? (float)((double)(end - cur.a[j]) * inv_occ)
+                    : (k == 25 ? tx - (float)c0 : (k == 26 ? ty - (float)r0 : 0.0f));
     }
     const float y = mlp_tile(d, net, lane, pack8(f));
     // nearest point in the 3 x 3 block: the own cell split over the 4 lanes, then each lane's
