@@ -125,12 +125,15 @@ __device__ __forceinline__ void search(const View& g, const int32_t* __restrict_
         const double dy = (double)sy[p] - py;
         const double d2 = dx * dx + dy * dy;
         const int32_t id = sidx[p];
-        if ((LANES == 1 || d2 <= bound) && (d2 < bk[KMAX - 1] || (d2 == bk[KMAX - 1] && id < bi[KMAX - 1]))) {
+        // the comparisons of the (d2, index) order are combined with bitwise operators: each is
+        // then one vector compare, where short-circuit forms compile to branches on the exec mask
+        const bool take = (d2 < bk[KMAX - 1]) | ((d2 == bk[KMAX - 1]) & (id < bi[KMAX - 1]));
+        if ((LANES == 1 || d2 <= bound) && take) {
           bk[KMAX - 1] = d2;
           bi[KMAX - 1] = id;
 #pragma unroll
           for (int s = KMAX - 1; s > 0; --s) {
-            const bool sw = bk[s] < bk[s - 1] || (bk[s] == bk[s - 1] && bi[s] < bi[s - 1]);
+            const bool sw = (bk[s] < bk[s - 1]) | ((bk[s] == bk[s - 1]) & (bi[s] < bi[s - 1]));
             const double lo = bk[s], hi = bk[s - 1];
             const int32_t ilo = bi[s], ihi = bi[s - 1];
             bk[s - 1] = sw ? lo : hi;
