@@ -227,7 +227,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="uniform_1m")
-    ap.add_argument("--cpu-sample", type=int, default=1024, help="queries of the CPU-baseline sample")
+    ap.add_argument("--cpu-sample", type=int, default=4096, help="queries of the CPU-baseline and z-error sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-R comparison")
     ap.add_argument("--learned-workload", default="learned_1m")
