@@ -6,7 +6,8 @@
 // of cells around its query's cell (level L = cells at Chebyshev distance L)
 // and keeps its k best candidates in registers, ordered by (squared distance,
 // data index), with a fully unrolled insertion (the paper's insert-and-swap
-// k-array, initialised to +inf instead of 0 so that it accepts candidates).
+// k-array, initialised to +inf instead of 0 so that it accepts candidates) whose
+// comparisons are branch-free (vector compares combined with bitwise operators).
 //
 // Stop rule.  The paper expands until the block holds k points and then adds
 // one more level.  That is not always enough: the block of level L only
@@ -187,7 +188,7 @@ hipError_t launch_knn_lanes(const GridScalars* gs, const int32_t* cell_start, co
   if (m <= 0) return hipSuccess;
   if (lanes != 2 && lanes != 4 && lanes != 8) return hipErrorInvalidValue;
   // one workgroup per 256 / lanes queries; with an active count the workgroups beyond it exit at
-  // once (a grid-stride loop instead costs the search registers: 161 -> 198 VGPRs, measured slower)
+  // once (a grid-stride loop instead keeps more registers live across the search: measured slower)
   const dim3 grid((int)(((int64_t)m * lanes + 255) / 256)), block(256);
 #define AIDW_KNNL(K, LN)                                                                                         \
   hipLaunchKernelGGL((k_knn_lanes<K, LN>), grid, block, 0, s, gs, cell_start, sx, sy, sidx, qx, qy, qperm, active, \
