@@ -178,6 +178,45 @@ def test_learned_run_prediction_matches_fp64_network(T):
     assert np.median(err) < 1e-5 and np.quantile(err, 0.99) < 1e-3 and err.max() < 2e-2
 
 
+def _strip(n, m, seed):
+    """Data and queries on a thin horizontal strip: a grid of one or two rows."""
+    rng = np.random.default_rng(seed)
+    q = lambda a: (np.floor(np.asarray(a) * 2.0 ** 20) / 2.0 ** 20).astype(np.float32)
+    x, y = q(rng.random(n)), q(0.5 + 0.001 * rng.random(n))
+    qx, qy = q(rng.random(m)), q(0.5 + 0.001 * rng.random(m))
+    return x, y, rng.standard_normal(n).astype(np.float32), qx, qy
+
+
+@pytest.mark.parametrize("case", ["n5_m37", "n40_m16", "n200_m33", "strip"])
+def test_learned_prediction_small_grids(T, case):
+    """R_hat of the fused front on grids where most of the 5 x 5 window lies outside the
+    grid (a handful of cells, a one-row strip) and with a ragged last tile of queries."""
+    aidw, L = mods()
+    if case == "strip":
+        x, y, z, qx, qy = _strip(3000, 517, 77)
+        area = 0.05  # cell width sqrt(2 A / n) ~ 1 / 170 of the strip's length
+    else:
+        n, m = (int(v[1:]) for v in case.split("_"))
+        ds = W.make(n, m, min(15, n), 300 + n, "uniform")
+        x, y, z, qx, qy = ds.x, ds.y, ds.z, ds.qx, ds.qy
+        area = 0.0
+    params = random_params(21, 0.3)
+    mlp = L.MLP(seed=7)
+    mlp.set_params(params)
+    p = aidw.Params(k=min(15, x.size), area=area)
+    dx, dy, dz, dqx, dqy = (dev(T, a) for a in (x, y, z, qx, qy))
+    _, _, rh, _ = L.run_learned(dx, dy, dz, dqx, dqy, p, mlp, L.ALPHA_EXACT, 0.3, want_rhat=True)
+    g = aidw.build_grid(dx, dy, dqx, dqy, p)
+    d = g.describe()
+    g.close()
+    if case == "strip":
+        assert d["nrow"] <= 2 and d["ncol"] > 100
+    feat = O.features(x, y, qx, qy, d["min_x"], d["min_y"], d["inv_cell_width"], d["ncol"], d["nrow"])
+    yo, _ = OM.forward(params.astype(np.float64), feat)
+    err = np.abs(rh.cpu().numpy().astype(np.float64) - yo) / (1.0 + np.abs(yo))
+    assert err.max() < 2e-2 and np.median(err) < 1e-4, (case, d["ncol"], d["nrow"], float(err.max()))
+
+
 def test_all_fallback_equals_plain_path(T):
     aidw, L = mods()
     ds = W.make(6000, 3000, 15, 231, "mixture", 8)
