@@ -310,33 +310,47 @@ def learned_comparison(args, with_oracle):
     x, y, z, qx, qy = (torch.from_numpy(getattr(ds, k)).to(dev) for k in ("x", "y", "z", "qx", "qy"))
     p = aidw.Params(k=ds.k, levels=ds.levels, r_min=ds.r_min, r_max=ds.r_max, occupancy=ds.occupancy)
     qz_p = torch.empty(ds.m, dtype=torch.float32, device=dev)
-    qz_l = torch.empty(ds.m, dtype=torch.float32, device=dev)
     ms_p, st_p = timed_runs(lambda: aidw.run(x, y, z, qx, qy, p, out=qz_p), args.learned_steps, 1)
-    ms_l, st_l = timed_runs(lambda: L.run_learned(x, y, z, qx, qy, p, mlp, L.ALPHA_EXACT, args.delta, out=qz_l),
-                            args.learned_steps, 1)
     _, al_p, _ = aidw.run(x, y, z, qx, qy, p, want_alpha=True)
-    _, al_l, _, nfb = L.run_learned(x, y, z, qx, qy, p, mlp, L.ALPHA_EXACT, args.delta, want_alpha=True)
-    mismatch = float((al_p != al_l).float().mean().item())
     rstage_p = st_p["grid_ms"] + st_p["knn_ms"]
-    rstage_l = st_l["grid_ms"] + st_l["knn_ms"]
-    out = {"workload": args.learned_workload, "n": ds.n, "m": ds.m, "k": ds.k, "rule": "alpha-exact",
-           "delta": args.delta,
-           "plain_points_per_s": ds.m / (ms_p * 1e-3), "learned_points_per_s": ds.m / (ms_l * 1e-3),
-           "speedup_end_to_end": ms_p / ms_l,
-           "plain_rstage_ms": rstage_p, "learned_rstage_ms": rstage_l, "speedup_rstage": rstage_p / rstage_l,
-           "plain_stages_ms": st_p, "learned_stages_ms": st_l,
-           "skipped_knn_fraction": 1.0 - nfb / ds.m, "alpha_mismatch_fraction": mismatch,
-           "training": {"pairs": npairs, "epochs": 16, "batch": 1024, "lr": 2e-3, "final_loss": float(losses[-1]),
-                        "data_s": t1 - t0, "train_s": t2 - t1}}
+    sel = ref = None
     if with_oracle:
         import oracle
         sel = W.sample_queries(ds.m, args.cpu_sample, ds.seed)
         ref = oracle.aidw(ds.x, ds.y, ds.z, ds.qx, ds.qy, k=ds.k, levels=ds.levels, r_min=ds.r_min,
                           r_max=ds.r_max, occupancy=ds.occupancy, qsel=sel)
-        for name, qz in (("z_error_plain", qz_p), ("z_error_learned", qz_l)):
-            e = np.abs(qz.cpu().numpy()[sel].astype(np.float64) - ref["z"]) / np.maximum(np.abs(ref["z"]), ref["s"])
-            out[name] = {"max": float(e.max()), "median": float(np.median(e)),
-                         "frac_within_1e-5": float(np.mean(e <= 1e-5)), "sample": len(sel)}
+
+    def z_error(qz):
+        e = np.abs(qz.cpu().numpy()[sel].astype(np.float64) - ref["z"]) / np.maximum(np.abs(ref["z"]), ref["s"])
+        return {"max": float(e.max()), "median": float(np.median(e)), "frac_within_1e-5": float(np.mean(e <= 1e-5)),
+                "sample": len(sel)}
+
+    def one_rule(rule):
+        qz_l = torch.empty(ds.m, dtype=torch.float32, device=dev)
+        ms_l, st_l = timed_runs(lambda: L.run_learned(x, y, z, qx, qy, p, mlp, rule, args.delta, out=qz_l),
+                                args.learned_steps, 1)
+        _, al_l, _, nfb = L.run_learned(x, y, z, qx, qy, p, mlp, rule, args.delta, want_alpha=True)
+        rstage_l = st_l["grid_ms"] + st_l["knn_ms"]
+        r = {"learned_points_per_s": ds.m / (ms_l * 1e-3), "speedup_end_to_end": ms_p / ms_l,
+             "learned_rstage_ms": rstage_l, "speedup_rstage": rstage_p / rstage_l, "learned_stages_ms": st_l,
+             "skipped_knn_fraction": 1.0 - nfb / ds.m,
+             "alpha_mismatch_fraction": float((al_p != al_l).float().mean().item())}
+        if with_oracle:
+            r["z_error_learned"] = z_error(qz_l)
+        return r
+
+    out = {"workload": args.learned_workload, "n": ds.n, "m": ds.m, "k": ds.k, "rule": "alpha-exact",
+           "delta": args.delta, "plain_points_per_s": ds.m / (ms_p * 1e-3), "plain_rstage_ms": rstage_p,
+           "plain_stages_ms": st_p}
+    out.update(one_rule(L.ALPHA_EXACT))
+    # the count certificate (no network; alpha exact by construction) and the certificate
+    # followed by the network's rule
+    out["certified"] = one_rule(L.CERTIFIED)
+    out["certified_then_alpha_exact"] = one_rule(L.CERTIFIED_THEN_ALPHA_EXACT)
+    out["training"] = {"pairs": npairs, "epochs": 16, "batch": 1024, "lr": 2e-3, "final_loss": float(losses[-1]),
+                       "data_s": t1 - t0, "train_s": t2 - t1}
+    if with_oracle:
+        out["z_error_plain"] = z_error(qz_p)
     mlp.close()
     return out
 

@@ -214,8 +214,8 @@ hipError_t launch_mlp_forward(const MlpDevice& d, const float* feat, int m, floa
 hipError_t launch_learned_front(const MlpDevice& d, const GridScalars* gs, const int32_t* cell_start, const float* sx,
                                 const float* sy, const float* qx, const float* qy, const uint32_t* perm, int m,
                                 double inv_occ, double slack_cells, const AlphaParams& ap, int rule, double delta,
-                                double r_sat_lo, double r_sat_hi, uint32_t* flag, float* alpha_f, float* d1sq,
-                                float* r_hat_out, hipStream_t s);
+                                double r_sat_lo, double r_sat_hi, int k, double cert_sum_min, uint32_t* flag,
+                                float* alpha_f, float* d1sq, float* r_hat_out, hipStream_t s);
 size_t mlp_batch_scratch_floats(int B);
 // grad [AIDW_MLP_PARAMS + 1]: the batch gradient, then the batch's mean squared error.
 hipError_t launch_mlp_gradients(const MlpDevice& d, const float* feat, const float* target, const uint32_t* sel, int B,

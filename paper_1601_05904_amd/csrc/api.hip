@@ -893,7 +893,9 @@ aidw_status aidw_run_learned(const float* x, const float* y, const float* z, int
   if (!z) return fail(AIDW_EINVAL, "z is NULL");
   if ((st = check_params(p)) != AIDW_OK) return st;
   if (!mlp) return fail(AIDW_EINVAL, "network is NULL");
-  if (rule != AIDW_FALLBACK_LITERAL && rule != AIDW_FALLBACK_ALPHA_EXACT) return fail(AIDW_EINVAL, "unknown rule %d", rule);
+  if (rule != AIDW_FALLBACK_LITERAL && rule != AIDW_FALLBACK_ALPHA_EXACT && rule != AIDW_FALLBACK_CERTIFIED &&
+      rule != AIDW_FALLBACK_CERTIFIED_THEN_ALPHA_EXACT)
+    return fail(AIDW_EINVAL, "unknown rule %d", rule);
   if (!(delta >= 0) || !isfinite(delta)) return fail(AIDW_EINVAL, "delta must be finite and >= 0");
   if (p->cell_width > 0 || p->occupancy != mlp->occupancy)
     return fail(AIDW_EINVAL, "the grid must use the network's occupancy (%g) and no explicit cell width",
@@ -949,12 +951,16 @@ aidw_status aidw_run_learned(const float* x, const float* y, const float* z, int
     const double r_sat_lo = p->r_min + p->r_max / M_PI * acos(0.8);
     const double r_sat_hi = p->r_min + p->r_max / M_PI * acos(-0.8);
     const double inv_occ = (double)g->host.ncells / (double)n;
+    // the certificate's threshold on the sum of the k nearest distances: alpha = alpha_5 for
+    // R > min(r_sat_hi, R_max) (Eq. 5 is 1 from R_max on); the margin covers the float32
+    // rounding of r_obs and the rounding of mu near 0.9
+    const double cert_sum_min = (double)p->k * g->host.r_exp * fmin(r_sat_hi, p->r_max) * (1.0 + 1e-6);
 #define STEP(expr, what) \
   if (st == AIDW_OK && (e = (expr)) != hipSuccess) st = hip_fail(e, what)
     STEP(bin_queries(g->dev, qx, qy, mm, ncells, cnt, key, slot, scan, order, stream), "query binning");
     STEP(launch_learned_front(mlp->d, g->dev, g->cell_start, g->sx, g->sy, qx, qy, order, mm, inv_occ,
-                              slack_cells(g->host), ap, rule, delta, r_sat_lo, r_sat_hi, flag, alpha_f, d1sq, r_hat_out,
-                              stream),
+                              slack_cells(g->host), ap, rule, delta, r_sat_lo, r_sat_hi, p->k, cert_sum_min, flag,
+                              alpha_f, d1sq, r_hat_out, stream),
          "features / network / decision kernel");
     STEP(compact_flags(flag, order, mm, stmp, list, count, stream), "fallback compaction");
     // the fallback queries are few and hard (cluster edges): eight lanes per query measured best

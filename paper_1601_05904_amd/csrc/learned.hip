@@ -382,6 +382,11 @@ __global__ void k_accumulate_loss(const float* __restrict__ grad, float* __restr
 //                     other queries use alpha(mu(r_hat)) by Eq. 5, 6.
 //   rule 1 (alpha-exact): skip only when r_hat >= r_sat_hi + delta (alpha = alpha_5) or
 //                     r_hat <= r_sat_lo - delta (alpha = alpha_1), where mu = 0.9 / 0.1.
+//   rule 2 (certified): skip only when a lower bound of r_obs (from the counts of the 5 x 5
+//                     block, or the exact distances of the 3 x 3 block) proves R beyond the
+//                     point where alpha saturates at alpha_5 (certified_saturated,
+//                     certified_by_distances below); the network is not evaluated.
+//   rule 3 (certified, then alpha-exact): skip when certified, else as rule 1.
 // Coincident queries (d1 == 0) always fall back.
 __device__ inline double fuzzy_mu_l(double R, double rmin, double rmax) {
   if (R <= rmin) return 0.0;
@@ -415,6 +420,53 @@ __device__ inline bool decide_one(double R, float d1, const AlphaParams& ap, int
     return false;
   }
   return true;
+}
+
+// Lower bound of Eq. 3 from block counts.  B_L is the block of (2L + 1)^2 cells around the
+// query's cell (clipped to the grid) and c_L the number of data points binned into it; every
+// point binned outside B_L lies at least D_L from the query, D_L = the distance from the query
+// to the nearest side of B_L that has cells beyond it, less the binning slack (no such side:
+// the block holds every point).  At most c_L of the query's neighbours lie inside B_L, so its
+// j-th nearest distance is >= D_L whenever c_L < j; the k nearest distances sum to at least
+// sum over L of D_L * (min(k, c_{L+1}) - min(k, c_L)), with c_3 = k.  True when that sum
+// exceeds sum_min (k * r_exp * the R above which alpha = alpha_5, with a relative margin).
+__device__ inline double block_side_distance(double px, double py, int c0, int r0, int L, int ncol, int nrow,
+                                             double minx, double miny, double cw, double slack) {
+  double d = INFINITY;
+  if (c0 - L > 0) d = fmin(d, px - (minx + (double)(c0 - L) * cw));
+  if (c0 + L < ncol - 1) d = fmin(d, (minx + (double)(c0 + L + 1) * cw) - px);
+  if (r0 - L > 0) d = fmin(d, py - (miny + (double)(r0 - L) * cw));
+  if (r0 + L < nrow - 1) d = fmin(d, (miny + (double)(r0 + L + 1) * cw) - py);
+  return fmax(d - slack * cw, 0.0);
+}
+__device__ inline bool certified_saturated(double px, double py, int c0, int r0, int ncol, int nrow, double minx,
+                                           double miny, double cw, double slack, int c_0, int c_1, int c_2, int k,
+                                           double sum_min) {
+  const int c[4] = {min(c_0, k), min(c_1, k), min(c_2, k), k};
+  double sum = 0.0;
+#pragma unroll
+  for (int L = 0; L < 3; ++L) {
+    const int mult = c[L + 1] - c[L];
+    if (mult > 0) sum += (double)mult * block_side_distance(px, py, c0, r0, L, ncol, nrow, minx, miny, cw, slack);
+  }
+  return sum > sum_min;
+}
+
+// Tighter, from the exact distances of the 3 x 3 block: its points nearer than D_1 are all
+// the data points within D_1 of the query (v_cnt of them, distances summing to v_sum, the
+// largest v_max).  The j-th nearest distance is >= min(s_j, D_1), s_j the j-th smallest
+// distance in the 3 x 3 block, and >= D_2 when c_2 < j.  With K = min(k, c_2), the K smallest
+// of min(s_j, D_1) sum to v_sum + (K - v_cnt) D_1 when v_cnt < K, and to at least
+// v_sum - (v_cnt - K) v_max otherwise (the v_cnt - K left out are each <= v_max); the other
+// k - K terms are >= D_2.  The float32 distances are each within 2.2e-7 relative of the exact
+// ones and a point within that of D_1 may be counted on either side of it: the sum is lowered
+// by (3 v_cnt + k) * 5e-7 * D_1 to cover both.
+__device__ inline bool certified_by_distances(double v_sum, int v_cnt, float v_max, int c_2, int k, double d_1,
+                                              double d_2, double sum_min) {
+  const int kk = min(k, c_2);
+  double sum = v_cnt < kk ? v_sum + (double)(kk - v_cnt) * d_1 : v_sum - (double)(v_cnt - kk) * (double)v_max;
+  if (k > kk) sum += (double)(k - kk) * d_2;
+  return sum - (double)(3 * v_cnt + k) * 5e-7 * d_1 > sum_min;
 }
 
 // Eq. 4-6 for the fallback queries (the first *count entries of perm) from their exact r_obs.
@@ -542,15 +594,18 @@ __global__ __launch_bounds__(256) void k_mlp_forward_mfma(MlpDevice d, const flo
 // there the registers of the loads in flight across the network spill 3 dwords to scratch,
 // which still measured faster than issuing those loads after the network (no spill) or
 // than three wavefronts per SIMD.
+// kCert: the counts certificate (rules 2, 3); kNet: the network (rules 0, 1, 3).
+template <bool kCert, bool kNet>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_learned_front(
     MlpDevice d, const GridScalars* __restrict__ gs, const int32_t* __restrict__ cell_start,
     const float* __restrict__ sx, const float* __restrict__ sy, const float* __restrict__ qx,
     const float* __restrict__ qy, const uint32_t* __restrict__ perm, int m, double inv_occ, double slack_cells,
-    AlphaParams ap, int rule, double delta, double r_sat_lo, double r_sat_hi, uint32_t* __restrict__ flag,
-    float* __restrict__ alpha_f, float* __restrict__ d1sq, float* __restrict__ r_hat_out) {
+    AlphaParams ap, int rule, double delta, double r_sat_lo, double r_sat_hi, int k, double cert_sum_min,
+    uint32_t* __restrict__ flag, float* __restrict__ alpha_f, float* __restrict__ d1sq,
+    float* __restrict__ r_hat_out) {
   const int lane = threadIdx.x & 63, c = lane & 15, g = lane >> 4;
   __shared__ uint4 lds[kNetOperands];
-  const MfmaNet net = stage_net(d, lds);
+  const MfmaNet net = kNet ? stage_net(d, lds) : MfmaNet{lds};
   const float minx = gs->minx, miny = gs->miny, inv = gs->inv_cw;
   const int ncol = gs->ncol, nrow = gs->nrow;
   const double cwd = gs->cwd, minxd = minx, minyd = miny;
@@ -590,8 +645,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
     const int c0 = clamp_cell((A.fx - minx) * inv, ncol), r0 = clamp_cell((A.fy - miny) * inv, nrow);
 #pragma unroll
     for (int j = 0; j < 9; ++j) {
-      const int k = 8 * g + j;
-      A.a[j] = k < 25 ? offset(r0, c0, k / 5 - 2, k % 5 - 2) : 0;
+      const int kk = 8 * g + j;
+      A.a[j] = kk < 25 ? offset(r0, c0, kk / 5 - 2, kk % 5 - 2) : 0;
     }
     const int k1 = 8 * g + j1, k2 = k1 + 5;
     A.e0 = k1 < 25 ? offset(r0, c0, k1 / 5 - 2, 3) : 0;
@@ -628,27 +683,55 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
       issue(qn, nx);
     }
     // features 8 g .. 8 g + 7: counts of the 5 x 5 block (row-major), then the in-cell offset
+    // and this lane's share of the data points in the blocks of 1, 3 x 3 and 5 x 5 cells
     float f[8];
+    int n0 = 0, n1 = 0, n2 = 0;
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
-      const int k = 8 * g + j;
+      const int kk = 8 * g + j;
       const int end = j == j1 ? cur.e0 : (j == j1 + 5 ? cur.e1 : cur.a[j + 1]);
-      f[j] = k < 25 ? (float)((double)(end - cur.a[j]) * inv_occ)
-                    : (k == 25 ? tx - (float)c0 : (k == 26 ? ty - (float)r0 : 0.0f));
+      const int cnt = kk < 25 ? end - cur.a[j] : 0;
+      if constexpr (kCert) {
+        const int br = kk / 5, bc = kk % 5;
+        n2 += cnt;
+        n1 += br >= 1 && br <= 3 && bc >= 1 && bc <= 3 ? cnt : 0;
+        n0 += kk == 12 ? cnt : 0;
+      }
+      f[j] = kk < 25 ? (float)((double)cnt * inv_occ)
+                     : (kk == 25 ? tx - (float)c0 : (kk == 26 ? ty - (float)r0 : 0.0f));
     }
-    const float y = mlp_tile(d, net, lane, pack8(f));
+    float y = __builtin_nanf("");
+    if constexpr (kNet) y = mlp_tile(d, net, lane, pack8(f));
     // nearest point in the 3 x 3 block: the own cell split over the 4 lanes, then each lane's
     // neighbour segment unless all of it lies farther than the own cell's nearest, then the
     // minimum over the 4 lanes.  float32 suffices: the value only sets the power-of-two
     // scale of the pair weights; a coincident point (which lies in the own cell) is found
     // exactly, as a zero difference.
+    // With the certificate, every point of the 3 x 3 block nearer than D_1 (the distance to
+    // the block's open sides, less the binning slack) is counted and its distance summed.
     const double px = fx, py = fy;
     float best = INFINITY;
     int hit = 0;
+    double d_1 = 0.0, v_sum = 0.0;
+    float d_1sq = 0.0f, v_max = 0.0f;
+    int v_cnt = 0;
+    if constexpr (kCert) {
+      d_1 = block_side_distance(px, py, c0, r0, 1, ncol, nrow, minxd, minyd, cwd, slack_cells);
+      d_1sq = (float)(d_1 * d_1);
+    }
     for (int p = o0 + g; p < o1; p += 4) {
       const float dx = sx[p] - fx, dy = sy[p] - fy;
+      const float dd = __builtin_fmaf(dx, dx, dy * dy);
       hit |= (dx == 0.0f) & (dy == 0.0f);
-      best = fminf(best, __builtin_fmaf(dx, dx, dy * dy));
+      best = fminf(best, dd);
+      if constexpr (kCert) {
+        if (dd < d_1sq) {
+          const float dist = __builtin_sqrtf(dd);
+          v_sum += (double)dist;
+          v_max = fmaxf(v_max, dist);
+          ++v_cnt;
+        }
+      }
     }
     best = fminf(best, __shfl_xor(best, 16, 64));
     best = fminf(best, __shfl_xor(best, 32, 64));
@@ -660,18 +743,42 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
                        : g == 1 ? (minyd + ((double)r0 + 1.0 - slack_cells) * cwd) - py
                        : g == 2 ? px - (minxd + ((double)c0 + slack_cells) * cwd)
                                 : (minxd + ((double)c0 + 1.0 - slack_cells) * cwd) - px;
-      if (e > 0.0 && e * e > (double)best) p1 = p0;
+      // (with the certificate, only a segment wholly beyond D_1 is left out)
+      if (e > 0.0 && e * e > (double)best && (!kCert || e >= d_1)) p1 = p0;
     }
     if (seg) {
       for (int p = p0; p < p1; ++p) {
         const float dx = sx[p] - fx, dy = sy[p] - fy;
-        best = fminf(best, __builtin_fmaf(dx, dx, dy * dy));
+        const float dd = __builtin_fmaf(dx, dx, dy * dy);
+        best = fminf(best, dd);
+        if constexpr (kCert) {
+          if (dd < d_1sq) {
+            const float dist = __builtin_sqrtf(dd);
+            v_sum += (double)dist;
+            v_max = fmaxf(v_max, dist);
+            ++v_cnt;
+          }
+        }
       }
     }
     best = fminf(best, __shfl_xor(best, 16, 64));
     best = fminf(best, __shfl_xor(best, 32, 64));
     hit |= __shfl_xor(hit, 16, 64);
     hit |= __shfl_xor(hit, 32, 64);
+    if constexpr (kCert) {
+      n0 += __shfl_xor(n0, 16, 64);
+      n1 += __shfl_xor(n1, 16, 64);
+      n2 += __shfl_xor(n2, 16, 64);
+      n0 += __shfl_xor(n0, 32, 64);
+      n1 += __shfl_xor(n1, 32, 64);
+      n2 += __shfl_xor(n2, 32, 64);
+      v_cnt += __shfl_xor(v_cnt, 16, 64);
+      v_cnt += __shfl_xor(v_cnt, 32, 64);
+      v_sum += __shfl_xor(v_sum, 16, 64);
+      v_sum += __shfl_xor(v_sum, 32, 64);
+      v_max = fmaxf(v_max, __shfl_xor(v_max, 16, 64));
+      v_max = fmaxf(v_max, __shfl_xor(v_max, 32, 64));
+    }
     if (g != 0 || !valid) continue;
     double dout = INFINITY;
     if (c0 - 1 > 0) dout = fmin(dout, px - (minxd + (double)(c0 - 1) * cwd));
@@ -685,8 +792,22 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
     else
       v = dout > 0 ? dout * dout : 0;  // lower bound
     const float d1 = hit ? 0.0f : fmaxf((float)v, FLT_MIN);
-    double alpha;
-    const bool fall = decide_one((double)y, d1, ap, rule, delta, r_sat_lo, r_sat_hi, &alpha);
+    double alpha = 0.0;
+    bool fall = true;
+    bool cert = false;
+    if constexpr (kCert)
+      cert = d1 != 0.0f &&
+             (certified_saturated(px, py, c0, r0, ncol, nrow, minxd, minyd, cwd, slack_cells, n0, n1, n2, k,
+                                  cert_sum_min) ||
+              certified_by_distances(
+                  v_sum, v_cnt, v_max, n2, k, d_1,
+                  block_side_distance(px, py, c0, r0, 2, ncol, nrow, minxd, minyd, cwd, slack_cells), cert_sum_min));
+    if (cert) {
+      fall = false;
+      alpha = ap.levels[4];
+    } else if (kNet) {
+      fall = decide_one((double)y, d1, ap, rule == 3 ? 1 : rule, delta, r_sat_lo, r_sat_hi, &alpha);
+    }
     flag[t] = fall ? 1u : 0u;
     if (!fall) {
       alpha_f[q] = (float)alpha;
@@ -741,12 +862,20 @@ int tile_blocks(const void* kernel, int m) {
 hipError_t launch_learned_front(const MlpDevice& d, const GridScalars* gs, const int32_t* cell_start, const float* sx,
                                 const float* sy, const float* qx, const float* qy, const uint32_t* perm, int m,
                                 double inv_occ, double slack_cells, const AlphaParams& ap, int rule, double delta,
-                                double r_sat_lo, double r_sat_hi, uint32_t* flag, float* alpha_f, float* d1sq,
-                                float* r_hat_out, hipStream_t s) {
+                                double r_sat_lo, double r_sat_hi, int k, double cert_sum_min, uint32_t* flag,
+                                float* alpha_f, float* d1sq, float* r_hat_out, hipStream_t s) {
   if (m <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_learned_front, dim3(tile_blocks((const void*)k_learned_front, m)), dim3(256), 0, s, d, gs,
-                     cell_start, sx, sy, qx, qy, perm, m, inv_occ, slack_cells, ap, rule, delta, r_sat_lo, r_sat_hi,
-                     flag, alpha_f, d1sq, r_hat_out);
+#define FRONT(CERT, NET)                                                                                       \
+  hipLaunchKernelGGL((k_learned_front<CERT, NET>), dim3(tile_blocks((const void*)k_learned_front<CERT, NET>, m)), \
+                     dim3(256), 0, s, d, gs, cell_start, sx, sy, qx, qy, perm, m, inv_occ, slack_cells, ap, rule,   \
+                     delta, r_sat_lo, r_sat_hi, k, cert_sum_min, flag, alpha_f, d1sq, r_hat_out)
+  if (rule == 2)
+    FRONT(true, false);
+  else if (rule == 3)
+    FRONT(true, true);
+  else
+    FRONT(false, true);
+#undef FRONT
   return hipGetLastError();
 }
 

@@ -17,7 +17,7 @@ from . import Params, _VP, _check, _dev, _stream, build_grid, knn, load
 
 N_IN = 27
 N_PARAMS = 6017
-LITERAL, ALPHA_EXACT = 0, 1
+LITERAL, ALPHA_EXACT, CERTIFIED, CERTIFIED_THEN_ALPHA_EXACT = 0, 1, 2, 3
 
 
 class MLP:

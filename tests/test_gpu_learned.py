@@ -277,3 +277,69 @@ def test_trained_network_gain(T):
     assert skipped > 0.85
     assert wrong_alpha < 0.005
     assert np.mean(e <= 1e-5) > 0.995
+
+
+def _certificate_oracle(ds, k, margin=0.0):
+    """Oracle certified set (oracle/certificate.py) on the grid the library builds for ds; the
+    threshold is the library's (k r_exp R_sat (1 + 1e-6)) raised by the relative margin."""
+    import oracle.certificate as C
+    b = O.bounds(ds.x, ds.y, ds.qx, ds.qy)
+    gp = O.grid_params(b, ds.n, occupancy=2.0)
+    slack = (max(gp["ncol"], gp["nrow"]) + 1) * 2.0 ** -21 + 1e-9
+    r_sat = 0.0 + 2.0 / np.pi * np.arccos(-0.8)
+    sum_min = k * gp["r_exp"] * min(r_sat, 2.0) * (1 + 1e-6) * (1 + margin)
+    return C.certified(ds.x, ds.y, ds.qx, ds.qy, k, b[0], b[1], gp["cw"], gp["inv_cw"], gp["ncol"], gp["nrow"],
+                       slack, sum_min)
+
+
+@pytest.mark.parametrize("case", ["mixture", "uniform_k1", "small_grid"])
+def test_certified_rule_is_exact(T, case):
+    """Rule 2 skips kNN where the certificate proves alpha = alpha_5: as many queries as the
+    oracle's bound certifies, up to the kernel's float32 margin (the oracle's distances are
+    FP64); every query's alpha equals the plain path's and z stays within the error bar of
+    the FP64 oracle."""
+    aidw, L = mods()
+    if case == "mixture":
+        ds, k = W.make(40000, 6000, 15, 251, "mixture", 16), 15
+    elif case == "uniform_k1":
+        ds, k = W.make(20000, 3000, 1, 252), 1
+    else:
+        ds, k = W.make(60, 500, 5, 253, "mixture", 4), 5
+    ds.qx[5], ds.qy[5] = ds.x[2], ds.y[2]  # a coincident query always falls back
+    mlp = L.MLP(seed=7)
+    qz_p, al_p, _, qz_l, al_l, rh, nfb = _plain_and_learned(T, ds, mlp, L.CERTIFIED, 0.0, k)
+    cert = _certificate_oracle(ds, k)
+    cert_strict = _certificate_oracle(ds, k, 1e-3)
+    cert[5] = cert_strict[5] = False
+    assert int(cert_strict.sum()) <= ds.m - nfb <= int(cert.sum())
+    if case == "mixture":
+        assert cert.mean() > 0.8
+    assert np.all(np.isnan(rh))  # the network is not evaluated
+    assert np.array_equal(al_l, al_p)
+    assert qz_l[5] == ds.z[2]
+    assert np.allclose(qz_l, qz_p, rtol=2e-6, atol=1e-7)
+    sel = np.arange(0, ds.m, max(1, ds.m // 400))
+    ref = O.aidw(ds.x, ds.y, ds.z, ds.qx, ds.qy, k=k, qsel=sel)
+    e = np.abs(qz_l[sel].astype(np.float64) - ref["z"]) / np.maximum(np.abs(ref["z"]), ref["s"])
+    assert e.max() <= 1e-5
+
+
+def test_certified_then_network_rule(T):
+    """Rule 3 skips the union of rule 2's and rule 1's queries; certified ones keep the exact alpha."""
+    aidw, L = mods()
+    ds = W.make(20000, 4000, 15, 254, "mixture", 8)
+    mlp = L.MLP(seed=5)
+    mlp.set_params(random_params(9, 0.2))
+    _, al_p, _, _, al_1, rh1, nfb1 = _plain_and_learned(T, ds, mlp, L.ALPHA_EXACT, 0.1, 15)
+    _, _, _, _, _, _, nfb2 = _plain_and_learned(T, ds, mlp, L.CERTIFIED, 0.1, 15)
+    _, _, _, qz_3, al_3, rh3, nfb3 = _plain_and_learned(T, ds, mlp, L.CERTIFIED_THEN_ALPHA_EXACT, 0.1, 15)
+    assert np.array_equal(rh1, rh3)
+    cert = _certificate_oracle(ds, 15)
+    cert_strict = _certificate_oracle(ds, 15, 1e-3)
+    hi, lo = 2 / np.pi * np.arccos(-0.8), 2 / np.pi * np.arccos(0.8)
+    rh64 = rh3.astype(np.float64)
+    net_skip = (rh64 >= hi + 0.1) | (rh64 <= lo - 0.1)
+    assert int((cert_strict | net_skip).sum()) <= ds.m - nfb3 <= int((cert | net_skip).sum())
+    assert nfb3 <= min(nfb1, nfb2)
+    assert np.all(al_3[cert_strict] == al_p[cert_strict])
+    assert np.all(np.isfinite(qz_3))
