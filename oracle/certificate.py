@@ -25,7 +25,9 @@ Section 4.1) and the query's position:
         sum_k >= v_sum + (K - v_cnt) * D_1 + (k - K) * D_2,
     and with v_cnt >= K (v_max the largest of the v_cnt distances):
         sum_k >= v_sum - (v_cnt - K) * v_max + (k - K) * D_2;
-    the larger of this and the count bound is the bound.
+    the larger of this and the count bound is the bound.  When dense_limit is
+    given, the 3 x 3 route is taken only for c_1 <= dense_limit (the library
+    leaves denser blocks, whose R lies far below saturation, to the exact path).
   * The query is certified when the bound exceeds sum_min (the caller passes
     k * r_exp * the saturation point of R, with any rounding margin).
 
@@ -64,7 +66,7 @@ def side_distance(px, py, col, row, L, ncol, nrow, minx, miny, cw, slack):
     return max(d - slack * cw, 0.0)
 
 
-def robs_lower_bound_sum(x, y, qx, qy, k, minx, miny, cw, inv_cw, ncol, nrow, slack):
+def robs_lower_bound_sum(x, y, qx, qy, k, minx, miny, cw, inv_cw, ncol, nrow, slack, dense_limit=None):
     """Lower bound of the sum of the k nearest distances of every query -> float64 [m]."""
     cells = cell_index(x, y, minx, miny, inv_cw, ncol, nrow)
     qcell = cell_index(qx, qy, minx, miny, inv_cw, ncol, nrow)
@@ -87,6 +89,9 @@ def robs_lower_bound_sum(x, y, qx, qy, k, minx, miny, cw, inv_cw, ncol, nrow, sl
             mult = c[L + 1] - c[L]
             if mult > 0:
                 s += float(mult) * D[L]
+        if dense_limit is not None and int(cnt[1, j]) > dense_limit:
+            out[j] = s
+            continue
         # the 3 x 3 block's points nearer than D_1
         idx = np.concatenate([order[start[r * ncol + max(col - 1, 0)]:start[r * ncol + min(col + 1, ncol - 1) + 1]]
                               for r in range(max(row - 1, 0), min(row + 2, nrow))])
@@ -104,6 +109,6 @@ def robs_lower_bound_sum(x, y, qx, qy, k, minx, miny, cw, inv_cw, ncol, nrow, sl
     return out
 
 
-def certified(x, y, qx, qy, k, minx, miny, cw, inv_cw, ncol, nrow, slack, sum_min):
+def certified(x, y, qx, qy, k, minx, miny, cw, inv_cw, ncol, nrow, slack, sum_min, dense_limit=None):
     """True where the bound proves the sum of the k nearest distances exceeds sum_min."""
-    return robs_lower_bound_sum(x, y, qx, qy, k, minx, miny, cw, inv_cw, ncol, nrow, slack) > sum_min
+    return robs_lower_bound_sum(x, y, qx, qy, k, minx, miny, cw, inv_cw, ncol, nrow, slack, dense_limit) > sum_min

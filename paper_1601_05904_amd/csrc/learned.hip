@@ -670,7 +670,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
     const float tx = (fx - minx) * inv, ty = (fy - miny) * inv;
     const int c0 = clamp_cell(tx, ncol), r0 = clamp_cell(ty, nrow);
     // the scan's bounds: the own cell and lane g's neighbour segment
-    const int o0 = cell_start[r0 * ncol + c0], o1 = cell_start[r0 * ncol + c0 + 1];
+    const int o0 = cell_start[r0 * ncol + c0];
+    int o1 = cell_start[r0 * ncol + c0 + 1];
     int srow, sa, sb, p0 = 0, p1 = 0;
     const bool seg = segment(c0, r0, srow, sa, sb);
     if (seg) {
@@ -702,20 +703,46 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
     }
     float y = __builtin_nanf("");
     if constexpr (kNet) y = mlp_tile(d, net, lane, pack8(f));
-    // nearest point in the 3 x 3 block: the own cell split over the 4 lanes, then each lane's
+    const double px = fx, py = fy;
+    // What the scan below has to find depends on what is decided without it (all inputs
+    // here are the same on a query's four lanes): a query that takes the exact kNN in any case
+    // needs no scan (that search gives its d1); a skipped one needs its nearest distance
+    // (mode 1); one the certificate may still accept needs the statistics of its 3 x 3 block
+    // (mode 2).  A 3 x 3 block holding more than 8 k + 16 points is left to the exact path:
+    // such a query's R lies far below the saturation point (k neighbours within about a cell).
+    bool cert = false;
+    if constexpr (kCert) {
+      n0 += __shfl_xor(n0, 16, 64);
+      n1 += __shfl_xor(n1, 16, 64);
+      n2 += __shfl_xor(n2, 16, 64);
+      n0 += __shfl_xor(n0, 32, 64);
+      n1 += __shfl_xor(n1, 32, 64);
+      n2 += __shfl_xor(n2, 32, 64);
+      cert = certified_saturated(px, py, c0, r0, ncol, nrow, minxd, minyd, cwd, slack_cells, n0, n1, n2, k,
+                                 cert_sum_min);
+    }
+    double alpha_net = 0.0;
+    bool net_fall = true;
+    if constexpr (kNet) net_fall = decide_one((double)y, 1.0f, ap, rule == 3 ? 1 : rule, delta, r_sat_lo, r_sat_hi,
+                                              &alpha_net);
+    const int mode = !valid ? 0 : cert ? 1 : (kCert && n1 <= 8 * k + 16) ? 2 : !net_fall ? 1 : 0;
+    if (mode == 0) {
+      o1 = o0;
+      p1 = p0;
+    }
+    // Nearest point in the 3 x 3 block: the own cell split over the 4 lanes, then each lane's
     // neighbour segment unless all of it lies farther than the own cell's nearest, then the
     // minimum over the 4 lanes.  float32 suffices: the value only sets the power-of-two
     // scale of the pair weights; a coincident point (which lies in the own cell) is found
-    // exactly, as a zero difference.
-    // With the certificate, every point of the 3 x 3 block nearer than D_1 (the distance to
-    // the block's open sides, less the binning slack) is counted and its distance summed.
-    const double px = fx, py = fy;
+    // exactly, as a zero difference.  In mode 2 every point of the block nearer than D_1
+    // (the distance to the block's open sides, less the binning slack) is also counted and
+    // its distance summed, and a segment is left out only when it lies wholly beyond D_1.
     float best = INFINITY;
     int hit = 0;
     double d_1 = 0.0, v_sum = 0.0;
     float d_1sq = 0.0f, v_max = 0.0f;
     int v_cnt = 0;
-    if constexpr (kCert) {
+    if (kCert && mode == 2) {
       d_1 = block_side_distance(px, py, c0, r0, 1, ncol, nrow, minxd, minyd, cwd, slack_cells);
       d_1sq = (float)(d_1 * d_1);
     }
@@ -743,8 +770,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
                        : g == 1 ? (minyd + ((double)r0 + 1.0 - slack_cells) * cwd) - py
                        : g == 2 ? px - (minxd + ((double)c0 + slack_cells) * cwd)
                                 : (minxd + ((double)c0 + 1.0 - slack_cells) * cwd) - px;
-      // (with the certificate, only a segment wholly beyond D_1 is left out)
-      if (e > 0.0 && e * e > (double)best && (!kCert || e >= d_1)) p1 = p0;
+      if (e > 0.0 && e * e > (double)best && (mode != 2 || e >= d_1)) p1 = p0;
     }
     if (seg) {
       for (int p = p0; p < p1; ++p) {
@@ -766,12 +792,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
     hit |= __shfl_xor(hit, 16, 64);
     hit |= __shfl_xor(hit, 32, 64);
     if constexpr (kCert) {
-      n0 += __shfl_xor(n0, 16, 64);
-      n1 += __shfl_xor(n1, 16, 64);
-      n2 += __shfl_xor(n2, 16, 64);
-      n0 += __shfl_xor(n0, 32, 64);
-      n1 += __shfl_xor(n1, 32, 64);
-      n2 += __shfl_xor(n2, 32, 64);
       v_cnt += __shfl_xor(v_cnt, 16, 64);
       v_cnt += __shfl_xor(v_cnt, 32, 64);
       v_sum += __shfl_xor(v_sum, 16, 64);
@@ -792,21 +812,22 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
     else
       v = dout > 0 ? dout * dout : 0;  // lower bound
     const float d1 = hit ? 0.0f : fmaxf((float)v, FLT_MIN);
+    // the decision: a coincident query (d1 = 0) and a query not scanned take the exact path;
+    // then the certificate (counts, else the 3 x 3 distances), then the network's rule
     double alpha = 0.0;
     bool fall = true;
-    bool cert = false;
-    if constexpr (kCert)
-      cert = d1 != 0.0f &&
-             (certified_saturated(px, py, c0, r0, ncol, nrow, minxd, minyd, cwd, slack_cells, n0, n1, n2, k,
-                                  cert_sum_min) ||
-              certified_by_distances(
-                  v_sum, v_cnt, v_max, n2, k, d_1,
-                  block_side_distance(px, py, c0, r0, 2, ncol, nrow, minxd, minyd, cwd, slack_cells), cert_sum_min));
-    if (cert) {
-      fall = false;
-      alpha = ap.levels[4];
-    } else if (kNet) {
-      fall = decide_one((double)y, d1, ap, rule == 3 ? 1 : rule, delta, r_sat_lo, r_sat_hi, &alpha);
+    if (mode != 0 && d1 != 0.0f) {
+      if (kCert && mode == 2 && !cert)
+        cert = certified_by_distances(
+            v_sum, v_cnt, v_max, n2, k, d_1,
+            block_side_distance(px, py, c0, r0, 2, ncol, nrow, minxd, minyd, cwd, slack_cells), cert_sum_min);
+      if (cert) {
+        fall = false;
+        alpha = ap.levels[4];
+      } else if (!net_fall) {
+        fall = false;
+        alpha = alpha_net;
+      }
     }
     flag[t] = fall ? 1u : 0u;
     if (!fall) {

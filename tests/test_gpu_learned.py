@@ -289,7 +289,7 @@ def _certificate_oracle(ds, k, margin=0.0):
     r_sat = 0.0 + 2.0 / np.pi * np.arccos(-0.8)
     sum_min = k * gp["r_exp"] * min(r_sat, 2.0) * (1 + 1e-6) * (1 + margin)
     return C.certified(ds.x, ds.y, ds.qx, ds.qy, k, b[0], b[1], gp["cw"], gp["inv_cw"], gp["ncol"], gp["nrow"],
-                       slack, sum_min)
+                       slack, sum_min, dense_limit=8 * k + 16)
 
 
 @pytest.mark.parametrize("case", ["mixture", "uniform_k1", "small_grid"])

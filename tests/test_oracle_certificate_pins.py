@@ -51,6 +51,10 @@ def test_hand_derived_case():
     got = bound(x, y, qx, qy, 4, b, gp)[0]
     assert got == pytest.approx(sum(near) + d1, abs=1e-12)
     assert got == pytest.approx(0.38489, abs=1e-4)
+    # without the 3 x 3 route (dense_limit below c_1): the count bound, j = 2, 3 >= D_0, j = 4 >= D_1
+    only_counts = C.robs_lower_bound_sum(x, y, qx, qy, 4, b[0], b[1], gp["cw"], gp["inv_cw"], 11, 11,
+                                         slack_for(11, 11), dense_limit=2)[0]
+    assert only_counts == pytest.approx(2 * d0 + d1, abs=1e-12)
     # k = 6: K = 4; j = 5, 6 lie beyond the 5 x 5 block
     assert bound(x, y, qx, qy, 6, b, gp)[0] == pytest.approx(sum(near) + d1 + 2 * d2, abs=1e-12)
     # k = 1: K = 1 < v_cnt = 3 -> the three distances less twice the largest (0.0139)
