@@ -9,11 +9,12 @@ workload is n = m = 2^20 uniform points, k = 10 (synthetic, seeded).
 Printed: one JSON line with the metric, the pair kernel's roofline fraction
 (its duration measured with HIP events on the run's stream), the plain FP64
 CPU oracle timed on a bounded sample of the same workload on this host, and
-the z error of the timed run on that sample.  Two more measurements ride on
-the same line: "learned_r" (plain vs learned-R on the clustered 2^20
-workload, after training the network on held-out sets), "batch" (256
-independent jobs as one autotuned plan replayed as a HIP graph) "clustered" (the
-2^18 mixture workload) and "paper_rule" (the paper's kNN stop rule against exact kNN);
+the z error of the timed run on that sample.  More measurements ride on the
+same line: "learned_r" (plain vs learned-R on the clustered 2^20 workload,
+after training the network on held-out sets, for the network's fallback rule,
+the certified rule and the two combined), "batch" (256 independent jobs as one
+autotuned plan replayed as a HIP graph), "clustered" (the 2^18 mixture
+workload) and "paper_rule" (the paper's kNN stop rule against exact kNN);
 the plain run also reports its grid and kNN stages against
 HBM ("stage_bandwidth") and a rate with host-memory copies included ("host_inclusive").
 
