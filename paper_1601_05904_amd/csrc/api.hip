@@ -224,8 +224,11 @@ hipError_t scalar_staging(GridScalars** slot, hipEvent_t* ev) {
   return hipSuccess;
 }
 
+// outer (may be null): the caller's temporaries, released when the caller's call ends, so the
+// release's event records are issued after the rest of the caller's work, not between the grid
+// build and the next stage.
 aidw_status build_grid_impl(const float* x, const float* y, int64_t n, const float* qx, const float* qy, int64_t m,
-                            const aidw_params* p, hipStream_t s, bool async, aidw_grid** out) {
+                            const aidw_params* p, hipStream_t s, bool async, aidw_grid** out, Temps* outer = nullptr) {
   aidw_grid* g = new aidw_grid();
   g->n = n;
   g->async = async;
@@ -244,7 +247,8 @@ aidw_status build_grid_impl(const float* x, const float* y, int64_t n, const flo
   GridScalars* pinned = nullptr;
   hipEvent_t ready = nullptr;
   if ((e = scalar_staging(&pinned, &ready)) != hipSuccess) return cleanup(hip_fail(e, "scalar staging"));
-  Temps t(s);
+  Temps local(s);
+  Temps& t = outer ? *outer : local;
   BoundsPartial* part = nullptr;
   uint32_t *keys, *vals, *tk, *tv, *hist, *scan;
   if ((e = t.get(&part, kBoundsBlocks)) != hipSuccess || (e = t.get(&keys, n)) != hipSuccess ||
@@ -675,7 +679,8 @@ aidw_status aidw_run(const float* x, const float* y, const float* z, int64_t n, 
     HIP_TRY(hipEventRecord(ev[0], stream), "event");
   }
   aidw_grid* g = nullptr;
-  if ((st = build_grid_impl(x, y, n, qx, qy, m, p, stream, true, &g)) != AIDW_OK) return st;
+  Temps grid_temps(stream);
+  if ((st = build_grid_impl(x, y, n, qx, qy, m, p, stream, true, &g, &grid_temps)) != AIDW_OK) return st;
   if (ev) {
     hipError_t e = hipEventRecord(ev[1], stream);
     if (e != hipSuccess) {
@@ -914,7 +919,8 @@ aidw_status aidw_run_learned(const float* x, const float* y, const float* z, int
     HIP_TRY(hipEventRecord(ev[0], stream), "event");
   }
   aidw_grid* g = nullptr;
-  if ((st = build_grid_impl(x, y, n, qx, qy, m, p, stream, true, &g)) != AIDW_OK) return st;
+  Temps grid_temps(stream);
+  if ((st = build_grid_impl(x, y, n, qx, qy, m, p, stream, true, &g, &grid_temps)) != AIDW_OK) return st;
   uint32_t host_count = 0;
   {
     Temps t(stream);
