@@ -348,6 +348,10 @@ def learned_comparison(args, with_oracle):
     # followed by the network's rule
     out["certified"] = one_rule(L.CERTIFIED)
     out["certified_then_alpha_exact"] = one_rule(L.CERTIFIED_THEN_ALPHA_EXACT)
+    # the rule whose alpha equals the exact path's for every query (the z error of the plain run)
+    out["at_equal_z_error"] = {"rule": "certified", "speedup_rstage": out["certified"]["speedup_rstage"],
+                               "speedup_end_to_end": out["certified"]["speedup_end_to_end"],
+                               "alpha_mismatch_fraction": out["certified"]["alpha_mismatch_fraction"]}
     out["training"] = {"pairs": npairs, "epochs": 16, "batch": 1024, "lr": 2e-3, "final_loss": float(losses[-1]),
                        "data_s": t1 - t0, "train_s": t2 - t1}
     if with_oracle:
