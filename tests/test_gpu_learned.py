@@ -343,3 +343,20 @@ def test_certified_then_network_rule(T):
     assert nfb3 <= min(nfb1, nfb2)
     assert np.all(al_3[cert_strict] == al_p[cert_strict])
     assert np.all(np.isfinite(qz_3))
+
+
+def test_certified_rule_full_size(T):
+    """Rule 2 on the clustered 2^20 workload in the configuration the benchmark times: every
+    query's alpha equals the plain path's (bitwise), most queries skip the kNN search, and z
+    on sampled queries is within the error bar of the FP64 oracle."""
+    aidw, L = mods()
+    ds = W.learned_1m()
+    mlp = L.MLP(seed=3)
+    qz_p, al_p, _, qz_l, al_l, rh, nfb = _plain_and_learned(T, ds, mlp, L.CERTIFIED, 0.0, ds.k)
+    assert np.array_equal(al_l, al_p)
+    assert 1.0 - nfb / ds.m > 0.9
+    assert np.allclose(qz_l, qz_p, rtol=2e-6, atol=1e-7)
+    sel = W.sample_queries(ds.m, 256, ds.seed)
+    ref = O.aidw(ds.x, ds.y, ds.z, ds.qx, ds.qy, k=ds.k, qsel=sel)
+    e = np.abs(qz_l[sel].astype(np.float64) - ref["z"]) / np.maximum(np.abs(ref["z"]), ref["s"])
+    assert e.max() <= 1e-5
