@@ -185,17 +185,14 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_reduce(const uint32_t* __
   if (threadIdx.x == 0) sums[blockIdx.x] = tot;
 }
 
-// Exclusive scan of the block sums in place (one block, any length).
-__global__ __launch_bounds__(kScanThreads) void k_scan_top(uint32_t* __restrict__ sums, int nsums) {
-  uint32_t carry = 0;
-  for (int base = 0; base < nsums; base += kScanThreads) {
-    const int i = base + threadIdx.x;
-    const uint32_t v = i < nsums ? sums[i] : 0u;
-    uint32_t tot;
-    const uint32_t ex = block_exclusive_scan(v, &tot);
-    if (i < nsums) sums[i] = carry + ex;
-    carry += tot;
-  }
+// The exclusive prefix of block b: the sum of the totals sums[0 .. b) of the blocks before it
+// (the same value in every thread).
+__device__ inline uint32_t block_prefix(const uint32_t* __restrict__ sums, int b) {
+  uint32_t s = 0;
+  for (int i = threadIdx.x; i < b; i += kScanThreads) s += sums[i];
+  uint32_t tot;
+  block_exclusive_scan(s, &tot);
+  return tot;
 }
 
 __global__ __launch_bounds__(kScanThreads) void k_scan_down(const uint32_t* __restrict__ in, size_t len,
@@ -209,7 +206,8 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_down(const uint32_t* __re
     s += v[i];
   }
   uint32_t tot;
-  uint32_t run = sums[blockIdx.x] + block_exclusive_scan(s, &tot);
+  const uint32_t pre = block_prefix(sums, blockIdx.x);
+  uint32_t run = pre + block_exclusive_scan(s, &tot);
   for (int i = 0; i < kScanItems; ++i) {
     if (base + i < len) out[base + i] = run;
     run += v[i];
@@ -232,7 +230,8 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_compact(const uint32_t* _
     s += v[i];
   }
   uint32_t tot;
-  uint32_t run = sums[blockIdx.x] + block_exclusive_scan(s, &tot);
+  const uint32_t pre = block_prefix(sums, blockIdx.x);
+  uint32_t run = pre + block_exclusive_scan(s, &tot);
   for (int i = 0; i < kScanItems; ++i) {
     if (v[i]) list[run] = vals[base + i];
     run += v[i];
@@ -403,7 +402,6 @@ void radix_pass(const uint32_t* ki, const uint32_t* vi, uint32_t* ko, uint32_t* 
   const int nsb = div_up((int64_t)hlen, kScanChunk);
   hipLaunchKernelGGL(k_radix_hist<BITS>, dim3(nblocks), dim3(kSortThreads), 0, s, ki, n, shift, hist, nblocks);
   hipLaunchKernelGGL(k_scan_reduce, dim3(nsb), dim3(kScanThreads), 0, s, hist, hlen, scan_tmp);
-  hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kScanThreads), 0, s, scan_tmp, nsb);
   hipLaunchKernelGGL(k_scan_down, dim3(nsb), dim3(kScanThreads), 0, s, hist, hlen, scan_tmp, hist);
   hipLaunchKernelGGL(k_radix_scatter<BITS>, dim3(nblocks), dim3(kSortThreads), 0, s, ki, vi, ko, vo, n, shift, hist,
                      nblocks);
@@ -481,7 +479,6 @@ hipError_t compact_flags(const uint32_t* flag, const uint32_t* vals, size_t len,
   if (len == 0) return hipSuccess;
   const int nsb = (int)((len + kScanChunk - 1) / kScanChunk);
   hipLaunchKernelGGL(k_scan_reduce, dim3(nsb), dim3(kScanThreads), 0, s, flag, len, tmp);
-  hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kScanThreads), 0, s, tmp, nsb);
   hipLaunchKernelGGL(k_scan_compact, dim3(nsb), dim3(kScanThreads), 0, s, flag, len, tmp, vals, list, total);
   return hipGetLastError();
 }
@@ -491,7 +488,6 @@ hipError_t exclusive_scan_u32(const uint32_t* in, uint32_t* out, size_t len, uin
   if (len == 0) return hipSuccess;
   const int nsb = (int)((len + kScanChunk - 1) / kScanChunk);
   hipLaunchKernelGGL(k_scan_reduce, dim3(nsb), dim3(kScanThreads), 0, s, in, len, tmp);
-  hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kScanThreads), 0, s, tmp, nsb);
   hipLaunchKernelGGL(k_scan_down, dim3(nsb), dim3(kScanThreads), 0, s, in, len, tmp, out);
   if (total) hipLaunchKernelGGL(k_scan_total, dim3(1), dim3(64), 0, s, in, out, len, total);
   return hipGetLastError();
