@@ -105,6 +105,11 @@ hipError_t radix_sort_pairs_to(uint32_t* keys, uint32_t* vals, uint32_t* tmp_key
 // The 10-bit passes of the same sort for the digits at shift0, shift0 + 10, ... below `bits`
 // (shift0 = 0 and bits = 10 is one pass; a later call with shift0 = 10 continues it on the
 // buffers the first call returned).
+// Cell keys of the data points (keys [n], vals [n] = index) and the first 10-bit pass of their
+// stable radix sort into tmp_keys / tmp_vals, the key computation fused into the histogram.
+hipError_t cell_keys_first_pass(const float* x, const float* y, int n, const GridScalars* gs, uint32_t* keys,
+                                uint32_t* vals, uint32_t* tmp_keys, uint32_t* tmp_vals, uint32_t* hist,
+                                uint32_t* scan_tmp, hipStream_t s);
 hipError_t radix_sort_wide_from(uint32_t* keys, uint32_t* vals, uint32_t* tmp_keys, uint32_t* tmp_vals, int n,
                                 int shift0, int bits, uint32_t* hist, uint32_t* scan_tmp, hipStream_t s,
                                 uint32_t** out_keys, uint32_t** out_vals);

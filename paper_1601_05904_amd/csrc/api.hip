@@ -263,11 +263,9 @@ aidw_status build_grid_impl(const float* x, const float* y, int64_t n, const flo
   if ((e = hipMemcpyAsync(pinned, g->dev, sizeof(GridScalars), hipMemcpyDeviceToHost, s)) != hipSuccess ||
       (e = hipEventRecord(ready, s)) != hipSuccess)
     return cleanup(hip_fail(e, "reading grid scalars"));
-  if ((e = launch_cell_keys(x, y, (int)n, g->dev, keys, vals, s)) != hipSuccess)
-    return cleanup(hip_fail(e, "cell key kernel"));
-  uint32_t *sk, *sv;  // the pairs sorted so far (in keys / vals or in the temporaries)
-  if ((e = radix_sort_wide_from(keys, vals, tk, tv, (int)n, 0, kRadixBitsWide, hist, scan, s, &sk, &sv)) != hipSuccess)
-    return cleanup(hip_fail(e, "radix sort"));
+  if ((e = cell_keys_first_pass(x, y, (int)n, g->dev, keys, vals, tk, tv, hist, scan, s)) != hipSuccess)
+    return cleanup(hip_fail(e, "cell keys / first sort pass"));
+  uint32_t *sk = tk, *sv = tv;  // the pairs sorted so far (in keys / vals or in the temporaries)
   if ((e = hipEventSynchronize(ready)) != hipSuccess) return cleanup(hip_fail(e, "synchronising grid scalars"));
   g->host = *pinned;
   const GridScalars& h = g->host;
@@ -396,11 +394,12 @@ aidw_status interp_impl(const float* x, const float* y, const float* z, int64_t 
   if (!naive) HIP_TRY(launch_pad_copy(x, y, z, (int)n, xp, yp, zp, s), "padding copy");
   HIP_TRY(hipMemsetAsync(count, 0, sizeof(uint32_t), s), "clearing coincidence count");
   HIP_TRY(launch_coincident_list(d1sq, (int)m, count, list, s), "coincidence list kernel");
+  const float* alpha_use = alpha_f;
   if (alpha_in) {  // alpha given per query: only the class keys are needed
-    HIP_TRY(hipMemcpyAsync(alpha_f, alpha_in, sizeof(float) * m, hipMemcpyDeviceToDevice, s), "copying alpha");
+    alpha_use = alpha_in;
     if (alpha_out)
       HIP_TRY(hipMemcpyAsync(alpha_out, alpha_in, sizeof(float) * m, hipMemcpyDeviceToDevice, s), "copying alpha");
-    HIP_TRY(launch_class_keys(alpha_f, (int)m, keys, perm, s), "class key kernel");
+    HIP_TRY(launch_class_keys(alpha_in, (int)m, keys, perm, s), "class key kernel");
   } else {
     HIP_TRY(launch_alpha_class(r_obs, (int)m, ap, alpha_f, alpha_out, keys, perm, s), "alpha kernel");
   }
@@ -409,9 +408,10 @@ aidw_status interp_impl(const float* x, const float* y, const float* z, int64_t 
     HIP_TRY(radix_sort_pairs_to(keys, perm, tk, tv, (int)m, 4, hist, scan, s, &ckeys, &cperm), "class sort");
   if (ev_begin) HIP_TRY(hipEventRecord(ev_begin, s), "event");
   if (naive) {
-    HIP_TRY(launch_interp_naive(x, y, z, (int)n, qx, qy, alpha_f, d1sq, (int)m, qz, s), "interpolation kernel (untiled)");
+    HIP_TRY(launch_interp_naive(x, y, z, (int)n, qx, qy, alpha_use, d1sq, (int)m, qz, s),
+            "interpolation kernel (untiled)");
   } else {
-    HIP_TRY(launch_interp(xp, yp, zp, (int)n, qx, qy, alpha_f, d1sq, cperm, ckeys, (int)m, fast_mask, q, split, qz,
+    HIP_TRY(launch_interp(xp, yp, zp, (int)n, qx, qy, alpha_use, d1sq, cperm, ckeys, (int)m, fast_mask, q, split, qz,
                           partial, s),
             "interpolation kernel");
   }

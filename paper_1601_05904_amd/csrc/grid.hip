@@ -75,19 +75,22 @@ __global__ __launch_bounds__(256) void k_finalize(const BoundsPartial* __restric
 
 // Section 4.1.2: cell of each data point, (x - minX) * inv_cw in float32 truncated,
 // clamped into the grid; key = row * nCol + col, value = original index.
+// Cell of a point (Section 4.1.2): column and row from float32 offsets scaled by 1 / cell width,
+// truncated and clamped to the grid.
+__device__ inline uint32_t cell_key(float x, float y, float minx, float miny, float inv, int ncol, int nrow) {
+  const float tx = (x - minx) * inv;
+  const float ty = (y - miny) * inv;
+  int col = (int)tx, row = (int)ty;
+  col = col > ncol - 1 ? ncol - 1 : (col < 0 ? 0 : col);
+  row = row > nrow - 1 ? nrow - 1 : (row < 0 ? 0 : row);
+  return (uint32_t)(row * ncol + col);
+}
 __global__ __launch_bounds__(256) void k_cell_keys(const float* __restrict__ x, const float* __restrict__ y, int n,
                                                    const GridScalars* __restrict__ gs, uint32_t* __restrict__ keys,
                                                    uint32_t* __restrict__ vals) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  const float minx = gs->minx, miny = gs->miny, inv = gs->inv_cw;
-  const int ncol = gs->ncol, nrow = gs->nrow;
-  const float tx = (x[i] - minx) * inv;
-  const float ty = (y[i] - miny) * inv;
-  int col = (int)tx, row = (int)ty;
-  col = col > ncol - 1 ? ncol - 1 : (col < 0 ? 0 : col);
-  row = row > nrow - 1 ? nrow - 1 : (row < 0 ? 0 : row);
-  keys[i] = (uint32_t)(row * ncol + col);
+  keys[i] = cell_key(x[i], y[i], gs->minx, gs->miny, gs->inv_cw, gs->ncol, gs->nrow);
   vals[i] = (uint32_t)i;
 }
 
@@ -145,6 +148,39 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_hist(const uint32_t* __r
 #pragma unroll
   for (int r = 0; r < kSortItems; ++r)
     if (base + r * kSortThreads + (int)threadIdx.x < n) atomicAdd(&h[(key[r] >> shift) & (R - 1)], 1u);
+  __syncthreads();
+  for (int d = threadIdx.x; d < R; d += kSortThreads) hist[(size_t)d * nblocks + blockIdx.x] = h[d];
+}
+// The first pass's histogram (digit 0) fused with the cell keys: each point's key is computed
+// as in k_cell_keys and stored with its index, then counted.
+template <int BITS>
+__global__ __launch_bounds__(kSortThreads) void k_radix_hist_cells(const float* __restrict__ x,
+                                                                   const float* __restrict__ y, int n,
+                                                                   const GridScalars* __restrict__ gs,
+                                                                   uint32_t* __restrict__ keys,
+                                                                   uint32_t* __restrict__ vals,
+                                                                   uint32_t* __restrict__ hist, int nblocks) {
+  constexpr int R = 1 << BITS;
+  __shared__ uint32_t h[R];
+  for (int i = threadIdx.x; i < R; i += kSortThreads) h[i] = 0;
+  const float minx = gs->minx, miny = gs->miny, inv = gs->inv_cw;
+  const int ncol = gs->ncol, nrow = gs->nrow;
+  const int base = blockIdx.x * kSortTile;
+  uint32_t key[kSortItems];
+#pragma unroll
+  for (int r = 0; r < kSortItems; ++r) {
+    const int i = base + r * kSortThreads + threadIdx.x;
+    key[r] = 0u;
+    if (i < n) {
+      key[r] = cell_key(x[i], y[i], minx, miny, inv, ncol, nrow);
+      keys[i] = key[r];
+      vals[i] = (uint32_t)i;
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < kSortItems; ++r)
+    if (base + r * kSortThreads + (int)threadIdx.x < n) atomicAdd(&h[key[r] & (R - 1)], 1u);
   __syncthreads();
   for (int d = threadIdx.x; d < R; d += kSortThreads) hist[(size_t)d * nblocks + blockIdx.x] = h[d];
 }
@@ -425,6 +461,21 @@ hipError_t radix_sort_passes(uint32_t*& ki, uint32_t*& vi, uint32_t*& ko, uint32
 }
 }  // namespace
 
+hipError_t cell_keys_first_pass(const float* x, const float* y, int n, const GridScalars* gs, uint32_t* keys,
+                                uint32_t* vals, uint32_t* tmp_keys, uint32_t* tmp_vals, uint32_t* hist,
+                                uint32_t* scan_tmp, hipStream_t s) {
+  constexpr int BITS = kRadixBitsWide;
+  const int nblocks = div_up(n, kSortTile);
+  const size_t hlen = ((size_t)1 << BITS) * nblocks;
+  const int nsb = div_up((int64_t)hlen, kScanChunk);
+  hipLaunchKernelGGL(k_radix_hist_cells<BITS>, dim3(nblocks), dim3(kSortThreads), 0, s, x, y, n, gs, keys, vals, hist,
+                     nblocks);
+  hipLaunchKernelGGL(k_scan_reduce, dim3(nsb), dim3(kScanThreads), 0, s, hist, hlen, scan_tmp);
+  hipLaunchKernelGGL(k_scan_down, dim3(nsb), dim3(kScanThreads), 0, s, hist, hlen, scan_tmp, hist);
+  hipLaunchKernelGGL(k_radix_scatter<BITS>, dim3(nblocks), dim3(kSortThreads), 0, s, keys, vals, tmp_keys, tmp_vals, n,
+                     0, hist, nblocks);
+  return hipGetLastError();
+}
 hipError_t radix_sort_wide_from(uint32_t* keys, uint32_t* vals, uint32_t* tmp_keys, uint32_t* tmp_vals, int n,
                                 int shift0, int bits, uint32_t* hist, uint32_t* scan_tmp, hipStream_t s,
                                 uint32_t** out_keys, uint32_t** out_vals) {
