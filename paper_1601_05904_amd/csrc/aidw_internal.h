@@ -161,9 +161,11 @@ struct AlphaParams {
 };
 
 // Eq. 4-6 per query -> alpha_f [m] (and alpha_out if non-null); class keys [m] (p in 1..8 when
-// alpha == p exactly, else 0) and the identity permutation vals [m], ready for a stable sort by key.
+// alpha == p exactly, else 0) and the identity permutation vals [m], ready for a stable sort by key;
+// the queries with d1sq = 0 appended to list, *count (cleared before) their number.
 hipError_t launch_alpha_class(const float* r_obs, int m, const AlphaParams& ap, float* alpha_f, float* alpha_out,
-                              uint32_t* keys, uint32_t* vals, hipStream_t s);
+                              uint32_t* keys, uint32_t* vals, const float* d1sq, uint32_t* count, uint32_t* list,
+                              hipStream_t s);
 // Pair kernels over the queries in class order (perm, sorted keys skeys); fast_mask bit p
 // requests the integer-power kernel for class p (the general kernel covers every other block).
 // x, y, z are the padded copies made by launch_pad_copy.
@@ -175,10 +177,10 @@ hipError_t launch_interp_naive(const float* x, const float* y, const float* z, i
                                const float* alpha_f, const float* d1sq, int m, float* qz, hipStream_t s);
 // Zero-padded copies of x, y, z for the pair kernels, which may prefetch one chunk past n.
 int interp_padded_len(int n);
+// zero_word (may be null) is cleared by the same launch.
 hipError_t launch_pad_copy(const float* x, const float* y, const float* z, int n, float* xp, float* yp, float* zp,
-                           hipStream_t s);
+                           uint32_t* zero_word, hipStream_t s);
 hipError_t launch_combine(const double2* partial, int m, int split, float* qz, hipStream_t s);
-hipError_t launch_coincident_list(const float* d1sq, int m, uint32_t* count, uint32_t* list, hipStream_t s);
 hipError_t launch_fixup_grid(const uint32_t* count, const uint32_t* list, const float* qx, const float* qy,
                              const GridScalars* gs, const int32_t* cell_start, const float* sx, const float* sy,
                              const int32_t* sidx, const float* z, float* qz, hipStream_t s);
@@ -230,8 +232,10 @@ hipError_t launch_adam(const MlpDevice& d, const float* grad, float lr, float b1
 hipError_t launch_accumulate_loss(const float* grad, float* epoch_loss, int epoch, float scale, hipStream_t s);
 hipError_t launch_alpha_fallback(const uint32_t* perm, const uint32_t* count, int m, const float* r_obs,
                                  const AlphaParams& ap, float* alpha_f, hipStream_t s);
-// Pair-kernel class keys from a given alpha (alpha == p in 1..8 -> p, else 0) and the identity permutation.
-hipError_t launch_class_keys(const float* alpha_f, int m, uint32_t* keys, uint32_t* vals, hipStream_t s);
+// Pair-kernel class keys from a given alpha (alpha == p in 1..8 -> p, else 0) and the identity permutation;
+// the coincident-query list as launch_alpha_class.
+hipError_t launch_class_keys(const float* alpha_f, int m, uint32_t* keys, uint32_t* vals, const float* d1sq,
+                             uint32_t* count, uint32_t* list, hipStream_t s);
 // Shuffle keys for training: a 32-bit hash of (seed, epoch, i), and the identity values.
 hipError_t launch_shuffle_keys(uint64_t seed, int epoch, int count, uint32_t* keys, uint32_t* vals, hipStream_t s);
 

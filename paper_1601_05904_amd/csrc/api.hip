@@ -391,17 +391,21 @@ aidw_status interp_impl(const float* x, const float* y, const float* z, int64_t 
       (e = t.get(&scan, radix_scan_tmp_words((int)m))) != hipSuccess || (e = t.get(&xp, npad)) != hipSuccess ||
       (e = t.get(&yp, npad)) != hipSuccess || (e = t.get(&zp, npad)) != hipSuccess)
     return hip_fail(e, "allocating interpolation buffers");
-  if (!naive) HIP_TRY(launch_pad_copy(x, y, z, (int)n, xp, yp, zp, s), "padding copy");
-  HIP_TRY(hipMemsetAsync(count, 0, sizeof(uint32_t), s), "clearing coincidence count");
-  HIP_TRY(launch_coincident_list(d1sq, (int)m, count, list, s), "coincidence list kernel");
+  // the coincident-query count is cleared by the padding copy (or on its own for the untiled
+  // kernel) and the list filled by the class-key kernel
+  if (!naive)
+    HIP_TRY(launch_pad_copy(x, y, z, (int)n, xp, yp, zp, count, s), "padding copy");
+  else
+    HIP_TRY(hipMemsetAsync(count, 0, sizeof(uint32_t), s), "clearing coincidence count");
   const float* alpha_use = alpha_f;
   if (alpha_in) {  // alpha given per query: only the class keys are needed
     alpha_use = alpha_in;
     if (alpha_out)
       HIP_TRY(hipMemcpyAsync(alpha_out, alpha_in, sizeof(float) * m, hipMemcpyDeviceToDevice, s), "copying alpha");
-    HIP_TRY(launch_class_keys(alpha_in, (int)m, keys, perm, s), "class key kernel");
+    HIP_TRY(launch_class_keys(alpha_in, (int)m, keys, perm, d1sq, count, list, s), "class key kernel");
   } else {
-    HIP_TRY(launch_alpha_class(r_obs, (int)m, ap, alpha_f, alpha_out, keys, perm, s), "alpha kernel");
+    HIP_TRY(launch_alpha_class(r_obs, (int)m, ap, alpha_f, alpha_out, keys, perm, d1sq, count, list, s),
+            "alpha kernel");
   }
   uint32_t *ckeys = keys, *cperm = perm;  // the class order (in keys / perm or in the temporaries)
   if (fast_mask && !naive)

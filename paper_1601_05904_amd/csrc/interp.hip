@@ -47,12 +47,16 @@ using pair::kThreads;
 using pair::Lane;
 using pair::level_alpha;
 
-// Eq. 4-6 per query (float64), the query's class key and the identity permutation.
+// Eq. 4-6 per query (float64), the query's class key and the identity permutation; a query
+// with d1sq = 0 (coincident with a data point) is appended to list (count cleared before).
 __global__ __launch_bounds__(256) void k_alpha_class(const float* __restrict__ r_obs, int m, AlphaParams ap,
                                                      float* __restrict__ alpha_f, float* __restrict__ alpha_out,
-                                                     uint32_t* __restrict__ keys, uint32_t* __restrict__ vals) {
+                                                     uint32_t* __restrict__ keys, uint32_t* __restrict__ vals,
+                                                     const float* __restrict__ d1sq, uint32_t* __restrict__ count,
+                                                     uint32_t* __restrict__ list) {
   const int q = blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= m) return;
+  if (d1sq[q] == 0.0f) list[atomicAdd(count, 1u)] = (uint32_t)q;
   const double R = (double)r_obs[q] / ap.r_exp;                                  // Eq. 4
   const double alpha = level_alpha(fuzzy_mu(R, ap.r_min, ap.r_max), ap.levels);  // Eq. 5, 6
   const float af = (float)alpha;
@@ -62,10 +66,15 @@ __global__ __launch_bounds__(256) void k_alpha_class(const float* __restrict__ r
   vals[q] = (uint32_t)q;
 }
 
+// The class key of a given alpha, the identity permutation and the coincident-query list (as
+// k_alpha_class).
 __global__ __launch_bounds__(256) void k_class_keys(const float* __restrict__ alpha_f, int m,
-                                                    uint32_t* __restrict__ keys, uint32_t* __restrict__ vals) {
+                                                    uint32_t* __restrict__ keys, uint32_t* __restrict__ vals,
+                                                    const float* __restrict__ d1sq, uint32_t* __restrict__ count,
+                                                    uint32_t* __restrict__ list) {
   const int q = blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= m) return;
+  if (d1sq[q] == 0.0f) list[atomicAdd(count, 1u)] = (uint32_t)q;
   const float a = alpha_f[q];
   uint32_t key = 0;
   if (a >= 1.0f && a <= (float)kMaxIntPow && a == floorf(a)) key = (uint32_t)a;
@@ -174,12 +183,14 @@ __global__ __launch_bounds__(kThreads) void k_interp_naive(const float* __restri
   qz[q] = (float)(L.num(0) / L.den(0));
 }
 
-// Copies the data into zero-padded arrays of interp_padded_len(n) points.
+// Copies the data into zero-padded arrays of interp_padded_len(n) points; clears *zero_word
+// (may be null) on the way.
 __global__ __launch_bounds__(256) void k_pad_copy(const float* __restrict__ x, const float* __restrict__ y,
                                                   const float* __restrict__ z, int n, int npad,
                                                   float* __restrict__ xp, float* __restrict__ yp,
-                                                  float* __restrict__ zp) {
+                                                  float* __restrict__ zp, uint32_t* __restrict__ zero_word) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (zero_word && i == 0) *zero_word = 0u;
   if (i >= npad) return;
   const bool in = i < n;
   xp[i] = in ? x[i] : 0.0f;
@@ -198,14 +209,6 @@ __global__ __launch_bounds__(256) void k_combine(const double2* __restrict__ par
     den += v.y;
   }
   qz[q] = (float)(num / den);
-}
-
-// Queries whose nearest neighbour is at distance 0 coincide with data points.
-__global__ __launch_bounds__(256) void k_coincident_list(const float* __restrict__ d1sq, int m,
-                                                         uint32_t* __restrict__ count, uint32_t* __restrict__ list) {
-  const int q = blockIdx.x * blockDim.x + threadIdx.x;
-  if (q >= m) return;
-  if (d1sq[q] == 0.0f) list[atomicAdd(count, 1u)] = (uint32_t)q;
 }
 
 // Coincident query = mean z of the data points at its exact position (the limit
@@ -266,16 +269,18 @@ __global__ __launch_bounds__(256) void k_fixup_scan(const uint32_t* __restrict__
 }  // namespace
 
 hipError_t launch_alpha_class(const float* r_obs, int m, const AlphaParams& ap, float* alpha_f, float* alpha_out,
-                              uint32_t* keys, uint32_t* vals, hipStream_t s) {
+                              uint32_t* keys, uint32_t* vals, const float* d1sq, uint32_t* count, uint32_t* list,
+                              hipStream_t s) {
   if (m <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_alpha_class, dim3((m + 255) / 256), dim3(256), 0, s, r_obs, m, ap, alpha_f, alpha_out, keys,
-                     vals);
+                     vals, d1sq, count, list);
   return hipGetLastError();
 }
 
-hipError_t launch_class_keys(const float* alpha_f, int m, uint32_t* keys, uint32_t* vals, hipStream_t s) {
+hipError_t launch_class_keys(const float* alpha_f, int m, uint32_t* keys, uint32_t* vals, const float* d1sq,
+                             uint32_t* count, uint32_t* list, hipStream_t s) {
   if (m <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_class_keys, dim3((m + 255) / 256), dim3(256), 0, s, alpha_f, m, keys, vals);
+  hipLaunchKernelGGL(k_class_keys, dim3((m + 255) / 256), dim3(256), 0, s, alpha_f, m, keys, vals, d1sq, count, list);
   return hipGetLastError();
 }
 
@@ -320,21 +325,15 @@ hipError_t launch_interp_naive(const float* x, const float* y, const float* z, i
 }
 
 hipError_t launch_pad_copy(const float* x, const float* y, const float* z, int n, float* xp, float* yp, float* zp,
-                           hipStream_t s) {
+                           uint32_t* zero_word, hipStream_t s) {
   const int npad = interp_padded_len(n);
-  hipLaunchKernelGGL(k_pad_copy, dim3((npad + 255) / 256), dim3(256), 0, s, x, y, z, n, npad, xp, yp, zp);
+  hipLaunchKernelGGL(k_pad_copy, dim3((npad + 255) / 256), dim3(256), 0, s, x, y, z, n, npad, xp, yp, zp, zero_word);
   return hipGetLastError();
 }
 
 hipError_t launch_combine(const double2* partial, int m, int split, float* qz, hipStream_t s) {
   if (m <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_combine, dim3((m + 255) / 256), dim3(256), 0, s, partial, m, split, qz);
-  return hipGetLastError();
-}
-
-hipError_t launch_coincident_list(const float* d1sq, int m, uint32_t* count, uint32_t* list, hipStream_t s) {
-  if (m <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_coincident_list, dim3((m + 255) / 256), dim3(256), 0, s, d1sq, m, count, list);
   return hipGetLastError();
 }
 
