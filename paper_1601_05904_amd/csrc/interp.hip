@@ -9,12 +9,13 @@
 // and every VALU instruction reads the point directly as a scalar operand.
 // Each lane holds Q queries, which gives Q independent dependency chains per
 // data point.  Per pair (query j, point i) the lane evaluates, in float32,
-//     d2 = (qx - x)^2 + (qy - y)^2,  t = d2 * s_j,  w = 2^(nh_j * log2 t),
+//     t = (s_j qx - s_j x)^2 + (s_j qy - s_j y)^2,  w = 2^(nh_j * log2 t),
 //     num += w z,  den += w,
-// with s_j = 1 / d1sq_j (d1 = nearest-neighbour distance) and nh_j = -alpha_j / 2,
-// i.e. w = (d1 / d)^alpha_j: the common factor d1^alpha cancels in num / den,
-// keeps w <= ~1 (no overflow for any alpha) and keeps the argument of log2 near
-// 1 for the dominant near points, where the hardware log2 is most accurate.
+// with s_j the smallest power of two with s_j^2 d1sq_j >= 1 (d1 = nearest-neighbour
+// distance) and nh_j = -alpha_j / 2.  Scaling by a power of two is exact, so t is
+// the float32 d^2 times s_j^2: the common factor s_j^-alpha cancels in num / den,
+// w stays <= ~1 (no overflow for any alpha) and the argument of log2 stays near 1
+// for the dominant near points, where the hardware log2 is most accurate.
 // The float32 sums of each tile of kTile points are folded into (hi, lo)
 // two-sum pairs; the final num / den is formed in float64.  Splitting the data
 // axis (blockIdx.y) gives more wavefronts when m is small; the splits' float64
