@@ -360,3 +360,15 @@ def test_certified_rule_full_size(T):
     ref = O.aidw(ds.x, ds.y, ds.z, ds.qx, ds.qy, k=ds.k, qsel=sel)
     e = np.abs(qz_l[sel].astype(np.float64) - ref["z"]) / np.maximum(np.abs(ref["z"]), ref["s"])
     assert e.max() <= 1e-5
+
+
+def test_learned_rule_validation(T):
+    """An unknown rule or a negative delta is rejected before any work is queued."""
+    aidw, L = mods()
+    ds = W.make(500, 100, 5, 261)
+    x, y, z, qx, qy = (dev(T, getattr(ds, a)) for a in ("x", "y", "z", "qx", "qy"))
+    mlp = L.MLP(seed=2)
+    for rule, delta in ((4, 0.1), (-1, 0.1), (L.CERTIFIED, -1.0)):
+        with pytest.raises(aidw.AidwError) as e:
+            L.run_learned(x, y, z, qx, qy, aidw.Params(k=5), mlp, rule, delta)
+        assert e.value.code == -1
