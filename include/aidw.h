@@ -289,10 +289,11 @@ typedef enum {
   AIDW_FALLBACK_LITERAL = 0,     /* kNN when |R_hat - r_min| < delta or |R_hat - r_max| < delta; else alpha(R_hat) */
   AIDW_FALLBACK_ALPHA_EXACT = 1, /* skip kNN only when R_hat is delta beyond the points where alpha
                                     saturates (mu = 0.1 / 0.9 in Eq. 6); skipped queries get alpha_1 / alpha_5 */
-  AIDW_FALLBACK_CERTIFIED = 2,   /* skip kNN only when the point counts of the 1, 3 x 3 and 5 x 5 cell blocks
-                                    around the query bound Eq. 3's r_obs from below by enough to prove
-                                    mu > 0.9 (alpha = alpha_5 by Eq. 6): every query gets the alpha of the exact
-                                    path; the network is not evaluated (r_hat_out receives NaN); delta unused */
+  AIDW_FALLBACK_CERTIFIED = 2,   /* skip kNN only when a lower bound of Eq. 3's r_obs proves mu > 0.9
+                                    (alpha = alpha_5 by Eq. 6); the bound comes from the point counts of the
+                                    1, 3 x 3 and 5 x 5 cell blocks around the query and the exact distances of
+                                    the 3 x 3 block's points.  Every query gets the alpha of the exact path; the
+                                    network is not evaluated (r_hat_out receives NaN); delta is checked, unused */
   AIDW_FALLBACK_CERTIFIED_THEN_ALPHA_EXACT = 3 /* skip when certified as in 2, else apply rule 1 */
 } aidw_fallback_rule;
 

@@ -594,7 +594,8 @@ __global__ __launch_bounds__(256) void k_mlp_forward_mfma(MlpDevice d, const flo
 // there the registers of the loads in flight across the network spill 3 dwords to scratch,
 // which still measured faster than issuing those loads after the network (no spill) or
 // than three wavefronts per SIMD.
-// kCert: the counts certificate (rules 2, 3); kNet: the network (rules 0, 1, 3).
+// kCert: the certificate, from block counts and 3 x 3 distances (rules 2, 3); kNet: the network
+// (rules 0, 1, 3).
 template <bool kCert, bool kNet>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_learned_front(
     MlpDevice d, const GridScalars* __restrict__ gs, const int32_t* __restrict__ cell_start,
