@@ -88,8 +88,6 @@ hipError_t launch_bounds(const float* x, const float* y, int n, const float* qx,
                          BoundsPartial* partial, hipStream_t s);
 hipError_t launch_finalize(const BoundsPartial* partial, int nparts, int64_t n, double area_in, double cw_in,
                            double occ, GridScalars* out, hipStream_t s);
-hipError_t launch_cell_keys(const float* x, const float* y, int n, const GridScalars* gs, uint32_t* keys,
-                            uint32_t* vals, hipStream_t s);
 // Stable LSD radix sort of (key, value) pairs on the low `bits` bits of the keys.
 // tmp_* are ping-pong buffers of n entries; hist needs radix_hist_words(n) words and
 // scan_tmp radix_scan_tmp_words(n) words.  The result ends in (keys, vals).

@@ -3,7 +3,7 @@
 //   point -> stable LSD radix sort of (cell, index) -> CSR cell offsets and the
 //   data coordinates gathered into cell order.
 // The paper sorts with a library sort_by_key and recovers per-cell size and head
-// with segmented reduce / unique; here one stable counting sort per 8-bit digit
+// with segmented reduce / unique; here one stable counting sort per 8- or 10-bit digit
 // produces the same cell-ordered segments, and the CSR offsets (head of cell c =
 // cell_start[c], size = cell_start[c+1] - cell_start[c]) come from a binary
 // search over the sorted keys, which also covers empty cells.
@@ -85,15 +85,6 @@ __device__ inline uint32_t cell_key(float x, float y, float minx, float miny, fl
   row = row > nrow - 1 ? nrow - 1 : (row < 0 ? 0 : row);
   return (uint32_t)(row * ncol + col);
 }
-__global__ __launch_bounds__(256) void k_cell_keys(const float* __restrict__ x, const float* __restrict__ y, int n,
-                                                   const GridScalars* __restrict__ gs, uint32_t* __restrict__ keys,
-                                                   uint32_t* __restrict__ vals) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  keys[i] = cell_key(x[i], y[i], gs->minx, gs->miny, gs->inv_cw, gs->ncol, gs->nrow);
-  vals[i] = (uint32_t)i;
-}
-
 // ---- query binning -------------------------------------------------------------
 // The kNN kernels and the learned front take the queries in cell order, so that a
 // wavefront's queries scan neighbouring cells.  Each query's results depend on that
@@ -152,7 +143,7 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_hist(const uint32_t* __r
   for (int d = threadIdx.x; d < R; d += kSortThreads) hist[(size_t)d * nblocks + blockIdx.x] = h[d];
 }
 // The first pass's histogram (digit 0) fused with the cell keys: each point's key is computed
-// as in k_cell_keys and stored with its index, then counted.
+// (cell_key) and stored with its index, then counted.
 template <int BITS>
 __global__ __launch_bounds__(kSortThreads) void k_radix_hist_cells(const float* __restrict__ x,
                                                                    const float* __restrict__ y, int n,
@@ -403,13 +394,6 @@ hipError_t launch_bounds(const float* x, const float* y, int n, const float* qx,
 hipError_t launch_finalize(const BoundsPartial* partial, int nparts, int64_t n, double area_in, double cw_in,
                            double occ, GridScalars* out, hipStream_t s) {
   hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, s, partial, nparts, n, area_in, cw_in, occ, out);
-  return hipGetLastError();
-}
-
-hipError_t launch_cell_keys(const float* x, const float* y, int n, const GridScalars* gs, uint32_t* keys,
-                            uint32_t* vals, hipStream_t s) {
-  if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_cell_keys, dim3(div_up(n, 256)), dim3(256), 0, s, x, y, n, gs, keys, vals);
   return hipGetLastError();
 }
 
