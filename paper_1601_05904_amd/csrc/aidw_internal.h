@@ -141,11 +141,14 @@ hipError_t launch_knn_brute(const float* x, const float* y, int n, const float* 
 hipError_t launch_knn_paper(const GridScalars* gs, const int32_t* cell_start, const float* sx, const float* sy,
                             const int32_t* sidx, const float* qx, const float* qy, const uint32_t* qperm, int m, int k,
                             float* r_obs, float* d1sq, int32_t* nn_idx, hipStream_t s);
+struct AlphaParams;
 // The same with `lanes` (2, 4 or 8) lanes per query (for small or sparse query sets); identical results.
+// With ap and alpha_f non-null, alpha_f[q] also receives Eq. 4-6 of each query's r_obs.
 hipError_t launch_knn_lanes(const GridScalars* gs, const int32_t* cell_start, const float* sx, const float* sy,
                             const int32_t* sidx, const float* qx, const float* qy, const uint32_t* qperm,
                             const uint32_t* active, int m, int k, double slack_cells, float* r_obs, float* d1sq,
-                            int32_t* nn_idx, int lanes, hipStream_t s);
+                            int32_t* nn_idx, int lanes, hipStream_t s, const AlphaParams* ap = nullptr,
+                            float* alpha_f = nullptr);
 // Four lanes per query.
 hipError_t launch_knn4(const GridScalars* gs, const int32_t* cell_start, const float* sx, const float* sy,
                        const int32_t* sidx, const float* qx, const float* qy, const uint32_t* qperm,
@@ -228,8 +231,6 @@ hipError_t launch_mlp_gradients(const MlpDevice& d, const float* feat, const flo
 hipError_t launch_adam(const MlpDevice& d, const float* grad, float lr, float b1, float b2, float eps, float bc1,
                        float bc2, hipStream_t s);
 hipError_t launch_accumulate_loss(const float* grad, float* epoch_loss, int epoch, float scale, hipStream_t s);
-hipError_t launch_alpha_fallback(const uint32_t* perm, const uint32_t* count, int m, const float* r_obs,
-                                 const AlphaParams& ap, float* alpha_f, hipStream_t s);
 // Pair-kernel class keys from a given alpha (alpha == p in 1..8 -> p, else 0) and the identity permutation;
 // the coincident-query list as launch_alpha_class.
 hipError_t launch_class_keys(const float* alpha_f, int m, uint32_t* keys, uint32_t* vals, const float* d1sq,

@@ -975,9 +975,8 @@ aidw_status aidw_run_learned(const float* x, const float* y, const float* z, int
     STEP(compact_flags(flag, order, mm, stmp, list, count, stream), "fallback compaction");
     // the fallback queries are few and hard (cluster edges): eight lanes per query measured best
     STEP(launch_knn_lanes(g->dev, g->cell_start, g->sx, g->sy, g->sidx, qx, qy, list, count, mm, p->k,
-                          slack_cells(g->host), r_obs, d1sq, nullptr, 8, stream),
-         "kNN kernel");
-    STEP(launch_alpha_fallback(list, count, mm, r_obs, ap, alpha_f, stream), "alpha kernel");
+                          slack_cells(g->host), r_obs, d1sq, nullptr, 8, stream, &ap, alpha_f),
+         "kNN kernel (with Eq. 4-6)");
 #undef STEP
     int q = 0, split = 0;
     if (st == AIDW_OK)

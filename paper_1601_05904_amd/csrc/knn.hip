@@ -27,6 +27,7 @@
 
 #include "aidw_internal.h"
 #include "knn_core.h"
+#include "pair_core.h"
 
 namespace aidw {
 
@@ -70,7 +71,8 @@ __global__ __launch_bounds__(256) void k_knn_lanes(const GridScalars* __restrict
                                               const float* __restrict__ qy, const uint32_t* __restrict__ qperm,
                                               const uint32_t* __restrict__ active, int m, int k, double slack_cells,
                                               float* __restrict__ r_obs, float* __restrict__ d1sq,
-                                              int32_t* __restrict__ nn_idx) {
+                                              int32_t* __restrict__ nn_idx, AlphaParams ap,
+                                              float* __restrict__ alpha_f) {
   const int gt = blockIdx.x * blockDim.x + threadIdx.x;
   const int t = gt / LANES, sub = gt % LANES;
   if (t >= m || (active && (uint32_t)t >= *active)) return;  // the lanes of a query leave together
@@ -84,6 +86,9 @@ __global__ __launch_bounds__(256) void k_knn_lanes(const GridScalars* __restrict
   if (sub == 0) {
     r_obs[q] = ro;
     if (d1sq) d1sq[q] = d1;
+    // Eq. 4-6 from the stored r_obs, as the alpha kernel of the plain path computes them
+    if (alpha_f)
+      alpha_f[q] = (float)pair::level_alpha(pair::fuzzy_mu((double)ro / ap.r_exp, ap.r_min, ap.r_max), ap.levels);
   }
 }
 
@@ -184,15 +189,17 @@ hipError_t launch_knn_paper(const GridScalars* gs, const int32_t* cell_start, co
 hipError_t launch_knn_lanes(const GridScalars* gs, const int32_t* cell_start, const float* sx, const float* sy,
                             const int32_t* sidx, const float* qx, const float* qy, const uint32_t* qperm,
                             const uint32_t* active, int m, int k, double slack_cells, float* r_obs, float* d1sq,
-                            int32_t* nn_idx, int lanes, hipStream_t s) {
+                            int32_t* nn_idx, int lanes, hipStream_t s, const AlphaParams* ap, float* alpha_f) {
   if (m <= 0) return hipSuccess;
+  const AlphaParams apv = ap ? *ap : AlphaParams{};
+  if (!ap) alpha_f = nullptr;
   if (lanes != 2 && lanes != 4 && lanes != 8) return hipErrorInvalidValue;
   // one workgroup per 256 / lanes queries; with an active count the workgroups beyond it exit at
   // once (a grid-stride loop instead keeps more registers live across the search: measured slower)
   const dim3 grid((int)(((int64_t)m * lanes + 255) / 256)), block(256);
 #define AIDW_KNNL(K, LN)                                                                                         \
   hipLaunchKernelGGL((k_knn_lanes<K, LN>), grid, block, 0, s, gs, cell_start, sx, sy, sidx, qx, qy, qperm, active, \
-                     m, k, slack_cells, r_obs, d1sq, nn_idx)
+                     m, k, slack_cells, r_obs, d1sq, nn_idx, apv, alpha_f)
 #define AIDW_KNNL_2(K) AIDW_KNNL(K, 2)
 #define AIDW_KNNL_4(K) AIDW_KNNL(K, 4)
 #define AIDW_KNNL_8(K) AIDW_KNNL(K, 8)

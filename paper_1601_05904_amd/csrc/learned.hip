@@ -469,19 +469,6 @@ __device__ inline bool certified_by_distances(double v_sum, int v_cnt, float v_m
   return sum - (double)(3 * v_cnt + k) * 5e-7 * d_1 > sum_min;
 }
 
-// Eq. 4-6 for the fallback queries (the first *count entries of perm) from their exact r_obs.
-__global__ __launch_bounds__(256) void k_alpha_fallback(const uint32_t* __restrict__ perm,
-                                                        const uint32_t* __restrict__ count,
-                                                        const float* __restrict__ r_obs, AlphaParams ap,
-                                                        float* __restrict__ alpha_f) {
-  const uint32_t cnt = *count;
-  for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < cnt; t += gridDim.x * blockDim.x) {
-    const uint32_t q = perm[t];
-    const double R = (double)r_obs[q] / ap.r_exp;
-    alpha_f[q] = (float)level_alpha_l(fuzzy_mu_l(R, ap.r_min, ap.r_max), ap.levels);
-  }
-}
-
 // ---- inference on the matrix cores -----------------------------------------------------
 //
 // v_mfma_f32_16x16x32_bf16 computes D (16 x 16) = A (16 x 32) B (32 x 16) + C with, for
@@ -937,15 +924,6 @@ hipError_t launch_adam(const MlpDevice& d, const float* grad, float lr, float b1
 
 hipError_t launch_accumulate_loss(const float* grad, float* epoch_loss, int epoch, float scale, hipStream_t s) {
   hipLaunchKernelGGL(k_accumulate_loss, dim3(1), dim3(64), 0, s, grad, epoch_loss, epoch, scale);
-  return hipGetLastError();
-}
-
-hipError_t launch_alpha_fallback(const uint32_t* perm, const uint32_t* count, int m, const float* r_obs,
-                                 const AlphaParams& ap, float* alpha_f, hipStream_t s) {
-  if (m <= 0) return hipSuccess;
-  const int blocks = (m + 255) / 256;
-  hipLaunchKernelGGL(k_alpha_fallback, dim3(blocks < 1024 ? blocks : 1024), dim3(256), 0, s, perm, count, r_obs, ap,
-                     alpha_f);
   return hipGetLastError();
 }
 
