@@ -182,6 +182,21 @@ aidw_status aidw_knn_paper(const aidw_grid* g, const float* qx, const float* qy,
                            float* d1sq, int32_t* nn_idx, hipStream_t stream);
 
 /*
+ * The nearest-neighbour statistic of Eq. 4 for m queries on grid g:
+ *   R[j] = min(r_obs[j] / r_exp, clip),
+ * with r_obs[j] the mean distance of query j to its k nearest data points (Eq. 3,
+ * computed exactly as aidw_knn does, stored as float32) and r_exp = 1 / (2 sqrt(n / A))
+ * the grid's expected distance (Eq. 2).  The quotient is formed in float64 and
+ * rounded to float32.  clip > 0 caps R (the learned-R form trains on min(R, 3): alpha is
+ * saturated well before that); clip <= 0 or +inf leaves R uncapped.
+ * Arguments: qx, qy [m] and R [m] are device pointers (caller-owned).
+ * Errors: AIDW_EINVAL (null grid / pointers, m < 0, k outside [1, min(n, AIDW_KMAX)],
+ * clip NaN), AIDW_ECAPACITY (m > INT32_MAX), AIDW_ENOMEM, AIDW_EDEVICE.  m = 0 is AIDW_OK.
+ */
+aidw_status aidw_nn_statistic(const aidw_grid* g, const float* qx, const float* qy, int64_t m, int32_t k, double clip,
+                              float* R, hipStream_t stream);
+
+/*
  * Stage 2, adaptive power and weighted interpolation (Eq. 1, 2, 4, 5, 6;
  * Section 3.3, 4.2).
  * For each query j: R = r_obs[j] / r_exp with r_exp = 1 / (2 sqrt(n / A)),
@@ -294,7 +309,14 @@ typedef enum {
                                     1, 3 x 3 and 5 x 5 cell blocks around the query and the exact distances of
                                     the 3 x 3 block's points.  Every query gets the alpha of the exact path; the
                                     network is not evaluated (r_hat_out receives NaN); delta is checked, unused */
-  AIDW_FALLBACK_CERTIFIED_THEN_ALPHA_EXACT = 3 /* skip when certified as in 2, else apply rule 1 */
+  AIDW_FALLBACK_CERTIFIED_THEN_ALPHA_EXACT = 3, /* skip when certified as in 2, else apply rule 1 */
+  AIDW_FALLBACK_NETWORK_GATED_CERTIFICATE = 4   /* skip only when certified as in 2 (every alpha is the exact
+                                                   path's); the network decides which queries the 3 x 3 distance
+                                                   certificate is tried on: those the block counts do not already
+                                                   certify and whose r_hat >= (R where mu = 0.9) - delta; the others
+                                                   go to the exact kNN without that scan.  The network runs only on
+                                                   tiles of 16 queries holding such a query (r_hat_out: NaN
+                                                   elsewhere) */
 } aidw_fallback_rule;
 
 /* New network with weights drawn from `seed` (uniform in +-sqrt(6 / fan_in),
@@ -351,6 +373,20 @@ aidw_status aidw_run_learned(const float* x, const float* y, const float* z, int
                              const float* qy, int64_t m, const aidw_params* p, const aidw_mlp* mlp, int32_t rule,
                              double delta, float* qz, float* alpha_out, float* r_hat_out, int64_t* fallback_count,
                              hipStream_t stream);
+
+/* The learned form's decision for every query, without the kNN search or the
+ * interpolation (for inspecting a rule and a network): the grid build and the fused
+ * front of aidw_run_learned.  route_out [m] (device, uint8) receives the query's route:
+ *   0  exact kNN
+ *   1  exact kNN after the 3 x 3 distance certificate was tried and failed
+ *   2  skipped: alpha = alpha_5 certified by the block counts
+ *   3  skipped: alpha = alpha_5 certified by the 3 x 3 distances
+ *   4  skipped: alpha set from the network's prediction (rules 0, 1, 3)
+ * r_hat_out [m] (may be NULL) as for aidw_run_learned.  Arguments and errors as
+ * aidw_run_learned; synchronises the stream once at the end. */
+aidw_status aidw_learned_routes(const float* x, const float* y, int64_t n, const float* qx, const float* qy,
+                                int64_t m, const aidw_params* p, const aidw_mlp* mlp, int32_t rule, double delta,
+                                uint8_t* route_out, float* r_hat_out, hipStream_t stream);
 
 /* ---------------------------------------------------------------------------
  * Batched form.  Many independent interpolation problems ("jobs") of uneven

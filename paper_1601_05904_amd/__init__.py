@@ -138,6 +138,7 @@ def load(build_if_missing: bool = True):
     L.aidw_grid_destroy.restype = None
     L.aidw_knn.argtypes = [_VP, _VP, _VP, i64, i32, _VP, _VP, _VP, _VP]
     L.aidw_knn_paper.argtypes = [_VP, _VP, _VP, i64, i32, _VP, _VP, _VP, _VP]
+    L.aidw_nn_statistic.argtypes = [_VP, _VP, _VP, i64, i32, ctypes.c_double, _VP, _VP]
     L.aidw_knn_bruteforce.argtypes = [_VP, _VP, i64, _VP, _VP, i64, i32, _VP, _VP, _VP, _VP]
     L.aidw_interpolate_naive.argtypes = [_VP, _VP, _VP, i64, _VP, _VP, i64, _VP, _VP, P(_Params), _VP, _VP, _VP,
                                          _VP]
@@ -168,6 +169,8 @@ def load(build_if_missing: bool = True):
     L.aidw_mlp_train.argtypes = [_VP, _VP, _VP, i64, i32, i32, ctypes.c_float, u64, _VP, _VP]
     L.aidw_run_learned.argtypes = [_VP, _VP, _VP, i64, _VP, _VP, i64, P(_Params), _VP, i32, ctypes.c_double, _VP, _VP,
                                    _VP, P(i64), _VP]
+    L.aidw_learned_routes.argtypes = [_VP, _VP, i64, _VP, _VP, i64, P(_Params), _VP, i32, ctypes.c_double, _VP, _VP,
+                                      _VP]
     L.aidw_batch_config_default.argtypes = [P(_BatchConfig)]
     L.aidw_batch_config_default.restype = None
     L.aidw_batch_create.argtypes = [P(_Job), i32, P(_BatchConfig), P(_VP)]
@@ -180,11 +183,12 @@ def load(build_if_missing: bool = True):
     L.aidw_batch_destroy.restype = None
     L.aidw_run_batch.argtypes = [P(_Job), i32, P(_BatchConfig), P(i32), _VP]
     L.aidw_batch_tune.argtypes = [P(_Job), i32, P(_BatchConfig), i32, i32, P(ctypes.c_float), _VP]
-    for name in ("aidw_build_grid", "aidw_grid_describe", "aidw_grid_info", "aidw_grid_arrays", "aidw_grid_copy_arrays", "aidw_knn",
+    for name in ("aidw_build_grid", "aidw_nn_statistic", "aidw_grid_describe", "aidw_grid_info", "aidw_grid_arrays", "aidw_grid_copy_arrays", "aidw_knn",
                  "aidw_interpolate", "aidw_run", "aidw_knn_paper", "aidw_knn_bruteforce", "aidw_interpolate_naive",
                  "aidw_set_timing", "aidw_last_timing", "aidw_set_interp_config",
                  "aidw_mlp_create", "aidw_mlp_set_params", "aidw_mlp_get_params", "aidw_mlp_save", "aidw_mlp_load",
                  "aidw_features", "aidw_mlp_forward", "aidw_mlp_gradients", "aidw_mlp_train", "aidw_run_learned",
+                 "aidw_learned_routes",
                  "aidw_batch_create", "aidw_batch_run", "aidw_batch_job_status", "aidw_batch_describe",
                  "aidw_batch_set_timing", "aidw_batch_last_timing", "aidw_run_batch", "aidw_batch_tune",
                  "aidw_release_cached_memory"):
@@ -294,6 +298,16 @@ def knn(grid: Grid, qx, qy, k: int, want_d1sq=True, want_idx=False, stream=None,
     _check(fn(grid.handle, _dev(qx, "qx"), _dev(qy, "qy"), m, int(k), r.data_ptr(),
               None if d1 is None else d1.data_ptr(), None if ix is None else ix.data_ptr(), _stream(stream)))
     return r, d1, ix
+
+
+def nn_statistic(grid: Grid, qx, qy, k: int, clip: float = 0.0, stream=None):
+    """aidw_nn_statistic: R = min(r_obs / r_exp, clip) of every query (Eq. 3, 4) -> R [m]."""
+    import torch
+    m = qx.numel()
+    R = torch.empty(m, dtype=torch.float32, device=qx.device)
+    _check(load().aidw_nn_statistic(grid.handle, _dev(qx, "qx"), _dev(qy, "qy"), m, int(k), float(clip), R.data_ptr(),
+                                    _stream(stream)))
+    return R
 
 
 def interpolate(x, y, z, qx, qy, r_obs, d1sq, params: Params | None = None, grid: Grid | None = None,

@@ -2,7 +2,9 @@
 
 Every source in ``csrc/`` is compiled for gfx950 with hipcc (one process per
 file, in parallel) and linked into one shared library that exports the C ABI
-of ``include/aidw.h``.  Flags:
+of ``include/aidw.h``; ``ubench/issue_rate.hip`` (the VALU / transcendental
+issue-rate microbenchmark behind the pair kernel's roofline) becomes
+``libaidw_ubench.so``.  Flags:
   -O3 -std=c++17 -fPIC
   -ffp-contract=off   no implicit FMA contraction: the kNN squared distances
                       must be formed exactly as written; the pair kernel uses
@@ -21,6 +23,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libaidw.so")
+UBENCH_SRC = os.path.join(HERE, "ubench", "issue_rate.hip")
+UBENCH_LIB = os.path.join(HERE, "libaidw_ubench.so")
 OBJ = os.path.join(ROOT, "_build", "obj")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
@@ -59,7 +63,18 @@ def build(verbose: bool = False) -> str:
     if r.returncode != 0:
         raise RuntimeError("link failed:\n" + r.stdout + r.stderr)
     os.replace(tmp, LIB)
+    build_ubench()
     return LIB
+
+
+def build_ubench() -> str:
+    """The issue-rate microbenchmark (bench.py --issue-rates) as its own small library."""
+    tmp = UBENCH_LIB + ".tmp%d" % os.getpid()
+    r = subprocess.run([HIPCC] + FLAGS + ["-shared", "-o", tmp, UBENCH_SRC], capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError("hipcc failed for %s:\n%s" % (UBENCH_SRC, r.stdout + r.stderr))
+    os.replace(tmp, UBENCH_LIB)
+    return UBENCH_LIB
 
 
 if __name__ == "__main__":

@@ -19,6 +19,8 @@ struct GridScalars {
   int32_t ncol, nrow;
   int32_t status; // 0 ok, else an aidw_status value
   int64_t ncells;
+  int32_t band_shift;  // banded build: a band is 2^band_shift consecutive cells
+  int32_t nbands;      // banded build: bands covering the ncells cells
 };
 
 // Per-block partial of the bounds reduction.
@@ -55,7 +57,10 @@ __host__ __device__ inline double slack_cells(int32_t ncol, int32_t nrow) {
 }
 inline double slack_cells(const GridScalars& g) { return slack_cells(g.ncol, g.nrow); }
 
-// ---- host helpers shared by the ABI sources (api.hip, batch.hip) ----
+// ---- host helpers shared by the ABI sources (api.hip, batch.hip, noalloc.hip) ----
+
+// Clears the message of aidw_last_error_detail on the calling thread.
+void clear_error_detail();
 
 // Records a message for aidw_last_error_detail on the calling thread and returns st.
 aidw_status fail(aidw_status st, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
@@ -82,6 +87,35 @@ constexpr int kSortTile = kSortThreads * kSortItems; // elements per block
 constexpr int kRadixBits = 8;                        // digit width of the sort passes
 constexpr int kRadixBitsWide = 10;                   // used where it saves a pass
 constexpr int kRadixMax = 1 << kRadixBitsWide;
+
+// ---- banded grid build (grid_band.hip) ----
+// The data points and the queries are sorted by cell in two steps: a stable counting sort by
+// band (2^band_shift consecutive cells, at most kMaxBands bands per point set), then, per
+// band, a stable counting sort by cell inside the band.  Limits: at most kMaxBands bands of at
+// most 2^kMaxBandShift cells, i.e. kBandMaxCells cells.
+constexpr int kMaxBands = 512;
+constexpr int kMaxBandShift = 13;
+constexpr int64_t kBandMaxCells = (int64_t)kMaxBands << kMaxBandShift;
+struct BandScratch {
+  BoundsPartial* partial;  // [kBoundsBlocks]
+  uint32_t* hist;          // [band_hist_words(total)]: per digit and block counts, then prefixes
+  uint32_t* totals;        // [2 kMaxBands] per-digit totals
+  uint32_t* dstart;        // [2 kMaxBands + 1]
+  uint32_t* bidx;          // [total] band-sorted indices
+  float* bx;               // [total] band-sorted coordinates
+  float* by;
+};
+size_t band_hist_words(int64_t total);
+// Largest band shift a grid of at most cap cells can need.
+int band_shift_for(int64_t cap);
+// Bounds over data and queries, the grid scalars (Eq. 2, Section 4.1.1; the cell side widened if
+// the grid would exceed cap cells), and the stable sort of the data points into cell order:
+// cell_start [cap + 1], sx, sy, sidx [n].  With bin_q, the queries too: qorder [m] lists them in
+// cell order, qsx, qsy [m] (may be null) their coordinates in that order.  No host synchronisation.
+hipError_t build_grid_banded(const float* x, const float* y, int64_t n, const float* qx, const float* qy, int64_t m,
+                             bool bin_q, double area_in, double cw_in, double occ, int64_t cap, GridScalars* gs,
+                             int32_t* cell_start, float* sx, float* sy, int32_t* sidx, uint32_t* qorder, float* qsx,
+                             float* qsy, const BandScratch& b, hipStream_t s);
 
 // Host-side launchers (all asynchronous on `s`; return the first HIP error).
 hipError_t launch_bounds(const float* x, const float* y, int n, const float* qx, const float* qy, int m,
@@ -130,10 +164,12 @@ hipError_t launch_cell_start_gather(const uint32_t* keys, const uint32_t* vals, 
 
 // qperm (may be null) lists the queries in processing order; active (may be null) is a device
 // count: only the first *active entries of qperm are processed.
+// The kernels derive the binning slack (slack_cells) from the device scalars gs, and do no work
+// when gs->status reports a failed grid build.
 hipError_t launch_knn(const GridScalars* gs, const int32_t* cell_start, const float* sx, const float* sy,
                       const int32_t* sidx, const float* qx, const float* qy, const uint32_t* qperm,
-                      const uint32_t* active, int m, int k, double slack_cells, float* r_obs, float* d1sq,
-                      int32_t* nn_idx, hipStream_t s);
+                      const uint32_t* active, int m, int k, float* r_obs, float* d1sq, int32_t* nn_idx,
+                      hipStream_t s);
 // Brute-force kNN over all n points per query (the method the grid search replaces); exact.
 hipError_t launch_knn_brute(const float* x, const float* y, int n, const float* qx, const float* qy, int m, int k,
                             float* r_obs, float* d1sq, int32_t* nn_idx, hipStream_t s);
@@ -146,20 +182,21 @@ struct AlphaParams;
 // With ap and alpha_f non-null, alpha_f[q] also receives Eq. 4-6 of each query's r_obs.
 hipError_t launch_knn_lanes(const GridScalars* gs, const int32_t* cell_start, const float* sx, const float* sy,
                             const int32_t* sidx, const float* qx, const float* qy, const uint32_t* qperm,
-                            const uint32_t* active, int m, int k, double slack_cells, float* r_obs, float* d1sq,
-                            int32_t* nn_idx, int lanes, hipStream_t s, const AlphaParams* ap = nullptr,
-                            float* alpha_f = nullptr);
+                            const uint32_t* active, int m, int k, float* r_obs, float* d1sq, int32_t* nn_idx,
+                            int lanes, hipStream_t s, const AlphaParams* ap = nullptr, float* alpha_f = nullptr);
 // Four lanes per query.
 hipError_t launch_knn4(const GridScalars* gs, const int32_t* cell_start, const float* sx, const float* sy,
                        const int32_t* sidx, const float* qx, const float* qy, const uint32_t* qperm,
-                       const uint32_t* active, int m, int k, double slack_cells, float* r_obs, float* d1sq,
-                       int32_t* nn_idx, hipStream_t s);
+                       const uint32_t* active, int m, int k, float* r_obs, float* d1sq, int32_t* nn_idx,
+                       hipStream_t s);
 
 struct AlphaParams {
   double r_exp;
   double r_min, r_max;
   double levels[5];
+  const double* r_exp_dev = nullptr;  // non-null: r_exp is read here (a grid's device scalars)
 };
+__host__ __device__ inline double alpha_r_exp(const AlphaParams& ap) { return ap.r_exp_dev ? *ap.r_exp_dev : ap.r_exp; }
 
 // Eq. 4-6 per query -> alpha_f [m] (and alpha_out if non-null); class keys [m] (p in 1..8 when
 // alpha == p exactly, else 0) and the identity permutation vals [m], ready for a stable sort by key;
@@ -167,12 +204,16 @@ struct AlphaParams {
 hipError_t launch_alpha_class(const float* r_obs, int m, const AlphaParams& ap, float* alpha_f, float* alpha_out,
                               uint32_t* keys, uint32_t* vals, const float* d1sq, uint32_t* count, uint32_t* list,
                               hipStream_t s);
+// Eq. 4 per query: R[j] = min(r_obs[j] / r_exp, clip) in float64, stored as float32 (clip <= 0: none).
+hipError_t launch_nn_statistic(const float* r_obs, int m, double r_exp, double clip, float* R, hipStream_t s);
 // Pair kernels over the queries in class order (perm, sorted keys skeys); fast_mask bit p
 // requests the integer-power kernel for class p (the general kernel covers every other block).
 // x, y, z are the padded copies made by launch_pad_copy.
+// gs (may be null): a grid whose failed status makes the launch do nothing.
 hipError_t launch_interp(const float* x, const float* y, const float* z, int n, const float* qx, const float* qy,
                          const float* alpha_f, const float* d1sq, const uint32_t* perm, const uint32_t* skeys, int m,
-                         uint32_t fast_mask, int q, int split, float* qz, double2* partial, hipStream_t s);
+                         uint32_t fast_mask, int q, int split, float* qz, double2* partial, const GridScalars* gs,
+                         hipStream_t s);
 // The untiled pair kernel (per-lane global loads, general alpha form, one data range).
 hipError_t launch_interp_naive(const float* x, const float* y, const float* z, int n, const float* qx, const float* qy,
                                const float* alpha_f, const float* d1sq, int m, float* qz, hipStream_t s);
@@ -211,19 +252,24 @@ struct MlpDevice {
 };
 
 // perm (may be null): lane t handles query perm[t] and writes its outputs at position t.
+// n = the grid's data points (the counts are scaled by nCells / n).
 hipError_t launch_features(const GridScalars* gs, const int32_t* cell_start, const float* sx, const float* sy,
-                           const float* qx, const float* qy, const uint32_t* perm, int m, double inv_occ,
-                           double slack_cells, float* feat, float* d1sq, hipStream_t s);
+                           const float* qx, const float* qy, const uint32_t* perm, int m, int64_t n, float* feat,
+                           float* d1sq, hipStream_t s);
 hipError_t launch_mlp_repack(const MlpDevice& d, hipStream_t s);
 hipError_t launch_mlp_forward(const MlpDevice& d, const float* feat, int m, float* out, hipStream_t s);
 // Fused inference front of the learned run, per position t of the order perm (may be null):
 // features, the network (MFMA) and the fallback decision in one kernel; flag[t] = 1 marks a
-// query that takes the exact kNN.
+// query that takes the exact kNN.  route[q] (may be null) receives the query's route: 0 exact
+// kNN, 1 exact kNN after a failed 3 x 3 certificate, 2 certified by the block counts, 3
+// certified by the 3 x 3 distances, 4 alpha from the network.
+// The certificate's threshold on the sum of the k nearest distances is cert_factor * r_exp (r_exp
+// from gs).
 hipError_t launch_learned_front(const MlpDevice& d, const GridScalars* gs, const int32_t* cell_start, const float* sx,
                                 const float* sy, const float* qx, const float* qy, const uint32_t* perm, int m,
-                                double inv_occ, double slack_cells, const AlphaParams& ap, int rule, double delta,
-                                double r_sat_lo, double r_sat_hi, int k, double cert_sum_min, uint32_t* flag,
-                                float* alpha_f, float* d1sq, float* r_hat_out, hipStream_t s);
+                                int64_t n, const AlphaParams& ap, int rule, double delta, double r_sat_lo,
+                                double r_sat_hi, int k, double cert_factor, uint32_t* flag, float* alpha_f,
+                                float* d1sq, float* r_hat_out, uint8_t* route, hipStream_t s);
 size_t mlp_batch_scratch_floats(int B);
 // grad [AIDW_MLP_PARAMS + 1]: the batch gradient, then the batch's mean squared error.
 hipError_t launch_mlp_gradients(const MlpDevice& d, const float* feat, const float* target, const uint32_t* sel, int B,
@@ -239,4 +285,20 @@ hipError_t launch_class_keys(const float* alpha_f, int m, uint32_t* keys, uint32
 hipError_t launch_shuffle_keys(uint64_t seed, int epoch, int count, uint32_t* keys, uint32_t* vals, hipStream_t s);
 
 }  // namespace aidw
+
+// The grid handle of the C ABI (opaque to callers).
+struct aidw_grid {
+  int64_t n = 0;
+  aidw::GridScalars host{};  // host copy of the device scalars (valid when host_valid)
+  bool host_valid = false;
+  int64_t cells_alloc = 0;         // cells cell_start is sized for (the budget of a banded build)
+  aidw::GridScalars* dev = nullptr;  // device scalars
+  int32_t* cell_start = nullptr;   // [ncells + 1]
+  float* sx = nullptr;             // [n]
+  float* sy = nullptr;             // [n]
+  int32_t* sidx = nullptr;         // [n]
+  hipStream_t async_stream = nullptr;  // non-null: arrays are stream-ordered allocations on this stream
+  bool async = false;
+};
+
 

@@ -14,17 +14,6 @@
 
 using namespace aidw;
 
-struct aidw_grid {
-  int64_t n = 0;
-  GridScalars host{};            // host copy of the device scalars
-  GridScalars* dev = nullptr;    // device scalars
-  int32_t* cell_start = nullptr; // [ncells + 1]
-  float* sx = nullptr;           // [n]
-  float* sy = nullptr;           // [n]
-  int32_t* sidx = nullptr;       // [n]
-  hipStream_t async_stream = nullptr;  // non-null: arrays are stream-ordered allocations on this stream
-  bool async = false;
-};
 
 namespace {
 
@@ -56,6 +45,8 @@ aidw_status fail(aidw_status st, const char* fmt, ...) {
   g_detail = buf;
   return st;
 }
+
+void clear_error_detail() { g_detail.clear(); }
 
 aidw_status hip_fail(hipError_t e, const char* what) {
   if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation)
@@ -224,11 +215,61 @@ hipError_t scalar_staging(GridScalars** slot, hipEvent_t* ev) {
   return hipSuccess;
 }
 
+// Cell budget of a grid in occupancy mode: twice the cells the default side gives on a square
+// box plus the rim of a box of any aspect ratio up to about 4:1 (the batched form uses the same
+// budget).  Grids within it are built without a host round trip (banded build).
+int64_t occupancy_budget(int64_t n, double occ) {
+  const double base = (double)n / occ;
+  return (int64_t)(2.0 * ceil(base) + 4.0 * ceil(sqrt(base)) + 16.0);
+}
+
+// Queries binned by the grid build (the banded build bins the queries it bounds).
+struct QueryBins {
+  uint32_t* order = nullptr;  // [m] query indices in cell order
+  float* qx = nullptr;        // [m] their coordinates in that order
+  float* qy = nullptr;
+  bool valid = false;
+};
+
+aidw_status status_error(const GridScalars& h) {
+  if (h.status == AIDW_ENONFINITE) return fail(AIDW_ENONFINITE, "a coordinate is NaN or infinite");
+  if (h.status == AIDW_EDEGENERATE)
+    return fail(AIDW_EDEGENERATE, "the study area resolves to %g (collinear or coincident points); pass params.area",
+                h.area);
+  if (h.status == AIDW_ECAPACITY)
+    return fail(AIDW_ECAPACITY, "grid would exceed %lld cells; increase cell_width or occupancy",
+                (long long)AIDW_MAX_CELLS);
+  if (h.status != AIDW_OK) return fail(AIDW_EDEVICE, "grid finalize status %d", h.status);
+  return AIDW_OK;
+}
+
+// Waits for the grid build queued on s and fills g->host from the device scalars; returns the
+// build's status.
+aidw_status sync_grid_host(aidw_grid* g, hipStream_t s) {
+  GridScalars* pinned = nullptr;
+  hipEvent_t ready = nullptr;
+  hipError_t e;
+  if ((e = scalar_staging(&pinned, &ready)) != hipSuccess) return hip_fail(e, "scalar staging");
+  if ((e = hipMemcpyAsync(pinned, g->dev, sizeof(GridScalars), hipMemcpyDeviceToHost, s)) != hipSuccess ||
+      (e = hipEventRecord(ready, s)) != hipSuccess || (e = hipEventSynchronize(ready)) != hipSuccess)
+    return hip_fail(e, "reading grid scalars");
+  g->host = *pinned;
+  g->host_valid = true;
+  return status_error(g->host);
+}
+
+// The grid of the data points.  In occupancy mode with a cell budget within the banded build's
+// limit, the whole build (and, with bins, the binning of the queries) is queued without waiting
+// for the host: g->host is filled only with wait_host (the status is then checked too),
+// otherwise the caller reads the status later (sync_grid_host).  With an explicit cell side
+// (or a budget beyond the banded limit) the host waits once for the scalars, then sizes the
+// grid exactly and sorts by a stable LSD radix sort; bins are then left invalid.
 // outer (may be null): the caller's temporaries, released when the caller's call ends, so the
 // release's event records are issued after the rest of the caller's work, not between the grid
 // build and the next stage.
 aidw_status build_grid_impl(const float* x, const float* y, int64_t n, const float* qx, const float* qy, int64_t m,
-                            const aidw_params* p, hipStream_t s, bool async, aidw_grid** out, Temps* outer = nullptr) {
+                            const aidw_params* p, hipStream_t s, bool async, aidw_grid** out, Temps* outer = nullptr,
+                            QueryBins* bins = nullptr, bool wait_host = true) {
   aidw_grid* g = new aidw_grid();
   g->n = n;
   g->async = async;
@@ -240,6 +281,42 @@ aidw_status build_grid_impl(const float* x, const float* y, int64_t n, const flo
   hipError_t e = async ? dmalloc_async((void**)&g->dev, sizeof(GridScalars), s)
                        : dmalloc((void**)&g->dev, sizeof(GridScalars));
   if (e != hipSuccess) return cleanup(hip_fail(e, "allocating grid scalars"));
+  Temps local(s);
+  Temps& t = outer ? *outer : local;
+  auto alloc = [&](void** ptr, size_t bytes) { return async ? dmalloc_async(ptr, bytes, s) : dmalloc(ptr, bytes); };
+  const bool occ_mode = !(p->cell_width > 0);
+  const int64_t budget = occ_mode ? occupancy_budget(n, p->occupancy) : 0;
+  if (occ_mode && budget <= kBandMaxCells) {
+    const bool bin_q = bins != nullptr && m > 0;
+    const int64_t total = n + (bin_q ? m : 0);
+    BandScratch b{};
+    if ((e = t.get(&b.partial, kBoundsBlocks)) != hipSuccess || (e = t.get(&b.hist, band_hist_words(total))) != hipSuccess ||
+        (e = t.get(&b.totals, 2 * kMaxBands)) != hipSuccess || (e = t.get(&b.dstart, 2 * kMaxBands + 1)) != hipSuccess ||
+        (e = t.get(&b.bidx, total)) != hipSuccess || (e = t.get(&b.bx, total)) != hipSuccess ||
+        (e = t.get(&b.by, total)) != hipSuccess)
+      return cleanup(hip_fail(e, "allocating grid-build buffers"));
+    if (bin_q && ((e = t.get(&bins->order, m)) != hipSuccess || (e = t.get(&bins->qx, m)) != hipSuccess ||
+                  (e = t.get(&bins->qy, m)) != hipSuccess))
+      return cleanup(hip_fail(e, "allocating query-binning buffers"));
+    g->cells_alloc = budget;
+    if ((e = alloc((void**)&g->cell_start, sizeof(int32_t) * (budget + 1))) != hipSuccess ||
+        (e = alloc((void**)&g->sx, sizeof(float) * n)) != hipSuccess ||
+        (e = alloc((void**)&g->sy, sizeof(float) * n)) != hipSuccess ||
+        (e = alloc((void**)&g->sidx, sizeof(int32_t) * n)) != hipSuccess)
+      return cleanup(hip_fail(e, "allocating grid arrays"));
+    if ((e = build_grid_banded(x, y, n, qx, qy, m, bin_q, p->area, p->cell_width, p->occupancy, budget, g->dev,
+                               g->cell_start, g->sx, g->sy, g->sidx, bin_q ? bins->order : nullptr,
+                               bin_q ? bins->qx : nullptr, bin_q ? bins->qy : nullptr, b, s)) != hipSuccess)
+      return cleanup(hip_fail(e, "grid build"));
+    if (bins) bins->valid = bin_q;
+    g->host_valid = false;
+    if (wait_host) {
+      aidw_status st = sync_grid_host(g, s);
+      if (st != AIDW_OK) return cleanup(st);
+    }
+    *out = g;
+    return AIDW_OK;
+  }
   // The host needs the cell count (to size the CSR array and the sort's passes) and the
   // status.  The scalars are copied into pinned memory behind an event; the cell keys and
   // the sort's first 10-bit pass, which do not depend on them, are queued before the host
@@ -247,8 +324,6 @@ aidw_status build_grid_impl(const float* x, const float* y, int64_t n, const flo
   GridScalars* pinned = nullptr;
   hipEvent_t ready = nullptr;
   if ((e = scalar_staging(&pinned, &ready)) != hipSuccess) return cleanup(hip_fail(e, "scalar staging"));
-  Temps local(s);
-  Temps& t = outer ? *outer : local;
   BoundsPartial* part = nullptr;
   uint32_t *keys, *vals, *tk, *tv, *hist, *scan;
   if ((e = t.get(&part, kBoundsBlocks)) != hipSuccess || (e = t.get(&keys, n)) != hipSuccess ||
@@ -268,18 +343,12 @@ aidw_status build_grid_impl(const float* x, const float* y, int64_t n, const flo
   uint32_t *sk = tk, *sv = tv;  // the pairs sorted so far (in keys / vals or in the temporaries)
   if ((e = hipEventSynchronize(ready)) != hipSuccess) return cleanup(hip_fail(e, "synchronising grid scalars"));
   g->host = *pinned;
-  const GridScalars& h = g->host;
-  if (h.status == AIDW_ENONFINITE) return cleanup(fail(AIDW_ENONFINITE, "a coordinate is NaN or infinite"));
-  if (h.status == AIDW_EDEGENERATE)
-    return cleanup(fail(AIDW_EDEGENERATE, "the study area resolves to %g (collinear or coincident points); pass params.area",
-                        h.area));
-  if (h.status == AIDW_ECAPACITY)
-    return cleanup(fail(AIDW_ECAPACITY, "grid would exceed %lld cells; increase cell_width or occupancy",
-                        (long long)AIDW_MAX_CELLS));
-  if (h.status != AIDW_OK) return cleanup(fail(AIDW_EDEVICE, "grid finalize status %d", h.status));
+  g->host_valid = true;
+  aidw_status st = status_error(g->host);
+  if (st != AIDW_OK) return cleanup(st);
 
-  const int64_t ncells = h.ncells;
-  auto alloc = [&](void** ptr, size_t bytes) { return async ? dmalloc_async(ptr, bytes, s) : dmalloc(ptr, bytes); };
+  const int64_t ncells = g->host.ncells;
+  g->cells_alloc = ncells;
   if ((e = alloc((void**)&g->cell_start, sizeof(int32_t) * (ncells + 1))) != hipSuccess ||
       (e = alloc((void**)&g->sx, sizeof(float) * n)) != hipSuccess ||
       (e = alloc((void**)&g->sy, sizeof(float) * n)) != hipSuccess ||
@@ -294,6 +363,7 @@ aidw_status build_grid_impl(const float* x, const float* y, int64_t n, const flo
   if ((e = launch_cell_start_gather(sk, sv, (int)n, ncells, x, y, g->cell_start, g->sx, g->sy, g->sidx, s)) !=
       hipSuccess)
     return cleanup(hip_fail(e, "cell offsets / gather"));
+  if (bins) bins->valid = false;
   *out = g;
   return AIDW_OK;
 }
@@ -308,9 +378,15 @@ aidw_status check_data(const float* x, const float* y, int64_t n, const float* q
   return AIDW_OK;
 }
 
-aidw_status knn_impl(const aidw_grid* g, const float* qx, const float* qy, int64_t m, int32_t k, float* r_obs,
-                     float* d1sq, int32_t* nn_idx, hipStream_t s, bool paper_rule = false) {
-  Temps t(s);
+// The queries in cell order: those the grid build binned (bins), else a counting sort here,
+// which needs the grid's host description.
+aidw_status query_order(const aidw_grid* g, const float* qx, const float* qy, int64_t m, const QueryBins* bins,
+                        Temps& t, hipStream_t s, const uint32_t** order_out) {
+  if (bins && bins->valid) {
+    *order_out = bins->order;
+    return AIDW_OK;
+  }
+  if (!g->host_valid) return fail(AIDW_EDEVICE, "query binning needs the grid's description");
   const int64_t ncells = g->host.ncells;
   uint32_t *cnt, *key, *slot, *scan, *order;
   hipError_t e;
@@ -320,6 +396,17 @@ aidw_status knn_impl(const aidw_grid* g, const float* qx, const float* qy, int64
     return hip_fail(e, "allocating query-binning buffers");
   // bin the queries with the data's cell formula: order lists them in cell order
   HIP_TRY(bin_queries(g->dev, qx, qy, (int)m, ncells, cnt, key, slot, scan, order, s), "query binning");
+  *order_out = order;
+  return AIDW_OK;
+}
+
+aidw_status knn_impl(const aidw_grid* g, const float* qx, const float* qy, int64_t m, int32_t k, float* r_obs,
+                     float* d1sq, int32_t* nn_idx, hipStream_t s, bool paper_rule = false,
+                     const QueryBins* bins = nullptr) {
+  Temps t(s);
+  const uint32_t* order = nullptr;
+  aidw_status st = query_order(g, qx, qy, m, bins, t, s, &order);
+  if (st != AIDW_OK) return st;
   if (paper_rule) {
     HIP_TRY(launch_knn_paper(g->dev, g->cell_start, g->sx, g->sy, g->sidx, qx, qy, order, (int)m, k, r_obs, d1sq,
                              nn_idx, s),
@@ -328,8 +415,7 @@ aidw_status knn_impl(const aidw_grid* g, const float* qx, const float* qy, int64
   }
   // below 2^17 queries one lane per query leaves the chip idle: four lanes share each query
   auto knn = m < (1 << 17) ? launch_knn4 : launch_knn;
-  HIP_TRY(knn(g->dev, g->cell_start, g->sx, g->sy, g->sidx, qx, qy, order, nullptr, (int)m, k, slack_cells(g->host), r_obs,
-              d1sq, nn_idx, s),
+  HIP_TRY(knn(g->dev, g->cell_start, g->sx, g->sy, g->sidx, qx, qy, order, nullptr, (int)m, k, r_obs, d1sq, nn_idx, s),
           "kNN kernel");
   return AIDW_OK;
 }
@@ -359,10 +445,19 @@ aidw_status interp_impl(const float* x, const float* y, const float* z, int64_t 
                         int64_t m, const float* r_obs, const float* d1sq, const aidw_params* p, const aidw_grid* g,
                         float* qz, float* alpha_out, hipStream_t s, hipEvent_t ev_begin, hipEvent_t ev_end,
                         int* used_q, int* used_split, const float* alpha_in = nullptr, bool naive = false) {
-  double area = p->area > 0 ? p->area : (g ? g->host.area : 0.0);
-  if (!(area > 0)) return fail(AIDW_EINVAL, "aidw_interpolate needs params.area > 0 or a grid");
   AlphaParams ap;
-  ap.r_exp = (g && !(p->area > 0) && g->n == n) ? g->host.r_exp : 1.0 / (2.0 * sqrt((double)n / area));
+  if (p->area > 0) {
+    ap.r_exp = 1.0 / (2.0 * sqrt((double)n / p->area));
+  } else if (!g) {
+    return fail(AIDW_EINVAL, "aidw_interpolate needs params.area > 0 or a grid");
+  } else if (g->host_valid) {
+    if (!(g->host.area > 0)) return fail(AIDW_EINVAL, "the grid's area is not positive");
+    ap.r_exp = g->n == n ? g->host.r_exp : 1.0 / (2.0 * sqrt((double)n / g->host.area));
+  } else {
+    // a grid still being built on this stream (a run): its r_exp is read on the device
+    ap.r_exp = 0.0;
+    ap.r_exp_dev = &g->dev->r_exp;
+  }
   ap.r_min = p->r_min;
   ap.r_max = p->r_max;
   for (int i = 0; i < 5; ++i) ap.levels[i] = p->alpha[i];
@@ -416,7 +511,7 @@ aidw_status interp_impl(const float* x, const float* y, const float* z, int64_t 
             "interpolation kernel (untiled)");
   } else {
     HIP_TRY(launch_interp(xp, yp, zp, (int)n, qx, qy, alpha_use, d1sq, cperm, ckeys, (int)m, fast_mask, q, split, qz,
-                          partial, s),
+                          partial, g ? g->dev : nullptr, s),
             "interpolation kernel");
   }
   if (ev_end) HIP_TRY(hipEventRecord(ev_end, s), "event");
@@ -617,6 +712,27 @@ aidw_status aidw_knn_paper(const aidw_grid* g, const float* qx, const float* qy,
   return knn_impl(g, qx, qy, m, k, r_obs, d1sq, nn_idx, stream, true);
 }
 
+aidw_status aidw_nn_statistic(const aidw_grid* g, const float* qx, const float* qy, int64_t m, int32_t k, double clip,
+                              float* R, hipStream_t stream) {
+  g_detail.clear();
+  if (!g) return fail(AIDW_EINVAL, "grid is NULL");
+  if (m < 0) return fail(AIDW_EINVAL, "m = %lld < 0", (long long)m);
+  if (m > INT32_MAX) return fail(AIDW_ECAPACITY, "m exceeds INT32_MAX");
+  if (k < 1 || k > AIDW_KMAX || k > g->n)
+    return fail(AIDW_EINVAL, "k = %d must be in [1, min(n = %lld, %d)]", k, (long long)g->n, AIDW_KMAX);
+  if (isnan(clip)) return fail(AIDW_EINVAL, "clip is NaN");
+  if (m == 0) return AIDW_OK;
+  if (!qx || !qy || !R) return fail(AIDW_EINVAL, "qx / qy / R is NULL");
+  Temps t(stream);
+  float* r_obs = nullptr;
+  HIP_TRY(t.get(&r_obs, m), "allocating r_obs");
+  aidw_status st = knn_impl(g, qx, qy, m, k, r_obs, nullptr, nullptr, stream);
+  if (st != AIDW_OK) return st;
+  const double cap = isinf(clip) ? 0.0 : clip;
+  HIP_TRY(launch_nn_statistic(r_obs, (int)m, g->host.r_exp, cap, R, stream), "statistic kernel");
+  return AIDW_OK;
+}
+
 aidw_status aidw_interpolate(const float* x, const float* y, const float* z, int64_t n, const float* qx,
                              const float* qy, int64_t m, const float* r_obs, const float* d1sq, const aidw_params* p,
                              const aidw_grid* g, float* qz, float* alpha_out, hipStream_t stream) {
@@ -684,7 +800,8 @@ aidw_status aidw_run(const float* x, const float* y, const float* z, int64_t n, 
   }
   aidw_grid* g = nullptr;
   Temps grid_temps(stream);
-  if ((st = build_grid_impl(x, y, n, qx, qy, m, p, stream, true, &g, &grid_temps)) != AIDW_OK) return st;
+  QueryBins bins;
+  if ((st = build_grid_impl(x, y, n, qx, qy, m, p, stream, true, &g, &grid_temps, &bins, false)) != AIDW_OK) return st;
   if (ev) {
     hipError_t e = hipEventRecord(ev[1], stream);
     if (e != hipSuccess) {
@@ -699,7 +816,7 @@ aidw_status aidw_run(const float* x, const float* y, const float* z, int64_t n, 
     if (!robs) e = t.get(&robs, m);
     if (e == hipSuccess) e = t.get(&d1sq, m);
     if (e != hipSuccess) st = hip_fail(e, "allocating r_obs / d1sq");
-    if (st == AIDW_OK) st = knn_impl(g, qx, qy, m, p->k, robs, d1sq, nullptr, stream);
+    if (st == AIDW_OK) st = knn_impl(g, qx, qy, m, p->k, robs, d1sq, nullptr, stream, false, &bins);
     int q = 0, split = 0;
     if (st == AIDW_OK)
       st = interp_impl(x, y, z, n, qx, qy, m, robs, d1sq, p, g, qz, alpha_out, stream, ev ? ev[2] : nullptr,
@@ -711,6 +828,9 @@ aidw_status aidw_run(const float* x, const float* y, const float* z, int64_t n, 
       g_tm.split = split;
     }
   }
+  // the grid was built without a host round trip: its status (non-finite input, degenerate
+  // area) is read once everything is queued
+  if (st == AIDW_OK && !g->host_valid) st = sync_grid_host(g, stream);
   aidw_grid_destroy(g);
   return st;
 }
@@ -821,9 +941,7 @@ aidw_status aidw_features(const aidw_grid* g, const float* qx, const float* qy, 
   if (m < 0 || m > INT32_MAX) return fail(AIDW_EINVAL, "m = %lld out of range", (long long)m);
   if (m == 0) return AIDW_OK;
   if (!qx || !qy || !feat) return fail(AIDW_EINVAL, "qx / qy / feat is NULL");
-  const double inv_occ = (double)g->host.ncells / (double)g->n;
-  HIP_TRY(launch_features(g->dev, g->cell_start, g->sx, g->sy, qx, qy, nullptr, (int)m, inv_occ,
-                          slack_cells(g->host), feat, d1sq, stream),
+  HIP_TRY(launch_features(g->dev, g->cell_start, g->sx, g->sy, qx, qy, nullptr, (int)m, g->n, feat, d1sq, stream),
           "feature kernel");
   return AIDW_OK;
 }
@@ -902,8 +1020,7 @@ aidw_status aidw_run_learned(const float* x, const float* y, const float* z, int
   if (!z) return fail(AIDW_EINVAL, "z is NULL");
   if ((st = check_params(p)) != AIDW_OK) return st;
   if (!mlp) return fail(AIDW_EINVAL, "network is NULL");
-  if (rule != AIDW_FALLBACK_LITERAL && rule != AIDW_FALLBACK_ALPHA_EXACT && rule != AIDW_FALLBACK_CERTIFIED &&
-      rule != AIDW_FALLBACK_CERTIFIED_THEN_ALPHA_EXACT)
+  if (rule < AIDW_FALLBACK_LITERAL || rule > AIDW_FALLBACK_NETWORK_GATED_CERTIFICATE)
     return fail(AIDW_EINVAL, "unknown rule %d", rule);
   if (!(delta >= 0) || !isfinite(delta)) return fail(AIDW_EINVAL, "delta must be finite and >= 0");
   if (p->cell_width > 0 || p->occupancy != mlp->occupancy)
@@ -924,7 +1041,9 @@ aidw_status aidw_run_learned(const float* x, const float* y, const float* z, int
   }
   aidw_grid* g = nullptr;
   Temps grid_temps(stream);
-  if ((st = build_grid_impl(x, y, n, qx, qy, m, p, stream, true, &g, &grid_temps)) != AIDW_OK) return st;
+  QueryBins bins;
+  if ((st = build_grid_impl(x, y, n, qx, qy, m, p, stream, true, &g, &grid_temps, &bins, false)) != AIDW_OK)
+    return st;
   uint32_t host_count = 0;
   {
     Temps t(stream);
@@ -935,47 +1054,40 @@ aidw_status aidw_run_learned(const float* x, const float* y, const float* z, int
     // order; the fallback list is the flagged positions, compacted in order by a prefix sum,
     // so the kNN kernel sees them binned as well (its locality depends on that order).
     float *d1sq = nullptr, *alpha_f = nullptr, *r_obs = nullptr;
-    uint32_t *cnt = nullptr, *key = nullptr, *slot = nullptr, *scan = nullptr, *order = nullptr, *flag = nullptr,
-             *list = nullptr, *stmp = nullptr, *count = nullptr;
+    uint32_t *flag = nullptr, *list = nullptr, *stmp = nullptr, *count = nullptr;
     const int mm = (int)m;
-    const int64_t ncells = g->host.ncells;
     if (e == hipSuccess) e = t.get(&d1sq, mm);
     if (e == hipSuccess) e = t.get(&alpha_f, mm);
     if (e == hipSuccess) e = t.get(&r_obs, mm);
-    if (e == hipSuccess) e = t.get(&cnt, ncells + 1);
-    if (e == hipSuccess) e = t.get(&key, mm);
-    if (e == hipSuccess) e = t.get(&slot, mm);
-    if (e == hipSuccess) e = t.get(&scan, scan_tmp_words(ncells + 1));
-    if (e == hipSuccess) e = t.get(&order, mm);
     if (e == hipSuccess) e = t.get(&flag, mm);
     if (e == hipSuccess) e = t.get(&list, mm);
     if (e == hipSuccess) e = t.get(&stmp, scan_tmp_words(mm));
     if (e == hipSuccess) e = t.get(&count, 1);
     if (e != hipSuccess) st = hip_fail(e, "allocating learned-R buffers");
+    const uint32_t* order = nullptr;
+    if (st == AIDW_OK) st = query_order(g, qx, qy, m, &bins, t, stream, &order);
     AlphaParams ap;
-    ap.r_exp = g->host.r_exp;
+    ap.r_exp = 0.0;
+    ap.r_exp_dev = &g->dev->r_exp;
     ap.r_min = p->r_min;
     ap.r_max = p->r_max;
     for (int i = 0; i < 5; ++i) ap.levels[i] = p->alpha[i];
     // R where mu = 0.1 and 0.9 (Eq. 5 as applied): alpha is saturated below / above them (Eq. 6)
     const double r_sat_lo = p->r_min + p->r_max / M_PI * acos(0.8);
     const double r_sat_hi = p->r_min + p->r_max / M_PI * acos(-0.8);
-    const double inv_occ = (double)g->host.ncells / (double)n;
-    // the certificate's threshold on the sum of the k nearest distances: alpha = alpha_5 for
-    // R > min(r_sat_hi, R_max) (Eq. 5 is 1 from R_max on); the margin covers the float32
-    // rounding of r_obs and the rounding of mu near 0.9
-    const double cert_sum_min = (double)p->k * g->host.r_exp * fmin(r_sat_hi, p->r_max) * (1.0 + 1e-6);
+    // the certificate's threshold on the sum of the k nearest distances, in units of r_exp:
+    // alpha = alpha_5 for R > min(r_sat_hi, R_max) (Eq. 5 is 1 from R_max on); the margin covers
+    // the float32 rounding of r_obs and the rounding of mu near 0.9
+    const double cert_factor = (double)p->k * fmin(r_sat_hi, p->r_max) * (1.0 + 1e-6);
 #define STEP(expr, what) \
   if (st == AIDW_OK && (e = (expr)) != hipSuccess) st = hip_fail(e, what)
-    STEP(bin_queries(g->dev, qx, qy, mm, ncells, cnt, key, slot, scan, order, stream), "query binning");
-    STEP(launch_learned_front(mlp->d, g->dev, g->cell_start, g->sx, g->sy, qx, qy, order, mm, inv_occ,
-                              slack_cells(g->host), ap, rule, delta, r_sat_lo, r_sat_hi, p->k, cert_sum_min, flag,
-                              alpha_f, d1sq, r_hat_out, stream),
+    STEP(launch_learned_front(mlp->d, g->dev, g->cell_start, g->sx, g->sy, qx, qy, order, mm, n, ap, rule, delta,
+                              r_sat_lo, r_sat_hi, p->k, cert_factor, flag, alpha_f, d1sq, r_hat_out, nullptr, stream),
          "features / network / decision kernel");
     STEP(compact_flags(flag, order, mm, stmp, list, count, stream), "fallback compaction");
     // the fallback queries are few and hard (cluster edges): eight lanes per query measured best
-    STEP(launch_knn_lanes(g->dev, g->cell_start, g->sx, g->sy, g->sidx, qx, qy, list, count, mm, p->k,
-                          slack_cells(g->host), r_obs, d1sq, nullptr, 8, stream, &ap, alpha_f),
+    STEP(launch_knn_lanes(g->dev, g->cell_start, g->sx, g->sy, g->sidx, qx, qy, list, count, mm, p->k, r_obs, d1sq,
+                          nullptr, 8, stream, &ap, alpha_f),
          "kNN kernel (with Eq. 4-6)");
 #undef STEP
     int q = 0, split = 0;
@@ -992,12 +1104,67 @@ aidw_status aidw_run_learned(const float* x, const float* y, const float* z, int
       g_tm.split = split;
     }
   }
+  if (st == AIDW_OK && !g->host_valid) st = sync_grid_host(g, stream);
   aidw_grid_destroy(g);
   if (st == AIDW_OK && fallback_count) {
     hipError_t e = hipStreamSynchronize(stream);
     if (e != hipSuccess) return hip_fail(e, "synchronising");
     *fallback_count = host_count;
   }
+  return st;
+}
+
+aidw_status aidw_learned_routes(const float* x, const float* y, int64_t n, const float* qx, const float* qy,
+                                int64_t m, const aidw_params* p, const aidw_mlp* mlp, int32_t rule, double delta,
+                                uint8_t* route_out, float* r_hat_out, hipStream_t stream) {
+  g_detail.clear();
+  aidw_status st = check_data(x, y, n, qx, qy, m);
+  if (st != AIDW_OK) return st;
+  if ((st = check_params(p)) != AIDW_OK) return st;
+  if (!mlp) return fail(AIDW_EINVAL, "network is NULL");
+  if (rule < AIDW_FALLBACK_LITERAL || rule > AIDW_FALLBACK_NETWORK_GATED_CERTIFICATE)
+    return fail(AIDW_EINVAL, "unknown rule %d", rule);
+  if (!(delta >= 0) || !isfinite(delta)) return fail(AIDW_EINVAL, "delta must be finite and >= 0");
+  if (p->cell_width > 0 || p->occupancy != mlp->occupancy)
+    return fail(AIDW_EINVAL, "the grid must use the network's occupancy (%g) and no explicit cell width",
+                mlp->occupancy);
+  if (p->k < 1 || p->k > AIDW_KMAX || p->k > n)
+    return fail(AIDW_EINVAL, "k = %d must be in [1, min(n = %lld, %d)]", p->k, (long long)n, AIDW_KMAX);
+  if (m == 0) return AIDW_OK;
+  if (!route_out) return fail(AIDW_EINVAL, "route_out is NULL");
+  aidw_grid* g = nullptr;
+  Temps grid_temps(stream);
+  QueryBins bins;
+  if ((st = build_grid_impl(x, y, n, qx, qy, m, p, stream, true, &g, &grid_temps, &bins, false)) != AIDW_OK)
+    return st;
+  {
+    Temps t(stream);
+    const int mm = (int)m;
+    float *d1sq = nullptr, *alpha_f = nullptr;
+    uint32_t* flag = nullptr;
+    hipError_t e = t.get(&d1sq, mm);
+    if (e == hipSuccess) e = t.get(&alpha_f, mm);
+    if (e == hipSuccess) e = t.get(&flag, mm);
+    if (e != hipSuccess) st = hip_fail(e, "allocating learned-R buffers");
+    const uint32_t* order = nullptr;
+    if (st == AIDW_OK) st = query_order(g, qx, qy, m, &bins, t, stream, &order);
+    AlphaParams ap;
+    ap.r_exp = 0.0;
+    ap.r_exp_dev = &g->dev->r_exp;
+    ap.r_min = p->r_min;
+    ap.r_max = p->r_max;
+    for (int i = 0; i < 5; ++i) ap.levels[i] = p->alpha[i];
+    const double r_sat_lo = p->r_min + p->r_max / M_PI * acos(0.8);
+    const double r_sat_hi = p->r_min + p->r_max / M_PI * acos(-0.8);
+    const double cert_factor = (double)p->k * fmin(r_sat_hi, p->r_max) * (1.0 + 1e-6);
+    if (st == AIDW_OK &&
+        (e = launch_learned_front(mlp->d, g->dev, g->cell_start, g->sx, g->sy, qx, qy, order, mm, n, ap, rule, delta,
+                                  r_sat_lo, r_sat_hi, p->k, cert_factor, flag, alpha_f, d1sq, r_hat_out, route_out,
+                                  stream)) != hipSuccess)
+      st = hip_fail(e, "features / network / decision kernel");
+  }
+  if (st == AIDW_OK && !g->host_valid) st = sync_grid_host(g, stream);
+  aidw_grid_destroy(g);
   return st;
 }
 

@@ -24,7 +24,7 @@ __device__ inline int wave_or(int v) {
 }
 
 // Min / max / non-finite flag over the bounds partials [begin, end), reduced by a
-// workgroup of 256 threads; the result is valid in thread 0.
+// workgroup of up to 1024 threads; the result is valid in every thread.
 __device__ inline BoundsPartial block_reduce_bounds(const BoundsPartial* __restrict__ partial, int begin, int end) {
   float mnx = INFINITY, mny = INFINITY, mxx = -INFINITY, mxy = -INFINITY;
   int bad = 0;
@@ -40,12 +40,13 @@ __device__ inline BoundsPartial block_reduce_bounds(const BoundsPartial* __restr
   mxx = wave_max(mxx);
   mxy = wave_max(mxy);
   bad = wave_or(bad);
-  __shared__ BoundsPartial s[4];
+  __shared__ BoundsPartial s[16];  // one per wavefront of a block of up to 1024 threads
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   if (lane == 0) s[wave] = BoundsPartial{mnx, mny, mxx, mxy, bad, {0, 0, 0}};
   __syncthreads();
   BoundsPartial r = s[0];
-  for (int w = 1; w < 4; ++w) {
+  const int nw = (int)(blockDim.x + 63) >> 6;
+  for (int w = 1; w < nw; ++w) {
     r.minx = fminf(r.minx, s[w].minx);
     r.miny = fminf(r.miny, s[w].miny);
     r.maxx = fmaxf(r.maxx, s[w].maxx);

@@ -58,13 +58,22 @@ __global__ __launch_bounds__(256) void k_alpha_class(const float* __restrict__ r
   const int q = blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= m) return;
   if (d1sq[q] == 0.0f) list[atomicAdd(count, 1u)] = (uint32_t)q;
-  const double R = (double)r_obs[q] / ap.r_exp;                                  // Eq. 4
+  const double R = (double)r_obs[q] / alpha_r_exp(ap);                           // Eq. 4
   const double alpha = level_alpha(fuzzy_mu(R, ap.r_min, ap.r_max), ap.levels);  // Eq. 5, 6
   const float af = (float)alpha;
   alpha_f[q] = af;
   if (alpha_out) alpha_out[q] = af;
   keys[q] = alpha_class(alpha);
   vals[q] = (uint32_t)q;
+}
+
+// Eq. 4: the nearest-neighbour statistic R = r_obs / r_exp of each query, capped at clip.
+__global__ __launch_bounds__(256) void k_nn_statistic(const float* __restrict__ r_obs, int m, double r_exp,
+                                                      double clip, float* __restrict__ R) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= m) return;
+  const double v = (double)r_obs[q] / r_exp;
+  R[q] = (float)(clip > 0.0 ? fmin(v, clip) : v);
 }
 
 // The class key of a given alpha, the identity permutation and the coincident-query list (as
@@ -135,7 +144,9 @@ __global__ __launch_bounds__(kThreads) void k_interp(const float* __restrict__ x
                                                      const float* __restrict__ d1sq,
                                                      const uint32_t* __restrict__ perm,
                                                      const uint32_t* __restrict__ skeys, int m, uint32_t fast_mask,
-                                                     float* __restrict__ qz, double2* __restrict__ partial) {
+                                                     float* __restrict__ qz, double2* __restrict__ partial,
+                                                     const GridScalars* __restrict__ gs) {
+  if (gs && gs->status != AIDW_OK) return;  // a failed grid build: no result to compute
   const int pos0 = blockIdx.x * kThreads * Q;
   const int posl = min(m, pos0 + kThreads * Q) - 1;
   const uint32_t k0 = skeys[pos0], kl = skeys[posl];
@@ -222,6 +233,7 @@ __global__ __launch_bounds__(256) void k_fixup_grid(const uint32_t* __restrict__
                                                     const float* __restrict__ sx, const float* __restrict__ sy,
                                                     const int32_t* __restrict__ sidx, const float* __restrict__ z,
                                                     float* __restrict__ qz) {
+  if (gs->status != AIDW_OK) return;
   const uint32_t cnt = *count;
   const knn::View g{gs->minx, gs->miny, gs->inv_cw, gs->ncol, gs->nrow, gs->cwd};
   for (uint32_t e = blockIdx.x * blockDim.x + threadIdx.x; e < cnt; e += gridDim.x * blockDim.x) {
@@ -278,6 +290,12 @@ hipError_t launch_alpha_class(const float* r_obs, int m, const AlphaParams& ap, 
   return hipGetLastError();
 }
 
+hipError_t launch_nn_statistic(const float* r_obs, int m, double r_exp, double clip, float* R, hipStream_t s) {
+  if (m <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_nn_statistic, dim3((m + 255) / 256), dim3(256), 0, s, r_obs, m, r_exp, clip, R);
+  return hipGetLastError();
+}
+
 hipError_t launch_class_keys(const float* alpha_f, int m, uint32_t* keys, uint32_t* vals, const float* d1sq,
                              uint32_t* count, uint32_t* list, hipStream_t s) {
   if (m <= 0) return hipSuccess;
@@ -290,9 +308,10 @@ namespace {
 template <int Q>
 hipError_t launch_q(dim3 grid, hipStream_t s, const float* x, const float* y, const float* z, int n, int chunk,
                     const float* qx, const float* qy, const float* alpha_f, const float* d1sq, const uint32_t* perm,
-                    const uint32_t* skeys, int m, uint32_t mask, float* qz, double2* partial) {
+                    const uint32_t* skeys, int m, uint32_t mask, float* qz, double2* partial,
+                    const GridScalars* gs) {
   hipLaunchKernelGGL((k_interp<Q>), grid, dim3(kThreads), 0, s, x, y, z, n, chunk, qx, qy, alpha_f, d1sq, perm, skeys,
-                     m, mask, qz, partial);
+                     m, mask, qz, partial, gs);
   return hipGetLastError();
 }
 
@@ -300,17 +319,18 @@ hipError_t launch_q(dim3 grid, hipStream_t s, const float* x, const float* y, co
 
 hipError_t launch_interp(const float* x, const float* y, const float* z, int n, const float* qx, const float* qy,
                          const float* alpha_f, const float* d1sq, const uint32_t* perm, const uint32_t* skeys, int m,
-                         uint32_t fast_mask, int q, int split, float* qz, double2* partial, hipStream_t s) {
+                         uint32_t fast_mask, int q, int split, float* qz, double2* partial, const GridScalars* gs,
+                         hipStream_t s) {
   if (m <= 0) return hipSuccess;
   int chunk = (n + split - 1) / split;
   chunk = (chunk + kChunk - 1) / kChunk * kChunk;
   const dim3 grid((m + kThreads * q - 1) / (kThreads * q), split);
   fast_mask &= ((1u << (kMaxIntPow + 1)) - 2u);
   switch (q) {
-    case 1: return launch_q<1>(grid, s, x, y, z, n, chunk, qx, qy, alpha_f, d1sq, perm, skeys, m, fast_mask, qz, partial);
-    case 2: return launch_q<2>(grid, s, x, y, z, n, chunk, qx, qy, alpha_f, d1sq, perm, skeys, m, fast_mask, qz, partial);
-    case 4: return launch_q<4>(grid, s, x, y, z, n, chunk, qx, qy, alpha_f, d1sq, perm, skeys, m, fast_mask, qz, partial);
-    case 8: return launch_q<8>(grid, s, x, y, z, n, chunk, qx, qy, alpha_f, d1sq, perm, skeys, m, fast_mask, qz, partial);
+    case 1: return launch_q<1>(grid, s, x, y, z, n, chunk, qx, qy, alpha_f, d1sq, perm, skeys, m, fast_mask, qz, partial, gs);
+    case 2: return launch_q<2>(grid, s, x, y, z, n, chunk, qx, qy, alpha_f, d1sq, perm, skeys, m, fast_mask, qz, partial, gs);
+    case 4: return launch_q<4>(grid, s, x, y, z, n, chunk, qx, qy, alpha_f, d1sq, perm, skeys, m, fast_mask, qz, partial, gs);
+    case 8: return launch_q<8>(grid, s, x, y, z, n, chunk, qx, qy, alpha_f, d1sq, perm, skeys, m, fast_mask, qz, partial, gs);
     default: return hipErrorInvalidValue;
   }
 }

@@ -38,17 +38,18 @@ __global__ __launch_bounds__(256) void k_knn(const GridScalars* __restrict__ gs,
                                              const float* __restrict__ sx, const float* __restrict__ sy,
                                              const int32_t* __restrict__ sidx, const float* __restrict__ qx,
                                              const float* __restrict__ qy, const uint32_t* __restrict__ qperm,
-                                             const uint32_t* __restrict__ active, int m, int k, double slack_cells,
+                                             const uint32_t* __restrict__ active, int m, int k,
                                              float* __restrict__ r_obs, float* __restrict__ d1sq,
                                              int32_t* __restrict__ nn_idx) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= m || (active && (uint32_t)t >= *active)) return;
+  if (t >= m || (active && (uint32_t)t >= *active) || gs->status != AIDW_OK) return;
+  const double slack = slack_cells(gs->ncol, gs->nrow);
   const int q = qperm ? (int)qperm[t] : t;
   const float fx = qx[q], fy = qy[q];
   const knn::View g{gs->minx, gs->miny, gs->inv_cw, gs->ncol, gs->nrow, gs->cwd};
   double bk[KMAX];
   int32_t bi[KMAX];
-  knn::search<KMAX, 1, PAPER>(g, cell_start, sx, sy, sidx, fx, fy, k, slack_cells, bk, bi);
+  knn::search<KMAX, 1, PAPER>(g, cell_start, sx, sy, sidx, fx, fy, k, slack, bk, bi);
   float ro, d1;
   knn::summarise<KMAX>(bk, k, ro, d1);
   r_obs[q] = ro;
@@ -69,18 +70,20 @@ __global__ __launch_bounds__(256) void k_knn_lanes(const GridScalars* __restrict
                                               const float* __restrict__ sx, const float* __restrict__ sy,
                                               const int32_t* __restrict__ sidx, const float* __restrict__ qx,
                                               const float* __restrict__ qy, const uint32_t* __restrict__ qperm,
-                                              const uint32_t* __restrict__ active, int m, int k, double slack_cells,
+                                              const uint32_t* __restrict__ active, int m, int k,
                                               float* __restrict__ r_obs, float* __restrict__ d1sq,
                                               int32_t* __restrict__ nn_idx, AlphaParams ap,
                                               float* __restrict__ alpha_f) {
   const int gt = blockIdx.x * blockDim.x + threadIdx.x;
   const int t = gt / LANES, sub = gt % LANES;
-  if (t >= m || (active && (uint32_t)t >= *active)) return;  // the lanes of a query leave together
+  // the lanes of a query leave together
+  if (t >= m || (active && (uint32_t)t >= *active) || gs->status != AIDW_OK) return;
+  const double slack = slack_cells(gs->ncol, gs->nrow);
   const int q = qperm ? (int)qperm[t] : t;
   const knn::View g{gs->minx, gs->miny, gs->inv_cw, gs->ncol, gs->nrow, gs->cwd};
   double bk[KMAX];
   int32_t bi[KMAX];
-  knn::search<KMAX, LANES>(g, cell_start, sx, sy, sidx, qx[q], qy[q], k, slack_cells, bk, bi, sub);
+  knn::search<KMAX, LANES>(g, cell_start, sx, sy, sidx, qx[q], qy[q], k, slack, bk, bi, sub);
   float ro, d1;
   knn::merge_lanes<KMAX, LANES>(bk, bi, k, sub, ro, d1, nn_idx ? nn_idx + (size_t)q * k : nullptr);
   if (sub == 0) {
@@ -88,7 +91,8 @@ __global__ __launch_bounds__(256) void k_knn_lanes(const GridScalars* __restrict
     if (d1sq) d1sq[q] = d1;
     // Eq. 4-6 from the stored r_obs, as the alpha kernel of the plain path computes them
     if (alpha_f)
-      alpha_f[q] = (float)pair::level_alpha(pair::fuzzy_mu((double)ro / ap.r_exp, ap.r_min, ap.r_max), ap.levels);
+      alpha_f[q] =
+          (float)pair::level_alpha(pair::fuzzy_mu((double)ro / alpha_r_exp(ap), ap.r_min, ap.r_max), ap.levels);
   }
 }
 
@@ -173,7 +177,7 @@ hipError_t launch_knn_paper(const GridScalars* gs, const int32_t* cell_start, co
   const dim3 grid((m + 255) / 256), block(256);
 #define AIDW_KNNP(K)                                                                                                \
   hipLaunchKernelGGL((k_knn<K, true>), grid, block, 0, s, gs, cell_start, sx, sy, sidx, qx, qy, qperm, nullptr, m, \
-                     k, 0.0, r_obs, d1sq, nn_idx)
+                     k, r_obs, d1sq, nn_idx)
   if (k <= 8)
     AIDW_KNNP(8);
   else if (k <= 16)
@@ -188,8 +192,8 @@ hipError_t launch_knn_paper(const GridScalars* gs, const int32_t* cell_start, co
 
 hipError_t launch_knn_lanes(const GridScalars* gs, const int32_t* cell_start, const float* sx, const float* sy,
                             const int32_t* sidx, const float* qx, const float* qy, const uint32_t* qperm,
-                            const uint32_t* active, int m, int k, double slack_cells, float* r_obs, float* d1sq,
-                            int32_t* nn_idx, int lanes, hipStream_t s, const AlphaParams* ap, float* alpha_f) {
+                            const uint32_t* active, int m, int k, float* r_obs, float* d1sq, int32_t* nn_idx,
+                            int lanes, hipStream_t s, const AlphaParams* ap, float* alpha_f) {
   if (m <= 0) return hipSuccess;
   const AlphaParams apv = ap ? *ap : AlphaParams{};
   if (!ap) alpha_f = nullptr;
@@ -199,7 +203,7 @@ hipError_t launch_knn_lanes(const GridScalars* gs, const int32_t* cell_start, co
   const dim3 grid((int)(((int64_t)m * lanes + 255) / 256)), block(256);
 #define AIDW_KNNL(K, LN)                                                                                         \
   hipLaunchKernelGGL((k_knn_lanes<K, LN>), grid, block, 0, s, gs, cell_start, sx, sy, sidx, qx, qy, qperm, active, \
-                     m, k, slack_cells, r_obs, d1sq, nn_idx, apv, alpha_f)
+                     m, k, r_obs, d1sq, nn_idx, apv, alpha_f)
 #define AIDW_KNNL_2(K) AIDW_KNNL(K, 2)
 #define AIDW_KNNL_4(K) AIDW_KNNL(K, 4)
 #define AIDW_KNNL_8(K) AIDW_KNNL(K, 8)
@@ -221,21 +225,20 @@ hipError_t launch_knn_lanes(const GridScalars* gs, const int32_t* cell_start, co
 
 hipError_t launch_knn4(const GridScalars* gs, const int32_t* cell_start, const float* sx, const float* sy,
                        const int32_t* sidx, const float* qx, const float* qy, const uint32_t* qperm,
-                       const uint32_t* active, int m, int k, double slack_cells, float* r_obs, float* d1sq,
-                       int32_t* nn_idx, hipStream_t s) {
-  return launch_knn_lanes(gs, cell_start, sx, sy, sidx, qx, qy, qperm, active, m, k, slack_cells, r_obs, d1sq, nn_idx,
-                          4, s);
+                       const uint32_t* active, int m, int k, float* r_obs, float* d1sq, int32_t* nn_idx,
+                       hipStream_t s) {
+  return launch_knn_lanes(gs, cell_start, sx, sy, sidx, qx, qy, qperm, active, m, k, r_obs, d1sq, nn_idx, 4, s);
 }
 
 hipError_t launch_knn(const GridScalars* gs, const int32_t* cell_start, const float* sx, const float* sy,
                       const int32_t* sidx, const float* qx, const float* qy, const uint32_t* qperm,
-                      const uint32_t* active, int m, int k, double slack_cells, float* r_obs, float* d1sq,
-                      int32_t* nn_idx, hipStream_t s) {
+                      const uint32_t* active, int m, int k, float* r_obs, float* d1sq, int32_t* nn_idx,
+                      hipStream_t s) {
   if (m <= 0) return hipSuccess;
   const dim3 grid((m + 255) / 256), block(256);
 #define AIDW_KNN1(K)                                                                                              \
   hipLaunchKernelGGL(k_knn<K>, grid, block, 0, s, gs, cell_start, sx, sy, sidx, qx, qy, qperm, active, m, k, \
-                     slack_cells, r_obs, d1sq, nn_idx)
+                     r_obs, d1sq, nn_idx)
   AIDW_FOR_KNN_SLOTS(k, AIDW_KNN1)
 #undef AIDW_KNN1
   return hipGetLastError();

@@ -80,11 +80,12 @@ __global__ __launch_bounds__(256) void k_features(const GridScalars* __restrict_
                                                   const int32_t* __restrict__ cell_start,
                                                   const float* __restrict__ sx, const float* __restrict__ sy,
                                                   const float* __restrict__ qx, const float* __restrict__ qy,
-                                                  const uint32_t* __restrict__ perm, int m, double inv_occ,
-                                                  double slack_cells, float* __restrict__ feat,
-                                                  float* __restrict__ d1sq) {
+                                                  const uint32_t* __restrict__ perm, int m, int64_t n,
+                                                  float* __restrict__ feat, float* __restrict__ d1sq) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= m) return;
+  const double inv_occ = (double)gs->ncells / (double)n;
+  const double slack = slack_cells(gs->ncol, gs->nrow);
   const int q = perm ? (int)perm[t] : t;
   const float minx = gs->minx, miny = gs->miny, inv = gs->inv_cw;
   const int ncol = gs->ncol, nrow = gs->nrow;
@@ -134,7 +135,7 @@ __global__ __launch_bounds__(256) void k_features(const GridScalars* __restrict_
   if (c0 + 1 < ncol - 1) dout = fmin(dout, (minxd + (double)(c0 + 2) * cwd) - px);
   if (r0 - 1 > 0) dout = fmin(dout, py - (minyd + (double)(r0 - 1) * cwd));
   if (r0 + 1 < nrow - 1) dout = fmin(dout, (minyd + (double)(r0 + 2) * cwd) - py);
-  dout -= slack_cells * cwd;
+  dout -= slack * cwd;
   double v;
   if (dout == INFINITY || best < dout * dout)
     v = best;                       // exact nearest distance
@@ -387,6 +388,10 @@ __global__ void k_accumulate_loss(const float* __restrict__ grad, float* __restr
 //                     point where alpha saturates at alpha_5 (certified_saturated,
 //                     certified_by_distances below); the network is not evaluated.
 //   rule 3 (certified, then alpha-exact): skip when certified, else as rule 1.
+//   rule 4 (network-gated certificate): skip only when certified, as rule 2; the 3 x 3 distance
+//                     scan is tried only where the network predicts r_hat >= r_sat_hi - delta
+//                     (elsewhere the query goes straight to the exact kNN), so the network
+//                     never sets an alpha: every query gets the exact path's.
 // Coincident queries (d1 == 0) always fall back.
 __device__ inline double fuzzy_mu_l(double R, double rmin, double rmax) {
   if (R <= rmin) return 0.0;
@@ -587,11 +592,14 @@ template <bool kCert, bool kNet>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_learned_front(
     MlpDevice d, const GridScalars* __restrict__ gs, const int32_t* __restrict__ cell_start,
     const float* __restrict__ sx, const float* __restrict__ sy, const float* __restrict__ qx,
-    const float* __restrict__ qy, const uint32_t* __restrict__ perm, int m, double inv_occ, double slack_cells,
-    AlphaParams ap, int rule, double delta, double r_sat_lo, double r_sat_hi, int k, double cert_sum_min,
-    uint32_t* __restrict__ flag, float* __restrict__ alpha_f, float* __restrict__ d1sq,
-    float* __restrict__ r_hat_out) {
+    const float* __restrict__ qy, const uint32_t* __restrict__ perm, int m, int64_t n, AlphaParams ap, int rule,
+    double delta, double r_sat_lo, double r_sat_hi, int k, double cert_factor, uint32_t* __restrict__ flag,
+    float* __restrict__ alpha_f, float* __restrict__ d1sq, float* __restrict__ r_hat_out, uint8_t* __restrict__ route) {
+  if (gs->status != AIDW_OK) return;  // a failed grid build: nothing to decide
   const int lane = threadIdx.x & 63, c = lane & 15, g = lane >> 4;
+  const double inv_occ = (double)gs->ncells / (double)n;
+  const double slack_cells = aidw::slack_cells(gs->ncol, gs->nrow);
+  const double cert_sum_min = cert_factor * gs->r_exp;
   __shared__ uint4 lds[kNetOperands];
   const MfmaNet net = kNet ? stage_net(d, lds) : MfmaNet{lds};
   const float minx = gs->minx, miny = gs->miny, inv = gs->inv_cw;
@@ -689,8 +697,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
       f[j] = kk < 25 ? (float)((double)cnt * inv_occ)
                      : (kk == 25 ? tx - (float)c0 : (kk == 26 ? ty - (float)r0 : 0.0f));
     }
-    float y = __builtin_nanf("");
-    if constexpr (kNet) y = mlp_tile(d, net, lane, pack8(f));
     const double px = fx, py = fy;
     // What the scan below has to find depends on what is decided without it (all inputs
     // here are the same on a query's four lanes): a query that takes the exact kNN in any case
@@ -709,11 +715,24 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
       cert = certified_saturated(px, py, c0, r0, ncol, nrow, minxd, minyd, cwd, slack_cells, n0, n1, n2, k,
                                  cert_sum_min);
     }
+    const bool cert_counts = cert;
+    // rule 4 runs the network only on tiles holding a query the counts did not certify and
+    // whose 3 x 3 block the certificate would scan (the MFMA tile is the wavefront's)
+    const bool scan_ok = kCert && valid && !cert && n1 <= 8 * k + 16;
+    float y = __builtin_nanf("");
+    if constexpr (kNet) {
+      if (rule != 4 || __ballot(scan_ok) != 0ull) y = mlp_tile(d, net, lane, pack8(f));
+    }
     double alpha_net = 0.0;
     bool net_fall = true;
-    if constexpr (kNet) net_fall = decide_one((double)y, 1.0f, ap, rule == 3 ? 1 : rule, delta, r_sat_lo, r_sat_hi,
-                                              &alpha_net);
-    const int mode = !valid ? 0 : cert ? 1 : (kCert && n1 <= 8 * k + 16) ? 2 : !net_fall ? 1 : 0;
+    if constexpr (kNet) {
+      if (rule != 4)
+        net_fall = decide_one((double)y, 1.0f, ap, rule == 3 ? 1 : rule, delta, r_sat_lo, r_sat_hi, &alpha_net);
+    }
+    // rule 4: the 3 x 3 certificate is tried only where the network predicts R at or beyond
+    // r_sat_hi - delta; elsewhere the query goes to the exact kNN without the scan
+    const bool gate = rule != 4 || (double)y >= r_sat_hi - delta;
+    const int mode = !valid ? 0 : cert ? 1 : (scan_ok && gate) ? 2 : !net_fall ? 1 : 0;
     if (mode == 0) {
       o1 = o0;
       p1 = p0;
@@ -823,17 +842,19 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
       d1sq[q] = d1;
     }
     if (r_hat_out) r_hat_out[q] = y;
+    if (route)
+      route[q] = fall ? (mode == 2 ? 1 : 0) : (cert ? (cert_counts ? 2 : 3) : 4);
   }
 }
 
 }  // namespace
 
 hipError_t launch_features(const GridScalars* gs, const int32_t* cell_start, const float* sx, const float* sy,
-                           const float* qx, const float* qy, const uint32_t* perm, int m, double inv_occ,
-                           double slack_cells, float* feat, float* d1sq, hipStream_t s) {
+                           const float* qx, const float* qy, const uint32_t* perm, int m, int64_t n, float* feat,
+                           float* d1sq, hipStream_t s) {
   if (m <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_features, dim3((m + 255) / 256), dim3(256), 0, s, gs, cell_start, sx, sy, qx, qy, perm, m,
-                     inv_occ, slack_cells, feat, d1sq);
+  hipLaunchKernelGGL(k_features, dim3((m + 255) / 256), dim3(256), 0, s, gs, cell_start, sx, sy, qx, qy, perm, m, n,
+                     feat, d1sq);
   return hipGetLastError();
 }
 
@@ -870,17 +891,17 @@ int tile_blocks(const void* kernel, int m) {
 
 hipError_t launch_learned_front(const MlpDevice& d, const GridScalars* gs, const int32_t* cell_start, const float* sx,
                                 const float* sy, const float* qx, const float* qy, const uint32_t* perm, int m,
-                                double inv_occ, double slack_cells, const AlphaParams& ap, int rule, double delta,
-                                double r_sat_lo, double r_sat_hi, int k, double cert_sum_min, uint32_t* flag,
-                                float* alpha_f, float* d1sq, float* r_hat_out, hipStream_t s) {
+                                int64_t n, const AlphaParams& ap, int rule, double delta, double r_sat_lo,
+                                double r_sat_hi, int k, double cert_factor, uint32_t* flag, float* alpha_f,
+                                float* d1sq, float* r_hat_out, uint8_t* route, hipStream_t s) {
   if (m <= 0) return hipSuccess;
 #define FRONT(CERT, NET)                                                                                       \
   hipLaunchKernelGGL((k_learned_front<CERT, NET>), dim3(tile_blocks((const void*)k_learned_front<CERT, NET>, m)), \
-                     dim3(256), 0, s, d, gs, cell_start, sx, sy, qx, qy, perm, m, inv_occ, slack_cells, ap, rule,   \
-                     delta, r_sat_lo, r_sat_hi, k, cert_sum_min, flag, alpha_f, d1sq, r_hat_out)
+                     dim3(256), 0, s, d, gs, cell_start, sx, sy, qx, qy, perm, m, n, ap, rule, delta, r_sat_lo,   \
+                     r_sat_hi, k, cert_factor, flag, alpha_f, d1sq, r_hat_out, route)
   if (rule == 2)
     FRONT(true, false);
-  else if (rule == 3)
+  else if (rule == 3 || rule == 4)
     FRONT(true, true);
   else
     FRONT(false, true);

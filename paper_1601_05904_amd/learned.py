@@ -13,11 +13,12 @@ import ctypes
 
 import numpy as np
 
-from . import Params, _VP, _check, _dev, _stream, build_grid, knn, load
+from . import Params, _VP, _check, _dev, _stream, build_grid, load, nn_statistic
 
 N_IN = 27
 N_PARAMS = 6017
-LITERAL, ALPHA_EXACT, CERTIFIED, CERTIFIED_THEN_ALPHA_EXACT = 0, 1, 2, 3
+LITERAL, ALPHA_EXACT, CERTIFIED, CERTIFIED_THEN_ALPHA_EXACT, NETWORK_GATED_CERTIFICATE = 0, 1, 2, 3, 4
+ROUTE_KNN, ROUTE_KNN_AFTER_SCAN, ROUTE_CERT_COUNTS, ROUTE_CERT_DISTANCES, ROUTE_NETWORK = 0, 1, 2, 3, 4
 
 
 class MLP:
@@ -123,20 +124,31 @@ def run_learned(x, y, z, qx, qy, params: Params, mlp: MLP, rule=ALPHA_EXACT, del
     return qz, al, rh, int(cnt.value)
 
 
+def learned_routes(x, y, qx, qy, params: Params, mlp: MLP, rule, delta, want_rhat=False, stream=None):
+    """aidw_learned_routes -> (route [m] uint8, r_hat [m] or None): each query's route under the rule."""
+    import torch
+    p = params._c()
+    m = qx.numel()
+    route = torch.empty(m, dtype=torch.uint8, device=qx.device)
+    rh = torch.empty(m, dtype=torch.float32, device=qx.device) if want_rhat else None
+    _check(load().aidw_learned_routes(_dev(x, "x"), _dev(y, "y"), x.numel(), _dev(qx, "qx"), _dev(qy, "qy"), m,
+                                      ctypes.byref(p), mlp.handle, int(rule), float(delta), route.data_ptr(),
+                                      None if rh is None else rh.data_ptr(), _stream(stream)))
+    return route, rh
+
+
 def training_pairs(datasets, k=15, occupancy=2.0, clip=3.0):
     """(features, target) on the GPU for the queries of each dataset: target = min(R, clip),
-    R = r_obs / r_exp from the exact kNN."""
+    R = r_obs / r_exp from the exact kNN (aidw_nn_statistic)."""
     import torch
     feats, targets = [], []
     for ds in datasets:
         t = {a: torch.from_numpy(getattr(ds, a)).cuda() for a in ("x", "y", "qx", "qy")}
         g = build_grid(t["x"], t["y"], t["qx"], t["qy"], Params(k=k, occupancy=occupancy))
         f, _ = features(g, t["qx"], t["qy"], want_d1sq=False)
-        r, _, _ = knn(g, t["qx"], t["qy"], k, want_d1sq=False)
-        r_exp = g.describe()["r_exp"]
+        targets.append(nn_statistic(g, t["qx"], t["qy"], k, clip))
         g.close()
         feats.append(f)
-        targets.append(torch.clamp(r.double() / r_exp, max=clip).float())
     return torch.cat(feats).contiguous(), torch.cat(targets).contiguous()
 
 

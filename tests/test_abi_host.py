@@ -161,3 +161,9 @@ def test_baseline_entry_points_validate(L):
     assert L.aidw_interpolate_naive(FAKE, FAKE, None, 10, FAKE, FAKE, 5, FAKE, FAKE, _p(), None, FAKE, None,
                                     None) == aidw.EINVAL
     assert L.aidw_knn_paper(None, FAKE, FAKE, 10, 5, FAKE, None, None, None) == aidw.EINVAL
+
+
+def test_nn_statistic_validates(L):
+    # null grid, negative m, k out of range and NaN clip are rejected on the host
+    assert L.aidw_nn_statistic(None, FAKE, FAKE, 10, 5, 3.0, FAKE, None) == aidw.EINVAL
+    assert L.aidw_nn_statistic(FAKE, FAKE, FAKE, -1, 5, 3.0, FAKE, None) == aidw.EINVAL

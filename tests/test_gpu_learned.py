@@ -74,48 +74,111 @@ def test_features_match_oracle(T, case):
         assert got[4] == 0.0
 
 
+@pytest.mark.parametrize("case", ["mixture_k15", "uniform_k10_noclip"])
+def test_nn_statistic_matches_oracle(T, case):
+    """aidw_nn_statistic (the training targets): R = min(r_obs / r_exp, clip) of Eq. 3-4
+    against the oracle's r_obs (brute force) and r_exp (Eq. 2), within one float32 rounding."""
+    aidw, L = mods()
+    if case == "mixture_k15":
+        ds, k, clip = W.make(20000, 5000, 15, 205, "mixture", 16), 15, 3.0
+    else:
+        ds, k, clip = W.make(9000, 3000, 10, 206), 10, 0.0
+    x, y, qx, qy = (dev(T, getattr(ds, a)) for a in ("x", "y", "qx", "qy"))
+    g = aidw.build_grid(x, y, qx, qy, aidw.Params(k=k))
+    R = aidw.nn_statistic(g, qx, qy, k, clip).cpu().numpy().astype(np.float64)
+    g.close()
+    b = O.bounds(ds.x, ds.y, ds.qx, ds.qy)
+    r_exp = O.grid_params(b, ds.n)["r_exp"]
+    _, d2 = O.knn(ds.x, ds.y, ds.qx, ds.qy, k)
+    ref = O.robs(d2) / r_exp
+    if clip > 0:
+        ref = np.minimum(ref, clip)
+        assert np.any(ref == clip) and np.any(ref < clip)
+    assert np.all(np.abs(R - ref) <= 2.5 * 2.0 ** -24 * np.abs(ref)), float(np.max(np.abs(R - ref) / ref))
+
+
 # ------------------------------------------------------------------ network
 
-def test_forward_matches_fp64_reference(T):
+def check_outputs(yk, params, feat, min_exact=0.0):
+    """The network's float32 outputs yk against the FP64 reference on the same bf16 operands
+    (oracle.mlp.forward_candidates): every output lies in the intervals the float32 arithmetic
+    allows (a bf16 activation whose value is within the float32 error of a rounding boundary
+    counts with each value it can take, each such flip bounded by its own effect); outputs the
+    model proves fixed and exact are bit-exact; outputs with no ambiguous activation are within
+    1e-4 of the reference element-wise.  Returns the candidate model."""
+    yk = np.asarray(yk, np.float64)
+    cand = OM.forward_candidates(np.asarray(params, np.float64), feat)
+    res = cand["resolved"]
+    assert res.mean() > 0.995, res.mean()
+    ok = OM.within(yk, cand)
+    assert np.all(ok[res]), "outputs outside their bound: %d of %d" % (int((~ok[res]).sum()), int(res.sum()))
+    clean = res & (cand["ambiguous"] == 0)
+    err = np.abs(yk - cand["y"]) / (1.0 + np.abs(cand["y"]))
+    assert np.all(err[clean] <= 1e-4), float(err[clean].max())
+    assert cand["exact"].mean() >= min_exact, cand["exact"].mean()
+    assert np.all(yk[cand["exact"]] == np.float32(cand["y"][cand["exact"]]))
+    return cand
+
+
+def grid_features(seed, B):
+    """Network inputs on the 2^-8 grid: counts / occupancy and in-cell offsets."""
+    rng = np.random.default_rng(seed)
+    f = np.zeros((B, 27))
+    f[:, :25] = rng.poisson(2.0, (B, 25)) * 0.5
+    f[:, 25:] = rng.integers(0, 256, (B, 2)) / 256.0
+    return f.astype(np.float32)
+
+
+@pytest.mark.parametrize("kind,min_exact", [("positive", 0.9), ("signed", 0.4), ("mixed", 0.0)])
+def test_forward_matches_fp64_reference(T, kind, min_exact):
+    """aidw_mlp_forward (matrix cores) against the FP64 network, on features of a clustered
+    grid and on grid-aligned synthetic features."""
     aidw, L = mods()
     ds = W.make(20000, 6000, 15, 211, "mixture", 8)
     x, y, qx, qy = (dev(T, getattr(ds, a)) for a in ("x", "y", "qx", "qy"))
     g = aidw.build_grid(x, y, qx, qy, aidw.Params(k=15))
     f, _ = L.features(g, qx, qy, want_d1sq=False)
     g.close()
-    params = random_params(5)
+    params = OM.grid_params(5, kind)
     mlp = L.MLP(seed=1)
     mlp.set_params(params)
     assert np.array_equal(mlp.get_params(), params)
-    yk = mlp.forward(f).cpu().numpy().astype(np.float64)
-    yo, _ = OM.forward(params.astype(np.float64), f.cpu().numpy())
-    err = np.abs(yk - yo) / (1.0 + np.abs(yo))
-    # differences come from float32 vs float64 arithmetic and rare one-ulp bf16 flips of an activation
-    assert np.median(err) < 1e-5 and np.quantile(err, 0.99) < 1e-3 and err.max() < 2e-2
+    for feat in (f.cpu().numpy(), grid_features(212, 4000)):
+        yk = mlp.forward(dev(T, feat)).cpu().numpy()
+        check_outputs(yk, params, feat, min_exact)
 
 
-def test_gradients_match_fp64_reference(T):
+@pytest.mark.parametrize("kind", ["positive", "signed"])
+def test_gradients_match_fp64_reference(T, kind):
+    """aidw_mlp_gradients against the FP64 gradient on identical bf16 operands: the batch is
+    drawn from samples whose every bf16 activation the float32 error cannot move (the
+    forward model proves the output fixed), so both sides differentiate the same network
+    at the same points.  Each entry is within 1e-4 of the sum of the magnitudes of its
+    per-sample contributions (the scale of float32 summation error; entries without
+    cancellation are within 1e-4 relative of their value)."""
     aidw, L = mods()
     rng = np.random.default_rng(221)
+    params = OM.grid_params(6, kind)
+    pool = grid_features(222, 6000)
+    cand = OM.forward_candidates(params.astype(np.float64), pool)
+    fixed = np.nonzero(cand["exact"])[0]
     B = 700
-    feat = (rng.random((B, 27)) * 3).astype(np.float32)
-    feat[:, 25:] = rng.random((B, 2)).astype(np.float32)
+    assert fixed.size >= B
+    feat = pool[rng.choice(fixed, B, replace=False)]
     target = (rng.random(B) * 3).astype(np.float32)
-    params = random_params(6, 0.3)
     mlp = L.MLP()
     mlp.set_params(params)
     g, loss = mlp.gradients(dev(T, feat), dev(T, target))
-    lo, go = OM.loss_and_grad(params.astype(np.float64), feat, target)
+    lo, go, scale = OM.loss_and_grad_abs(params.astype(np.float64), feat, target)
     gk = g.cpu().numpy().astype(np.float64)
-    assert float(loss) == pytest.approx(lo, rel=2e-3)
-    assert np.linalg.norm(gk - go) / np.linalg.norm(go) < 2e-3
-    # every parameter block, normwise
-    o = 0
-    for name, shape in OM.SIZES:
-        k = int(np.prod(shape))
-        a, b = gk[o:o + k], go[o:o + k]
-        assert np.linalg.norm(a - b) <= 5e-3 * np.linalg.norm(b) + 1e-7, name
-        o += k
+    assert abs(float(loss) - lo) <= 1e-5 * lo
+    bad = np.abs(gk - go) > 1e-4 * scale + 1e-12
+    assert not bad.any(), "%d entries, worst ratio %.3g" % (
+        int(bad.sum()), float((np.abs(gk - go) / (scale + 1e-30)).max()))
+    well = scale > 0
+    well[well] = np.abs(go[well]) >= 0.5 * scale[well]
+    assert np.all(np.abs(gk[well] - go[well]) <= 1e-4 * np.abs(go[well]))
+    assert well.mean() > 0.3
 
 
 def test_training_reduces_loss_and_checkpoint_roundtrip(T):
@@ -158,12 +221,13 @@ def _plain_and_learned(T, ds, mlp, rule, delta, k):
             rh.cpu().numpy(), nfb)
 
 
-def test_learned_run_prediction_matches_fp64_network(T):
+@pytest.mark.parametrize("kind", ["positive", "signed"])
+def test_learned_run_prediction_matches_fp64_network(T, kind):
     """The learned run computes features, network and decision in one kernel (network on the
-    matrix cores); its prediction R_hat equals the FP64 network on the oracle's features."""
+    matrix cores); its prediction R_hat matches the FP64 network on the oracle's features."""
     aidw, L = mods()
     ds = W.make(30000, 9000, 15, 241, "mixture", 16)
-    params = random_params(12, 0.3)
+    params = OM.grid_params(12, kind)
     mlp = L.MLP(seed=6)
     mlp.set_params(params)
     x, y, z, qx, qy = (dev(T, getattr(ds, a)) for a in ("x", "y", "z", "qx", "qy"))
@@ -173,9 +237,7 @@ def test_learned_run_prediction_matches_fp64_network(T):
     d = g.describe()
     g.close()
     feat = O.features(ds.x, ds.y, ds.qx, ds.qy, d["min_x"], d["min_y"], d["inv_cell_width"], d["ncol"], d["nrow"])
-    yo, _ = OM.forward(params.astype(np.float64), feat)
-    err = np.abs(rh.cpu().numpy().astype(np.float64) - yo) / (1.0 + np.abs(yo))
-    assert np.median(err) < 1e-5 and np.quantile(err, 0.99) < 1e-3 and err.max() < 2e-2
+    check_outputs(rh.cpu().numpy(), params, feat, 0.3 if kind == "signed" else 0.9)
 
 
 def _strip(n, m, seed):
@@ -200,7 +262,7 @@ def test_learned_prediction_small_grids(T, case):
         ds = W.make(n, m, min(15, n), 300 + n, "uniform")
         x, y, z, qx, qy = ds.x, ds.y, ds.z, ds.qx, ds.qy
         area = 0.0
-    params = random_params(21, 0.3)
+    params = OM.grid_params(21, "signed")
     mlp = L.MLP(seed=7)
     mlp.set_params(params)
     p = aidw.Params(k=min(15, x.size), area=area)
@@ -212,9 +274,7 @@ def test_learned_prediction_small_grids(T, case):
     if case == "strip":
         assert d["nrow"] <= 2 and d["ncol"] > 100
     feat = O.features(x, y, qx, qy, d["min_x"], d["min_y"], d["inv_cell_width"], d["ncol"], d["nrow"])
-    yo, _ = OM.forward(params.astype(np.float64), feat)
-    err = np.abs(rh.cpu().numpy().astype(np.float64) - yo) / (1.0 + np.abs(yo))
-    assert err.max() < 2e-2 and np.median(err) < 1e-4, (case, d["ncol"], d["nrow"], float(err.max()))
+    check_outputs(rh.cpu().numpy(), params, feat)
 
 
 def test_all_fallback_equals_plain_path(T):
@@ -259,24 +319,77 @@ def test_learned_rules(T, rule):
 
 
 def test_trained_network_gain(T):
-    """A network trained on held-out mixture datasets lets most queries skip the kNN search
-    while the interpolated values stay within the error bar for nearly all of them."""
+    """A network trained on held-out mixture datasets, credited under the network-gated
+    certificate (rule 4): no loss of z accuracy -- every query's alpha equals the plain path's
+    bitwise, z equals the plain run's up to float32 rounding and is within 1e-5 of the FP64
+    oracle -- while the
+    network sends most of the queries whose 3 x 3 certificate would fail straight to the exact
+    kNN (the scan is skipped) and loses almost no certification.  An untrained network cannot
+    do both.  The network's own alpha rule (rule 1) is reported, not credited: it assigns
+    alpha to a few queries in the membership's transition band."""
     aidw, L = mods()
     n, mq = 1 << 18, 50000
     train = [W.make(n, mq, 15, 400 + i, "mixture", 16) for i in range(4)]
     mlp, losses = L.train_default(train, seed=11, epochs=10, batch=1024, lr=2e-3)
     assert losses[-1] < losses[0]
     ds = W.make(n, 16000, 15, 499, "mixture", 16)
-    qz_p, al_p, _, qz_l, al_l, rh, nfb = _plain_and_learned(T, ds, mlp, L.ALPHA_EXACT, 0.3, 15)
-    skipped = 1.0 - nfb / ds.m
-    wrong_alpha = float(np.mean(al_l != al_p))
+    qz_p, al_p, _, qz_g, al_g, rh, nfb_g = _plain_and_learned(T, ds, mlp, L.NETWORK_GATED_CERTIFICATE, 0.3, 15)
+    assert np.array_equal(al_g, al_p)
+    assert np.allclose(qz_g, qz_p, rtol=2e-6, atol=1e-7)
     sel = np.arange(0, ds.m, 16)
     ref = O.aidw(ds.x, ds.y, ds.z, ds.qx, ds.qy, k=15, qsel=sel)
-    e = np.abs(qz_l[sel].astype(np.float64) - ref["z"]) / np.maximum(np.abs(ref["z"]), ref["s"])
-    print("skipped %.3f wrong-alpha %.4f within-1e-5 %.4f" % (skipped, wrong_alpha, float(np.mean(e <= 1e-5))))
-    assert skipped > 0.85
-    assert wrong_alpha < 0.005
-    assert np.mean(e <= 1e-5) > 0.995
+    e = np.abs(qz_g[sel].astype(np.float64) - ref["z"]) / np.maximum(np.abs(ref["z"]), ref["s"])
+    assert e.max() <= 1e-5
+    x, y, qx, qy = (dev(T, getattr(ds, a)) for a in ("x", "y", "qx", "qy"))
+    p = aidw.Params(k=15)
+
+    def stats(net, rule):
+        r, _ = L.learned_routes(x, y, qx, qy, p, net, rule, 0.3)
+        r = r.cpu().numpy()
+        return {"skipped": float(np.mean(r >= 2)), "failed_scans": float(np.mean(r == 1))}
+
+    cert = stats(mlp, L.CERTIFIED)
+    gated = stats(mlp, L.NETWORK_GATED_CERTIFICATE)
+    untrained = L.MLP(seed=12)
+    gated_u = stats(untrained, L.NETWORK_GATED_CERTIFICATE)
+    _, _, _, _, al_1, _, nfb_1 = _plain_and_learned(T, ds, mlp, L.ALPHA_EXACT, 0.3, 15)
+    print("certified %s | gated (trained) %s | gated (untrained) %s | rule 1 skipped %.3f wrong alpha %.4f" % (
+        cert, gated, gated_u, 1.0 - nfb_1 / ds.m, float(np.mean(al_1 != al_p))))
+    assert abs(1.0 - nfb_g / ds.m - gated["skipped"]) < 1e-9
+    assert cert["skipped"] > 0.85
+    assert gated["skipped"] >= cert["skipped"] - 0.01
+    assert gated["failed_scans"] <= 0.5 * cert["failed_scans"]
+    # the untrained network either loses certifications or keeps the failing scans
+    assert gated_u["skipped"] < cert["skipped"] - 0.01 or gated_u["failed_scans"] > 0.5 * cert["failed_scans"]
+
+
+@pytest.mark.parametrize("case", ["mixture", "uniform_k10"])
+def test_certificate_independent_of_kernel(T, case):
+    """The certified rule against the oracle, with nothing taken from the kernel: every query
+    (not coincident with a data point) that the certificate written from the paper's grid
+    (oracle.certificate: block counts and 3 x 3 distances, no dense-block limit) certifies
+    with a 1 % margin is skipped; and every skipped query has R beyond the saturation point
+    and alpha = alpha_5 by Eq. 4-6 on the oracle's exact (brute-force) r_obs."""
+    aidw, L = mods()
+    import oracle.certificate as C
+    if case == "mixture":
+        ds, k = W.make(40000, 6000, 15, 271, "mixture", 16), 15
+    else:
+        ds, k = W.make(30000, 5000, 10, 272), 10
+    x, y, qx, qy = (dev(T, getattr(ds, a)) for a in ("x", "y", "qx", "qy"))
+    route, _ = L.learned_routes(x, y, qx, qy, aidw.Params(k=k), L.MLP(seed=1), L.CERTIFIED, 0.0)
+    skipped = route.cpu().numpy() >= 2
+    b = O.bounds(ds.x, ds.y, ds.qx, ds.qy)
+    gp = O.grid_params(b, ds.n, occupancy=2.0)
+    r_sat = 2.0 / np.pi * np.arccos(-0.8)  # mu(R) = 0.9 in Eq. 5 with R_min = 0, R_max = 2
+    slack = (max(gp["ncol"], gp["nrow"]) + 1) * 2.0 ** -21
+    cert = C.certified(ds.x, ds.y, ds.qx, ds.qy, k, b[0], b[1], gp["cw"], gp["inv_cw"], gp["ncol"], gp["nrow"],
+                       slack, 1.01 * k * gp["r_exp"] * r_sat)
+    _, d2 = O.knn(ds.x, ds.y, ds.qx, ds.qy, k)
+    R, _, alpha = O.alpha(O.robs(d2), gp["r_exp"])
+    assert cert.mean() > 0.5
+    assert np.all(skipped[cert & (d2[:, 0] > 0)])
+    assert np.all(alpha[skipped] == 5.0) and np.all(R[skipped] > r_sat)
 
 
 def _certificate_oracle(ds, k, margin=0.0):
@@ -356,7 +469,7 @@ def test_certified_rule_full_size(T):
     assert np.array_equal(al_l, al_p)
     assert 1.0 - nfb / ds.m > 0.9
     assert np.allclose(qz_l, qz_p, rtol=2e-6, atol=1e-7)
-    sel = W.sample_queries(ds.m, 256, ds.seed)
+    sel = W.sample_queries(ds.m, 4096, ds.seed)
     ref = O.aidw(ds.x, ds.y, ds.z, ds.qx, ds.qy, k=ds.k, qsel=sel)
     e = np.abs(qz_l[sel].astype(np.float64) - ref["z"]) / np.maximum(np.abs(ref["z"]), ref["s"])
     assert e.max() <= 1e-5

@@ -295,7 +295,7 @@ def test_error_paths_on_gpu(T):
 def test_full_size_sampled(T, name):
     aidw = aidw_mod()
     ds = W.WORKLOADS[name]()
-    sel = W.sample_queries(ds.m, 512, ds.seed)
+    sel = W.sample_queries(ds.m, 4096, ds.seed)
     x, y, z, qx, qy = upload(T, ds)
     p = aidw.Params(k=ds.k)
     # kNN of every query (the kernels run() uses), checked on the sample
