@@ -263,13 +263,17 @@ def parse():
 
 
 ISSUE_KINDS = ["fma (v_fma_f32)", "fmac (v_fmac_f32)", "exp2", "log2", "rsq", "rsq+9fmac", "log2+exp2+7fmac",
-               "pair loop alpha=5 (cached data)"]
+               "pair loop alpha=5 (cached data)", "mul (v_mul_f32)", "add (v_add_f32)",
+               "pair VALU mix (4 fma-type + 5 mul/add)"]
 
 
 def issue_rates(args):
-    """The VALU / transcendental issue-rate microbenchmark: lanes issued per clock per CU for a
-    stream of float32 FMAs, of each transcendental, and of the two mixes of the pair loop (one rsq
-    per 9 FMAs, log2 + exp2 per 7 FMAs), against the serial (no-overlap) and overlapped models."""
+    """The VALU / transcendental issue-rate microbenchmark: lanes issued per clock per CU for
+    streams of one float32 instruction kind (fma, fmac, mul, add, each transcendental), for the
+    nine VALU operations of the integer-alpha pair without its rsq, for the two mixes of a
+    transcendental with FMAs, and for the pair loop itself over cached data.  From these: the
+    VALU rate of the pair's own instruction mix, the transcendental rate, whether the two
+    overlap, and the ceiling they set for one alpha = 5 pair (9 VALU + 1 rsq, serial issue)."""
     import ctypes
     lib = ctypes.CDLL(os.path.join(ROOT, "paper_1601_05904_amd", "libaidw_ubench.so"))
     lib.aidw_ubench_issue_rate.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_float),
@@ -299,24 +303,38 @@ def issue_rates(args):
                       "valu_lanes_per_clk_cu_nominal": lanes * v.value / (sec * CLOCK * CUS),
                       "trans_lanes_per_clk_cu_nominal": lanes * t.value / (sec * CLOCK * CUS)}
         print(json.dumps({"issue_rate": name, "ms": ms.value, "clock_GHz": clk / 1e9}), file=sys.stderr, flush=True)
-    valu = max(rows[k]["valu_lanes_per_clk_cu"] for k in ("fma (v_fma_f32)", "fmac (v_fmac_f32)"))
-    trans = min(rows[k]["trans_lanes_per_clk_cu"] for k in ("exp2", "log2", "rsq"))
+
+    def best(keys, field):
+        return max(rows[k][field] for k in keys)
+
+    fma_only = best(("fma (v_fma_f32)", "fmac (v_fmac_f32)"), "valu_lanes_per_clk_cu_nominal")
+    mul_add = best(("mul (v_mul_f32)", "add (v_add_f32)"), "valu_lanes_per_clk_cu_nominal")
+    mix = rows["pair VALU mix (4 fma-type + 5 mul/add)"]["valu_lanes_per_clk_cu_nominal"]
+    trans = min(rows[k]["trans_lanes_per_clk_cu_nominal"] for k in ("exp2", "log2", "rsq"))
     pl = rows["pair loop alpha=5 (cached data)"]
     pl["pairs_per_clk_cu"] = pl["trans_lanes_per_clk_cu"]  # one transcendental per pair
     pl["pairs_per_s_at_2.4GHz"] = pl["trans_lanes_per_clk_cu_nominal"] * CUS * CLOCK
-    for name in ("rsq+9fmac", "log2+exp2+7fmac"):
+    for name, fma_share in (("rsq+9fmac", 1.0), ("log2+exp2+7fmac", 1.0)):
         r = rows[name]
-        steps_per_clk = r["valu_lanes_per_clk_cu"] / r["valu_per_lane"]  # mixed steps per clk per CU
-        serial = 1.0 / (r["valu_per_lane"] / valu + r["trans_per_lane"] / trans)
-        overlap = 1.0 / max(r["valu_per_lane"] / valu, r["trans_per_lane"] / trans)
-        r["steps_per_clk_cu"] = steps_per_clk
+        steps = r["valu_lanes_per_clk_cu_nominal"] / r["valu_per_lane"]  # mixed steps per clk per CU
+        serial = 1.0 / (r["valu_per_lane"] / fma_only + r["trans_per_lane"] / trans)
+        overlap = 1.0 / max(r["valu_per_lane"] / fma_only, r["trans_per_lane"] / trans)
+        r["steps_per_clk_cu_nominal"] = steps
         r["serial_model_steps_per_clk_cu"] = serial
         r["overlap_model_steps_per_clk_cu"] = overlap
-        r["frac_of_serial_model"] = steps_per_clk / serial
-    return {"issue_rates": rows, "valu_lanes_per_clk_cu": valu, "trans_lanes_per_clk_cu": trans,
-            "note": "lanes per clock per CU at the clock the chip held (s_memtime / s_memrealtime); the "
-                    "*_nominal figures use 2.4 GHz.  A mixed stream at <= 1.0 of the serial model means "
-                    "transcendentals and FMAs do not overlap."}
+        r["frac_of_serial_model"] = steps / serial
+    ceiling = 1.0 / (9.0 / mix + 1.0 / trans)  # alpha = 5 pairs per clk per CU, serial issue
+    return {"issue_rates": rows,
+            "valu_lanes_per_clk_cu_fma_only": fma_only, "valu_lanes_per_clk_cu_mul_add": mul_add,
+            "valu_lanes_per_clk_cu_pair_mix": mix, "trans_lanes_per_clk_cu": trans,
+            "alpha5_pair_ceiling": {"pairs_per_clk_cu": ceiling, "pairs_per_s_at_2.4GHz": ceiling * CUS * CLOCK,
+                                    "model": "9 VALU at the pair mix's rate + 1 rsq at the transcendental rate, "
+                                             "no overlap"},
+            "published_model": {"valu_lanes_per_clk_cu": VALU_PER_CLK_CU, "trans_lanes_per_clk_cu": TRANS_PER_CLK_CU,
+                                "alpha5_pairs_per_s": pair_peak(9, 1)},
+            "note": "rates per clock per CU, *_nominal at 2.4 GHz (the launch's wall time over 2.4e9 clocks); "
+                    "clock_GHz is block 0's s_memtime / s_memrealtime.  A mixed stream at <= 1.0 of the serial "
+                    "model means transcendentals and VALU operations do not overlap."}
 
 
 def copy_calibration(mb):

@@ -93,8 +93,8 @@ constexpr int kRadixMax = 1 << kRadixBitsWide;
 // band (2^band_shift consecutive cells, at most kMaxBands bands per point set), then, per
 // band, a stable counting sort by cell inside the band.  Limits: at most kMaxBands bands of at
 // most 2^kMaxBandShift cells, i.e. kBandMaxCells cells.
-constexpr int kMaxBands = 512;
-constexpr int kMaxBandShift = 13;
+constexpr int kMaxBands = 1024;
+constexpr int kMaxBandShift = 12;
 constexpr int64_t kBandMaxCells = (int64_t)kMaxBands << kMaxBandShift;
 struct BandScratch {
   BoundsPartial* partial;  // [kBoundsBlocks]

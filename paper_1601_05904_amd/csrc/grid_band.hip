@@ -36,7 +36,7 @@ constexpr int kItems = 8;
 constexpr int kTile = kThreads * kItems;  // points per block of k_band_hist / k_band_scatter
 constexpr int kWaves = kThreads / 64;
 constexpr int kDigits = 2 * kMaxBands;    // data bands, then query bands
-constexpr int kDigitBits = 10;            // kDigits = 2^kDigitBits
+constexpr int kDigitBits = 11;            // kDigits = 2^kDigitBits
 static_assert(kDigits == 1 << kDigitBits, "digit count");
 constexpr int kLocalThreads = 256;        // k_band_local
 constexpr int kLocalItems = 16;
@@ -69,7 +69,7 @@ __host__ __device__ inline int ceil_log2(int64_t v) {
 // Bands of a grid: at most kMaxBands of 2^shift cells each.
 __host__ __device__ inline int shift_for_cells(int64_t ncells) {
   const int bits = ceil_log2(ncells);
-  return bits > 9 ? bits - 9 : 0;
+  return bits > 10 ? bits - 10 : 0;
 }
 __device__ inline void set_bands(GridScalars& g) {
   const int shift = shift_for_cells(g.ncells);
@@ -328,11 +328,23 @@ __global__ __launch_bounds__(kThreads) void k_band_scatter(const GridScalars* __
 }
 
 // One block per digit: the stable counting sort of the digit's segment by cell inside its
-// band.  Segments of at most kLocalTile points are loaded once into registers, sorted into
-// LDS and written out in order; longer ones (dense bands) are counted in one pass and placed
-// in batches of kLocalTile, written directly.  Dynamic LDS: cnt [CB] (counts, then the
-// running cursor), wcnt [kLocalWaves][CB] bytes, the staged tile (index, x, y) [kLocalTile],
-// CB = the largest band the host sized for.
+// band.  The cells' counts (LDS atomics) and their exclusive scan give the CSR offsets, which
+// data blocks write (head of cell c = cell_start[c], size = cell_start[c + 1] - cell_start[c],
+// Section 3.2.3).  Two ways to order the points inside each cell by index:
+//   rank path    (the segment fits the LDS tile and no cell of the band holds more than
+//                kRankMaxCell points): every point takes a slot of its cell by an LDS atomic,
+//                then its place in the cell is the number of the cell's points with a smaller
+//                index; the sorted tile is written out in one coalesced pass.
+//   ballot path  (otherwise): the segment, which the stable scatter left in index order, is
+//                ranked in rounds of kLocalThreads points by wavefront ballots on the local
+//                cell key, earlier rounds counted by a running cursor per cell; a segment that
+//                fits the tile is sorted in LDS and written out, a longer one (a dense band) is
+//                written directly.
+// Query blocks write the queries in cell order (and their coordinates).  Dynamic LDS: cnt [CB]
+// (counts, then offsets / cursors), then a region used either by the rank path (slot indices,
+// sorted index, x, y [kLocalTile] each) or by the ballot path (wcnt [kLocalWaves][CB] bytes,
+// then the staged index, x, y [kLocalTile] each); CB = the largest band the host sized for.
+constexpr int kRankMaxCell = 64;
 __global__ __launch_bounds__(kLocalThreads) void k_band_local(const GridScalars* __restrict__ gs, int64_t n,
                                                               int cb_max, const uint32_t* __restrict__ dstart,
                                                               const uint32_t* __restrict__ bidx,
@@ -344,6 +356,7 @@ __global__ __launch_bounds__(kLocalThreads) void k_band_local(const GridScalars*
                                                               uint32_t* __restrict__ qorder, float* __restrict__ qsx,
                                                               float* __restrict__ qsy) {
   extern __shared__ uint32_t lds[];
+  __shared__ uint32_t s_max;  // the largest cell count of the band
   const GridScalars g = *gs;
   const int nb = g.nbands;
   const int d = blockIdx.x;
@@ -355,8 +368,15 @@ __global__ __launch_bounds__(kLocalThreads) void k_band_local(const GridScalars*
   const uint32_t cell0 = (uint32_t)band << shift;
   const int ncb = (int)(g.ncells - (int64_t)cell0 < cb ? g.ncells - (int64_t)cell0 : cb);
   uint32_t* cnt = lds;
-  uint8_t* wcnt = reinterpret_cast<uint8_t*>(lds + cb_max);  // [kLocalWaves][cb]
-  uint32_t* t_idx = lds + cb_max + kLocalWaves * cb_max / 4;
+  uint32_t* region = lds + cb_max;
+  // rank path
+  uint32_t* r_slot = region;
+  uint32_t* r_idx = region + kLocalTile;
+  float* r_x = reinterpret_cast<float*>(region + 2 * kLocalTile);
+  float* r_y = reinterpret_cast<float*>(region + 3 * kLocalTile);
+  // ballot path
+  uint8_t* wcnt = reinterpret_cast<uint8_t*>(region);  // [kLocalWaves][cb]
+  uint32_t* t_idx = region + kLocalWaves * cb_max / 4;
   float* t_x = reinterpret_cast<float*>(t_idx + kLocalTile);
   float* t_y = t_x + kLocalTile;
   const uint32_t s = dstart[d], e = dstart[d + 1];
@@ -366,7 +386,7 @@ __global__ __launch_bounds__(kLocalThreads) void k_band_local(const GridScalars*
   const uint64_t lt_mask = lane == 0 ? 0ull : (~0ull >> (64 - lane));
 
   for (int i = tid; i < cb; i += kLocalThreads) cnt[i] = 0u;
-  for (int i = tid; i < kLocalWaves * cb / 4; i += kLocalThreads) reinterpret_cast<uint32_t*>(wcnt)[i] = 0u;
+  if (tid == 0) s_max = 0u;
   // a staged segment stays in registers: (local cell, index, x, y) per item
   uint32_t lk[kLocalItems], id[kLocalItems];
   float px[kLocalItems], py[kLocalItems];
@@ -394,6 +414,11 @@ __global__ __launch_bounds__(kLocalThreads) void k_band_local(const GridScalars*
     for (uint32_t p = s + tid; p < e; p += kLocalThreads) atomicAdd(&cnt[cell_of(bx[p], by[p], g) - cell0], 1u);
   }
   __syncthreads();
+  if (staged) {
+    uint32_t mx = 0u;
+    for (int i = tid; i < cb; i += kLocalThreads) mx = max(mx, cnt[i]);
+    if (mx > 0u) atomicMax(&s_max, mx);
+  }
   // exclusive scan of the band's counts; a data band writes its cells' offsets
   uint32_t carry = 0;
   for (int c0 = 0; c0 < cb; c0 += kLocalThreads * 4) {
@@ -420,6 +445,50 @@ __global__ __launch_bounds__(kLocalThreads) void k_band_local(const GridScalars*
   }
   if (!query && band == nb - 1 && tid == 0) cell_start[g.ncells] = (int32_t)e;
   __syncthreads();
+  // writes the sorted point at segment position i (staged in LDS, or direct)
+  auto emit = [&](uint32_t i, uint32_t pid, float fx, float fy) {
+    if (!query) {
+      sidx[s + i] = (int32_t)pid;
+      sx[s + i] = fx;
+      sy[s + i] = fy;
+    } else {
+      const uint32_t qp = s + i - (uint32_t)n;
+      qorder[qp] = pid;
+      if (qsx) {
+        qsx[qp] = fx;
+        qsy[qp] = fy;
+      }
+    }
+  };
+  if (staged && s_max <= (uint32_t)kRankMaxCell) {
+    // rank path: a slot of the point's cell, then its place among the cell's points by index
+    uint32_t slot[kLocalItems];
+#pragma unroll
+    for (int it = 0; it < kLocalItems; ++it)
+      if (lk[it] != 0xffffffffu) {
+        slot[it] = atomicAdd(&cnt[lk[it]], 1u);
+        r_slot[slot[it]] = id[it];
+      }
+    __syncthreads();
+    // cnt[c] is now the end of cell c, which is the start of cell c + 1
+#pragma unroll
+    for (int it = 0; it < kLocalItems; ++it)
+      if (lk[it] != 0xffffffffu) {
+        const uint32_t c = lk[it];
+        const uint32_t c_end = cnt[c], c_begin = c == 0 ? 0u : cnt[c - 1];
+        uint32_t pos = c_begin;
+        for (uint32_t j = c_begin; j < c_end; ++j) pos += r_slot[j] < id[it] ? 1u : 0u;
+        r_idx[pos] = id[it];
+        r_x[pos] = px[it];
+        r_y[pos] = py[it];
+      }
+    __syncthreads();
+    for (uint32_t i = tid; i < size; i += kLocalThreads) emit(i, r_idx[i], r_x[i], r_y[i]);
+    return;
+  }
+  // ballot path
+  for (int i = tid; i < kLocalWaves * cb / 4; i += kLocalThreads) reinterpret_cast<uint32_t*>(wcnt)[i] = 0u;
+  __syncthreads();
   // one ranking round: the point of this thread (valid, local cell key, index, x, y) goes to
   // position cur[key] + (earlier waves' and lanes' points of the same key) of the segment
   auto round = [&](bool valid, uint32_t key, uint32_t pid, float fx, float fy) {
@@ -437,17 +506,8 @@ __global__ __launch_bounds__(kLocalThreads) void k_band_local(const GridScalars*
         t_idx[pos] = pid;
         t_x[pos] = fx;
         t_y[pos] = fy;
-      } else if (!query) {
-        sidx[s + pos] = (int32_t)pid;
-        sx[s + pos] = fx;
-        sy[s + pos] = fy;
       } else {
-        const uint32_t qp = s + pos - (uint32_t)n;
-        qorder[qp] = pid;
-        if (qsx) {
-          qsx[qp] = fx;
-          qsy[qp] = fy;
-        }
+        emit(pos, pid, fx, fy);
       }
     }
     __syncthreads();
@@ -461,20 +521,7 @@ __global__ __launch_bounds__(kLocalThreads) void k_band_local(const GridScalars*
     for (int it = 0; it < kLocalItems; ++it)
       round(lk[it] != 0xffffffffu, lk[it] == 0xffffffffu ? 0u : lk[it], id[it], px[it], py[it]);
     __syncthreads();
-    for (uint32_t i = tid; i < size; i += kLocalThreads) {
-      if (!query) {
-        sidx[s + i] = (int32_t)t_idx[i];
-        sx[s + i] = t_x[i];
-        sy[s + i] = t_y[i];
-      } else {
-        const uint32_t qp = s + i - (uint32_t)n;
-        qorder[qp] = t_idx[i];
-        if (qsx) {
-          qsx[qp] = t_x[i];
-          qsy[qp] = t_y[i];
-        }
-      }
-    }
+    for (uint32_t i = tid; i < size; i += kLocalThreads) emit(i, t_idx[i], t_x[i], t_y[i]);
   } else {
     for (uint32_t r0 = s; r0 < e; r0 += kLocalThreads) {
       const uint32_t p = r0 + tid;
@@ -496,7 +543,9 @@ inline int div_up(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
 
 // Dynamic LDS of k_band_local for bands of at most cb cells.
 size_t local_lds_bytes(int cb) {
-  return sizeof(uint32_t) * (size_t)cb + (size_t)kLocalWaves * cb + (sizeof(uint32_t) + 2 * sizeof(float)) * kLocalTile;
+  const size_t rank = 4 * sizeof(uint32_t) * (size_t)kLocalTile;
+  const size_t ballot = (size_t)kLocalWaves * cb + (sizeof(uint32_t) + 2 * sizeof(float)) * kLocalTile;
+  return sizeof(uint32_t) * (size_t)cb + (rank > ballot ? rank : ballot);
 }
 
 }  // namespace

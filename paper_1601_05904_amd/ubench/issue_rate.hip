@@ -15,6 +15,11 @@
 //   4 rsq    a = rsq(a)                              (1 v_rsq_f32; fixed point 1)
 //   5 mix5   r = rsq(a); 9 fmac on r                 (the integer-alpha pair's mix: 9 VALU + 1)
 //   6 mixg   log2, exp2; 7 fmac                      (the general pair's mix: 7 VALU + 2)
+//   8 mul    a = a * v                               (v_mul_f32)
+//   9 add    a = a + v                               (v_add_f32)
+//  10 pairv  the nine VALU operations of the integer-alpha pair without its rsq: 2 fma for
+//            the offsets, mul + fma for d^2, 3 mul for the power, fma + add for the sums
+//            (4 fma-type + 5 mul / add), chained through a
 // and kind 7 runs the interpolation kernel's own pair loop (alpha = 5, one query per lane,
 // data points streamed through the scalar cache) over a 512-point array that stays in
 // that cache: the kernel's instruction stream without its memory traffic.
@@ -47,11 +52,21 @@ __device__ __forceinline__ float step(float a, float m, float c) {
 #pragma unroll
     for (int i = 0; i < 9; ++i) r = __builtin_fmaf(m, c, r);
     return r;
-  } else {
+  } else if constexpr (KIND == 6) {
     float r = __builtin_amdgcn_exp2f(__builtin_amdgcn_logf(a));
 #pragma unroll
     for (int i = 0; i < 7; ++i) r = __builtin_fmaf(m, c, r);
     return r;
+  } else if constexpr (KIND == 8) {
+    return a * c;
+  } else if constexpr (KIND == 9) {
+    return a + c;
+  } else {
+    const float dx = __builtin_fmaf(m, c, a);
+    const float dy = __builtin_fmaf(a, m, c);
+    const float t = __builtin_fmaf(dx, dx, dy * dy);
+    const float t2 = t * t, t4 = t2 * t2, w = t4 * t;
+    return __builtin_fmaf(w, m, a) + w;
   }
 }
 
@@ -133,8 +148,8 @@ extern "C" {
 // pair count per round (kPairPoints) with the per-pair minimum of the alpha = 5 form
 // (9 VALU + 1 transcendental).
 int aidw_ubench_counts(int kind, int* valu, int* trans) {
-  static const int v[7] = {1, 1, 0, 0, 0, 9, 7}, t[7] = {0, 0, 1, 1, 1, 1, 2};
-  if (kind < 0 || kind > 7 || !valu || !trans) return -1;
+  static const int v[11] = {1, 1, 0, 0, 0, 9, 7, 0, 1, 1, 9}, t[11] = {0, 0, 1, 1, 1, 1, 2, 0, 0, 0, 0};
+  if (kind < 0 || kind > 10 || !valu || !trans) return -1;
   if (kind == 7) {
     *valu = 9 * kPairPoints;
     *trans = kPairPoints;
@@ -150,7 +165,7 @@ int aidw_ubench_counts(int kind, int* valu, int* trans) {
 // launch; shader_ticks / real_ticks = the two clocks over block 0's loop.  Returns 0 or the
 // HIP error code.
 int aidw_ubench_issue_rate(int kind, int iters, int blocks, float* ms, uint64_t* shader_ticks, uint64_t* real_ticks) {
-  if (kind < 0 || kind > 7 || iters < 1 || blocks < 1 || !ms) return -1;
+  if (kind < 0 || kind > 10 || iters < 1 || blocks < 1 || !ms) return -1;
   float* out = nullptr;
   uint64_t* clk = nullptr;
   float* pts = nullptr;
@@ -176,6 +191,9 @@ int aidw_ubench_issue_rate(int kind, int iters, int blocks, float* ms, uint64_t*
       case 4: return run<4>(it, blocks, out, clk, nullptr);
       case 5: return run<5>(it, blocks, out, clk, nullptr);
       case 6: return run<6>(it, blocks, out, clk, nullptr);
+      case 8: return run<8>(it, blocks, out, clk, nullptr);
+      case 9: return run<9>(it, blocks, out, clk, nullptr);
+      case 10: return run<10>(it, blocks, out, clk, nullptr);
       default:
         hipLaunchKernelGGL(k_pair_loop, dim3(blocks), dim3(256), 0, nullptr, it, pts, pts + plen, pts + 2 * plen, out,
                            clk);

@@ -80,10 +80,33 @@ def _check_grid(T, ds, params):
     g.close()
 
 
-@pytest.mark.parametrize("name", ["uniform_4k", "mixture", "ragged_rect", "lattice"])
+def dense_cells(seed, n=30000, m=3000, spots=50, dup=100):
+    """Uniform points plus `spots` positions holding `dup` coincident points each: cells of more
+    than 64 points, so their bands take the ballot-ranked local sort."""
+    rng = np.random.default_rng(seed)
+    ds = W.make(n, m, 10, seed)
+    sx, sy = W.quantise(rng.random(spots)), W.quantise(rng.random(spots))
+    pick = rng.permutation(n)[:spots * dup]
+    ds.x[pick] = np.repeat(sx, dup)
+    ds.y[pick] = np.repeat(sy, dup)
+    return ds
+
+
+@pytest.mark.parametrize("name", ["uniform_4k", "mixture", "ragged_rect", "lattice", "dense_cells", "uniform_1m",
+                                  "clustered_1m"])
 def test_grid_matches_oracle(T, name):
+    """The grid (bounds, scalars, CSR offsets, points in cell order with each cell by index)
+    bit for bit against the oracle's stable sort by cell.  uniform_1m takes the rank-ordered
+    local sort in every band, dense_cells the ballot-ranked one in the bands of its crowded
+    cells, clustered_1m (the 2^20 mixture) also bands too large for the LDS tile."""
     aidw = aidw_mod()
-    if name == "uniform_4k":
+    if name == "uniform_1m":
+        ds, p = W.WORKLOADS["uniform_1m"](), aidw.Params()
+    elif name == "clustered_1m":
+        ds, p = W.WORKLOADS["learned_1m"](), aidw.Params(k=15)
+    elif name == "dense_cells":
+        ds, p = dense_cells(33), aidw.Params()
+    elif name == "uniform_4k":
         ds, p = W.uniform_4k(), aidw.Params()
     elif name == "mixture":
         ds, p = W.make(20000, 3000, 15, 31, "mixture"), aidw.Params(k=15)
@@ -316,6 +339,14 @@ def test_full_size_sampled(T, name):
     e = zerr(zall[sel], ref)
     assert e.max() <= Z_TOL, "max z error %.3e" % e.max()
     assert np.allclose(a[sel], ref["alpha"], atol=2e-6)
+    # the grid built for the same cell side given explicitly (exactly sized, LSD-sorted, queries
+    # binned separately) gives every query the same r_obs, alpha and z bit for bit
+    g2 = aidw.build_grid(x, y, qx, qy, p)
+    cw = g2.info()["cell_width"]
+    g2.close()
+    qz2, al2, ro2 = aidw.run(x, y, z, qx, qy, aidw.Params(k=ds.k, cell_width=cw), want_alpha=True, want_robs=True)
+    T.cuda.synchronize()
+    assert T.equal(ro2, ro) and T.equal(al2, al) and T.equal(qz2, qz)
 
 
 # ------------------------------------------------------------------ the paper's stop rule
