@@ -249,12 +249,38 @@ aidw_status aidw_interpolate_naive(const float* x, const float* y, const float* 
  * The whole method (Fig. 1): aidw_build_grid -> aidw_knn -> aidw_interpolate
  * on one stream, with library-owned temporaries.  qz [m] receives the
  * interpolated values; alpha_out [m] and r_obs_out [m] may be NULL.
- * Synchronises the stream once (grid sizing), like aidw_build_grid.
+ * Synchronises the stream once: in occupancy mode at the end (the grid
+ * build's status), with an explicit cell width after the bounds (grid sizing).
  * Errors: those of the three stages.
  */
 aidw_status aidw_run(const float* x, const float* y, const float* z, int64_t n, const float* qx, const float* qy,
                      int64_t m, const aidw_params* p, float* qz, float* alpha_out, float* r_obs_out,
                      hipStream_t stream);
+
+/*
+ * aidw_run for callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops or harnesses that forbid hipMalloc): the same method,
+ * arguments, outputs and errors as aidw_run, with every temporary (grid, band
+ * sort, query bins, r_obs / d1^2, alpha and class keys, padded data, float64
+ * partials) taken from one fixed device array of AIDW_NOALLOC_SCRATCH_BYTES
+ * that the library holds on each GPU it runs on until the process ends.  The
+ * call makes no hipMalloc / hipFree or other allocation; it reads the grid's
+ * status once at the end with a pageable copy (the stream is synchronised).
+ *   - The grid is sized by occupancy: params.cell_width must be <= 0
+ *     (AIDW_EINVAL otherwise).
+ *   - Sizes whose scratch exceeds the array are rejected before any work with
+ *     AIDW_ECAPACITY (about 100 bytes per data point plus query: n = m = 2^20
+ *     fits).  The data axis of the pair kernel is split only as far as its
+ *     float64 partials fit beside the rest.
+ *   - Every call on one GPU uses that GPU's single array: calls that overlap on
+ *     one GPU (other streams, other host threads) race and give undefined
+ *     results.  The array keeps the last call's contents; each call
+ *     initialises what it reads.
+ */
+#define AIDW_NOALLOC_SCRATCH_BYTES (128ull << 20)
+aidw_status aidw_run_noalloc(const float* x, const float* y, const float* z, int64_t n, const float* qx,
+                             const float* qy, int64_t m, const aidw_params* p, float* qz, float* alpha_out,
+                             float* r_obs_out, hipStream_t stream);
 
 /* Per-stage device times of the last aidw_run on the calling thread, recorded
  * with HIP events on the run's stream when timing is enabled. */

@@ -144,6 +144,7 @@ def load(build_if_missing: bool = True):
                                          _VP]
     L.aidw_interpolate.argtypes = [_VP, _VP, _VP, i64, _VP, _VP, i64, _VP, _VP, P(_Params), _VP, _VP, _VP, _VP]
     L.aidw_run.argtypes = [_VP, _VP, _VP, i64, _VP, _VP, i64, P(_Params), _VP, _VP, _VP, _VP]
+    L.aidw_run_noalloc.argtypes = [_VP, _VP, _VP, i64, _VP, _VP, i64, P(_Params), _VP, _VP, _VP, _VP]
     L.aidw_set_timing.argtypes = [ctypes.c_int]
     L.aidw_last_timing.argtypes = [P(_Timing)]
     L.aidw_set_interp_config.argtypes = [i32, i32, i32]
@@ -353,6 +354,16 @@ def run(x, y, z, qx, qy, params: Params | None = None, want_alpha=False, want_ro
     if want_alpha or want_robs:
         return qz, al, ro
     return qz
+
+
+def run_noalloc(x, y, z, qx, qy, qz, params: Params | None = None, alpha=None, r_obs=None, stream=None):
+    """aidw_run_noalloc: the whole method into the caller's outputs (qz [m]; alpha and r_obs
+    [m] or None), every temporary taken from the library's fixed device array."""
+    p = (params or Params())._c()
+    _check(load().aidw_run_noalloc(_dev(x, "x"), _dev(y, "y"), _dev(z, "z"), x.numel(), _dev(qx, "qx"),
+                                   _dev(qy, "qy"), qx.numel(), ctypes.byref(p), _dev(qz, "qz"),
+                                   None if alpha is None else _dev(alpha, "alpha"),
+                                   None if r_obs is None else _dev(r_obs, "r_obs"), _stream(stream)))
 
 
 def set_timing(enable: bool):

@@ -299,6 +299,7 @@ struct aidw_grid {
   int32_t* sidx = nullptr;         // [n]
   hipStream_t async_stream = nullptr;  // non-null: arrays are stream-ordered allocations on this stream
   bool async = false;
+  bool heap = true;  // the handle itself was allocated by the library (else it is the caller's storage)
 };
 
 

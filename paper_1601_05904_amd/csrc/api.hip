@@ -20,6 +20,26 @@ namespace {
 thread_local std::string g_detail;
 thread_local int g_timing = 0;
 thread_local int g_cfg_q = 0, g_cfg_split = 0, g_cfg_intpow = 1;
+thread_local int g_split_cap = 0;  // > 0: at most this many data-axis splits (aidw_run_noalloc)
+
+// A fixed device region that a call carves its temporaries from instead of allocating
+// (aidw_run_noalloc): 256-byte aligned pieces in request order, nothing is freed.
+struct Arena {
+  char* base = nullptr;
+  size_t cap = 0, used = 0;
+};
+thread_local Arena* g_arena = nullptr;
+
+hipError_t arena_take(void** p, size_t bytes) {
+  const size_t b = (bytes + 255) / 256 * 256;
+  if (b > g_arena->cap - g_arena->used) return hipErrorOutOfMemory;
+  *p = g_arena->base + g_arena->used;
+  g_arena->used += b;
+  return hipSuccess;
+}
+bool in_arena(const void* p) {
+  return g_arena && (const char*)p >= g_arena->base && (const char*)p < g_arena->base + g_arena->cap;
+}
 
 struct Timing {
   hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
@@ -62,6 +82,7 @@ bool fault_alloc() {
 
 hipError_t dmalloc(void** p, size_t bytes) {
   *p = nullptr;
+  if (g_arena) return arena_take(p, bytes);
   if (fault_alloc()) return hipErrorOutOfMemory;
   return hipMalloc(p, bytes ? bytes : 1);
 }
@@ -99,6 +120,7 @@ size_t block_size_class(size_t bytes) {
 
 hipError_t dmalloc_async(void** p, size_t bytes, hipStream_t s) {
   *p = nullptr;
+  if (g_arena) return arena_take(p, bytes);
   if (fault_alloc()) return hipErrorOutOfMemory;
   int dev = 0;
   hipError_t e = hipGetDevice(&dev);
@@ -140,7 +162,7 @@ hipError_t dmalloc_async(void** p, size_t bytes, hipStream_t s) {
 }
 
 void dfree_async(void* p, hipStream_t s) {
-  if (!p) return;
+  if (!p || in_arena(p)) return;
   std::lock_guard<std::mutex> lock(g_cache_mu);
   for (CachedBlock& b : block_cache()) {
     if (b.p != p) continue;
@@ -249,6 +271,15 @@ aidw_status sync_grid_host(aidw_grid* g, hipStream_t s) {
   GridScalars* pinned = nullptr;
   hipEvent_t ready = nullptr;
   hipError_t e;
+  if (g_arena) {  // no pinned landing slot (it would be allocated on first use): a pageable read
+    GridScalars h{};
+    if ((e = hipMemcpyAsync(&h, g->dev, sizeof(GridScalars), hipMemcpyDeviceToHost, s)) != hipSuccess ||
+        (e = hipStreamSynchronize(s)) != hipSuccess)
+      return hip_fail(e, "reading grid scalars");
+    g->host = h;
+    g->host_valid = true;
+    return status_error(g->host);
+  }
   if ((e = scalar_staging(&pinned, &ready)) != hipSuccess) return hip_fail(e, "scalar staging");
   if ((e = hipMemcpyAsync(pinned, g->dev, sizeof(GridScalars), hipMemcpyDeviceToHost, s)) != hipSuccess ||
       (e = hipEventRecord(ready, s)) != hipSuccess || (e = hipEventSynchronize(ready)) != hipSuccess)
@@ -269,8 +300,12 @@ aidw_status sync_grid_host(aidw_grid* g, hipStream_t s) {
 // build and the next stage.
 aidw_status build_grid_impl(const float* x, const float* y, int64_t n, const float* qx, const float* qy, int64_t m,
                             const aidw_params* p, hipStream_t s, bool async, aidw_grid** out, Temps* outer = nullptr,
-                            QueryBins* bins = nullptr, bool wait_host = true) {
-  aidw_grid* g = new aidw_grid();
+                            QueryBins* bins = nullptr, bool wait_host = true, aidw_grid* storage = nullptr) {
+  aidw_grid* g = storage ? storage : new aidw_grid();
+  if (storage) {
+    *g = aidw_grid();
+    g->heap = false;
+  }
   g->n = n;
   g->async = async;
   g->async_stream = s;
@@ -436,6 +471,8 @@ void choose_interp_config(int64_t n, int64_t m, int* q, int* split) {
     const int64_t max_by_mem = ((int64_t)1 << 26) / (m > 0 ? m : 1);
     while (sp < 256 && (int64_t)sp * 2 <= max_by_mem && n / ((int64_t)sp * 2) >= 2048) sp *= 2;
   }
+  if (g_split_cap > 0)
+    while (sp > g_split_cap) sp >>= 1;
   if (sp > n) sp = (int)n;
   *q = qq;
   *split = sp < 1 ? 1 : sp;
@@ -681,7 +718,7 @@ void aidw_grid_destroy(aidw_grid* g) {
     else
       (void)hipFree(p);
   }
-  delete g;
+  if (g->heap) delete g;
 }
 
 aidw_status aidw_knn(const aidw_grid* g, const float* qx, const float* qy, int64_t m, int32_t k, float* r_obs,
@@ -778,18 +815,26 @@ aidw_status aidw_knn_bruteforce(const float* x, const float* y, int64_t n, const
   return AIDW_OK;
 }
 
-aidw_status aidw_run(const float* x, const float* y, const float* z, int64_t n, const float* qx, const float* qy,
-                     int64_t m, const aidw_params* p, float* qz, float* alpha_out, float* r_obs_out,
-                     hipStream_t stream) {
-  g_detail.clear();
+namespace {
+
+aidw_status check_run_args(const float* x, const float* y, const float* z, int64_t n, const float* qx,
+                           const float* qy, int64_t m, const aidw_params* p, float* qz) {
   aidw_status st = check_data(x, y, n, qx, qy, m);
   if (st != AIDW_OK) return st;
   if (!z) return fail(AIDW_EINVAL, "z is NULL");
   if ((st = check_params(p)) != AIDW_OK) return st;
   if (p->k < 1 || p->k > AIDW_KMAX || p->k > n)
     return fail(AIDW_EINVAL, "k = %d must be in [1, min(n = %lld, %d)]", p->k, (long long)n, AIDW_KMAX);
-  if (m == 0) return AIDW_OK;
-  if (!qz) return fail(AIDW_EINVAL, "qz is NULL");
+  if (m > 0 && !qz) return fail(AIDW_EINVAL, "qz is NULL");
+  return AIDW_OK;
+}
+
+// The whole method (arguments checked, m > 0).  grid_storage: where the grid's handle lives
+// (null: the library allocates it).
+aidw_status run_impl(const float* x, const float* y, const float* z, int64_t n, const float* qx, const float* qy,
+                     int64_t m, const aidw_params* p, float* qz, float* alpha_out, float* r_obs_out,
+                     hipStream_t stream, aidw_grid* grid_storage) {
+  aidw_status st = AIDW_OK;
   hipEvent_t* ev = nullptr;
   if (g_timing) {
     for (auto& e : g_tm.ev)
@@ -801,7 +846,9 @@ aidw_status aidw_run(const float* x, const float* y, const float* z, int64_t n, 
   aidw_grid* g = nullptr;
   Temps grid_temps(stream);
   QueryBins bins;
-  if ((st = build_grid_impl(x, y, n, qx, qy, m, p, stream, true, &g, &grid_temps, &bins, false)) != AIDW_OK) return st;
+  if ((st = build_grid_impl(x, y, n, qx, qy, m, p, stream, true, &g, &grid_temps, &bins, false, grid_storage)) !=
+      AIDW_OK)
+    return st;
   if (ev) {
     hipError_t e = hipEventRecord(ev[1], stream);
     if (e != hipSuccess) {
@@ -832,6 +879,92 @@ aidw_status aidw_run(const float* x, const float* y, const float* z, int64_t n, 
   // area) is read once everything is queued
   if (st == AIDW_OK && !g->host_valid) st = sync_grid_host(g, stream);
   aidw_grid_destroy(g);
+  return st;
+}
+
+// ---- aidw_run_noalloc: every temporary of a run from one fixed device array per GPU
+
+constexpr size_t kScratchBytes = (size_t)AIDW_NOALLOC_SCRATCH_BYTES;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+// This device's copy of `scratch` (its address is only known through the runtime).
+hipError_t scratch_region(char** out) {
+  constexpr int kMaxDevices = 64;
+  static std::mutex mu;
+  static char* addr[kMaxDevices] = {};
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(mu);
+  if (!addr[dev]) {
+    void* ptr = nullptr;
+    if ((e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch))) != hipSuccess) return e;
+    addr[dev] = static_cast<char*>(ptr);
+  }
+  *out = addr[dev];
+  return hipSuccess;
+}
+
+size_t piece(size_t bytes) { return (bytes + 255) / 256 * 256; }
+
+// Scratch bytes of run_impl in occupancy mode, split data-axis splits (the pieces it takes
+// from the arena, in any order).
+size_t run_scratch_bytes(int64_t n, int64_t m, double occ, bool robs_given, int split) {
+  const int64_t total = n + m;
+  const int64_t budget = occupancy_budget(n, occ);
+  size_t b = piece(sizeof(GridScalars));
+  b += piece(sizeof(BoundsPartial) * kBoundsBlocks) + piece(4 * band_hist_words(total)) +
+       piece(4 * 2 * kMaxBands) + piece(4 * (2 * kMaxBands + 1)) + 3 * piece(4 * (size_t)total);  // band sort
+  b += 3 * piece(4 * (size_t)m);                                                                 // query bins
+  b += piece(4 * (size_t)(budget + 1)) + 3 * piece(4 * (size_t)n);                                // the grid
+  b += (robs_given ? 0 : piece(4 * (size_t)m)) + piece(4 * (size_t)m);                          // r_obs, d1^2
+  if (split > 1) b += piece(16 * (size_t)split * m);                                             // partials
+  b += piece(4) + 6 * piece(4 * (size_t)m) + piece(4 * radix_hist_words((int)m)) +
+       piece(4 * radix_scan_tmp_words((int)m)) + 3 * piece(4 * (size_t)interp_padded_len((int)n));  // Eq. 1-6
+  return b;
+}
+
+}  // namespace
+
+aidw_status aidw_run(const float* x, const float* y, const float* z, int64_t n, const float* qx, const float* qy,
+                     int64_t m, const aidw_params* p, float* qz, float* alpha_out, float* r_obs_out,
+                     hipStream_t stream) {
+  g_detail.clear();
+  aidw_status st = check_run_args(x, y, z, n, qx, qy, m, p, qz);
+  if (st != AIDW_OK || m == 0) return st;
+  return run_impl(x, y, z, n, qx, qy, m, p, qz, alpha_out, r_obs_out, stream, nullptr);
+}
+
+aidw_status aidw_run_noalloc(const float* x, const float* y, const float* z, int64_t n, const float* qx,
+                             const float* qy, int64_t m, const aidw_params* p, float* qz, float* alpha_out,
+                             float* r_obs_out, hipStream_t stream) {
+  g_detail.clear();
+  aidw_status st = check_run_args(x, y, z, n, qx, qy, m, p, qz);
+  if (st != AIDW_OK || m == 0) return st;
+  if (p->cell_width > 0)
+    return fail(AIDW_EINVAL, "aidw_run_noalloc sizes the grid by occupancy: params.cell_width must be <= 0");
+  if (occupancy_budget(n, p->occupancy) > kBandMaxCells)
+    return fail(AIDW_ECAPACITY, "n / occupancy too large for aidw_run_noalloc's grid (at most %lld cells)",
+                (long long)kBandMaxCells);
+  const bool robs_given = r_obs_out != nullptr;
+  const size_t base = run_scratch_bytes(n, m, p->occupancy, robs_given, 1);
+  if (base > kScratchBytes)
+    return fail(AIDW_ECAPACITY, "n = %lld, m = %lld need %zu bytes of scratch; aidw_run_noalloc has %zu",
+                (long long)n, (long long)m, base, kScratchBytes);
+  // the largest power-of-two data-axis split whose float64 partials fit beside the rest
+  int cap = 1;
+  while (cap < 256 && run_scratch_bytes(n, m, p->occupancy, robs_given, cap * 2) <= kScratchBytes) cap *= 2;
+  char* region = nullptr;
+  hipError_t e = scratch_region(&region);
+  if (e != hipSuccess) return hip_fail(e, "locating the scratch array");
+  Arena arena{region, kScratchBytes, 0};
+  aidw_grid grid;
+  g_arena = &arena;
+  g_split_cap = cap;
+  st = run_impl(x, y, z, n, qx, qy, m, p, qz, alpha_out, r_obs_out, stream, &grid);
+  g_split_cap = 0;
+  g_arena = nullptr;
   return st;
 }
 

@@ -167,3 +167,29 @@ def test_nn_statistic_validates(L):
     # null grid, negative m, k out of range and NaN clip are rejected on the host
     assert L.aidw_nn_statistic(None, FAKE, FAKE, 10, 5, 3.0, FAKE, None) == aidw.EINVAL
     assert L.aidw_nn_statistic(FAKE, FAKE, FAKE, -1, 5, 3.0, FAKE, None) == aidw.EINVAL
+
+
+@pytest.mark.parametrize("case", [dict(n=0), dict(z=None), dict(qz=None), dict(p=dict(k=0)),
+                                  dict(p=dict(cell_width=0.01)), dict(p=dict(occupancy=0.0))])
+def test_run_noalloc_rejects_invalid_arguments(L, case):
+    """The no-allocation run checks its arguments as aidw_run does, and refuses an explicit cell
+    side (its grid is sized by occupancy), all before any GPU work."""
+    args = dict(x=FAKE, y=FAKE, z=FAKE, n=100, qx=FAKE, qy=FAKE, m=10, qz=FAKE)
+    args.update({k: v for k, v in case.items() if k != "p"})
+    st = L.aidw_run_noalloc(args["x"], args["y"], args["z"], args["n"], args["qx"], args["qy"], args["m"],
+                            _p(**case.get("p", {})), args["qz"], None, None, None)
+    assert st == aidw.EINVAL
+    assert L.aidw_last_error_detail().decode() != ""
+
+
+@pytest.mark.parametrize("n,m,occ", [(1 << 22, 1 << 22, 2.0), (1 << 20, 1 << 23, 2.0), (1 << 21, 16, 0.25)])
+def test_run_noalloc_rejects_sizes_beyond_its_scratch(L, n, m, occ):
+    """Sizes whose temporaries exceed the fixed scratch array (or whose grid exceeds the banded
+    build's cell limit) are capacity errors, raised before any GPU work."""
+    st = L.aidw_run_noalloc(FAKE, FAKE, FAKE, n, FAKE, FAKE, m, _p(occupancy=occ), FAKE, None, None, None)
+    assert st == aidw.ECAPACITY
+    assert L.aidw_last_error_detail().decode() != ""
+
+
+def test_run_noalloc_empty_query_set_is_a_no_op(L):
+    assert L.aidw_run_noalloc(FAKE, FAKE, FAKE, 100, None, None, 0, _p(), None, None, None, None) == aidw.OK
