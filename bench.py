@@ -53,20 +53,33 @@ VALU_PER_CLK_CU, TRANS_PER_CLK_CU = 128, 32
 CHAIN_MULS = {1: 0, 2: 1, 3: 2, 4: 2, 5: 3, 6: 3, 7: 4, 8: 3}
 
 
-def pair_peak(valu, trans):
-    return CUS * CLOCK / (valu / VALU_PER_CLK_CU + trans / TRANS_PER_CLK_CU)
+def pair_peak(valu, trans, rates=(VALU_PER_CLK_CU, TRANS_PER_CLK_CU)):
+    return CUS * CLOCK / (valu / rates[0] + trans / rates[1])
 
 
 PEAK_GENERAL = pair_peak(7, 2)
 
 
-def class_mix_peak(alpha, levels):
+def class_mix_peak(alpha, levels, rates=(VALU_PER_CLK_CU, TRANS_PER_CLK_CU)):
     """Peak pairs/s for the queries' alpha values (integer levels take the one-transcendental form)."""
     a = np.asarray(alpha, np.float64)
-    inv = np.full(a.shape, 1.0 / PEAK_GENERAL)
+    inv = np.full(a.shape, 1.0 / pair_peak(7, 2, rates))
     for p in sorted(set(int(v) for v in levels if float(v).is_integer() and 1 <= v <= 8)):
-        inv[a == p] = 1.0 / pair_peak(6 + CHAIN_MULS[p], 1)
+        inv[a == p] = 1.0 / pair_peak(6 + CHAIN_MULS[p], 1, rates)
     return 1.0 / inv.mean(), {("alpha=%d" % p): float(np.mean(a == p)) for p in range(1, 9) if np.any(a == p)}
+
+
+def measured_rates():
+    """(VALU, transcendental) lanes per clock per CU that the issue-rate microbenchmark measured on
+    the chip (the pair's own VALU mix; the slowest transcendental), from its committed summary."""
+    path = os.path.join(ROOT, "profiles", "valu_transcendental_issue_rates.md")
+    if not os.path.exists(path):
+        return None
+    f = profile_fields(path)
+    try:
+        return float(f["- valu_lanes_per_clk_cu_pair_mix"]), float(f["- trans_lanes_per_clk_cu"])
+    except (KeyError, ValueError):
+        return None
 
 
 PAIR_SOURCES = {"k_interp": ("interp.hip", "pair_core.h", "api.hip"), "k_b_interp": ("batch.hip", "pair_core.h"),
@@ -630,6 +643,8 @@ def plain_measurement(args):
     # alpha of every query (untimed run) decides the class mix of the roofline
     _, alpha, _ = aidw.run(x, y, z, qx, qy, p, want_alpha=True, stream=stream)
     peak, mix = class_mix_peak(alpha.cpu().numpy(), ds.levels)
+    rates = measured_rates()
+    ceiling = class_mix_peak(alpha.cpu().numpy(), ds.levels, rates)[0] if rates else None
 
     ms = (t1 - t0) * 1e3 / args.steps
     value = ds.m / (ms * 1e-3)
@@ -658,7 +673,11 @@ def plain_measurement(args):
                      "unit": "Gpair/s", "frac": achieved / peak, "traffic": measured_traffic("k_interp", args.workload),
                      "per_unit": "pair: general alpha 7 VALU + 2 transcendental; integer alpha p 6 VALU + chain(p) "
                                  "multiplies + 1 transcendental", "class_mix": mix,
-                     "peak_general_form": PEAK_GENERAL / 1e9, "units_per_launch": pairs},
+                     "peak_general_form": PEAK_GENERAL / 1e9, "units_per_launch": pairs,
+                     "measured_ceiling": None if ceiling is None else ceiling / 1e9,
+                     "frac_of_measured_ceiling": None if ceiling is None else achieved / ceiling,
+                     "measured_ceiling_note": "the same per-pair counts at the VALU and transcendental rates the "
+                                              "issue-rate microbenchmark measured on the chip"},
     }
 
     g = aidw.build_grid(x, y, qx, qy, p, stream=stream)
