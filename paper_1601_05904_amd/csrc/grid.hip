@@ -26,22 +26,31 @@ __global__ __launch_bounds__(kBoundsThreads) void k_bounds(const float* __restri
                                                            BoundsPartial* __restrict__ partial) {
   float mnx = INFINITY, mny = INFINITY, mxx = -INFINITY, mxy = -INFINITY;
   int bad = 0;
-  const int64_t total = (int64_t)n + m;
-  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
-    float a, b;
-    if (e < n) {
-      a = x[e];
-      b = y[e];
-    } else {
-      a = qx[e - n];
-      b = qy[e - n];
-    }
+  auto take = [&](float a, float b) {
     bad |= !(isfinite(a) && isfinite(b));
     mnx = fminf(mnx, a);
     mxx = fmaxf(mxx, a);
     mny = fminf(mny, b);
     mxy = fmaxf(mxy, b);
-  }
+  };
+  // the data points, then the queries; four strides per step keep eight loads in flight
+  auto sweep = [&](const float* __restrict__ a, const float* __restrict__ b, int64_t len) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (; i + 3 * stride < len; i += 4 * stride) {
+      float av[4], bv[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        av[u] = a[i + u * stride];
+        bv[u] = b[i + u * stride];
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) take(av[u], bv[u]);
+    }
+    for (; i < len; i += stride) take(a[i], b[i]);
+  };
+  sweep(x, y, n);
+  if (m > 0) sweep(qx, qy, m);
   mnx = wave_min(mnx);
   mny = wave_min(mny);
   mxx = wave_max(mxx);

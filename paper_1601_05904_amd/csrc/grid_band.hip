@@ -8,7 +8,7 @@
 //                     of points per digit: the digit of a data point is its band (the
 //                     cell index >> band_shift), a query's is nbands + its band.
 //   k_band_prefix     per digit, the exclusive scan of its counts over the blocks, and the
-//                     digit's total (8 digits per block).
+//                     digit's total (64 digits per block).
 //   k_band_scatter    a stable counting sort of each tile by digit: ranks from wavefront
 //                     ballots, the tile sorted in LDS, then written out in runs, so each
 //                     block writes contiguous pieces of every digit's segment.
@@ -141,6 +141,21 @@ __device__ inline uint64_t match_key(uint32_t key, int bits, uint64_t live) {
   return match;
 }
 
+// Number of the 16-bit values a[lo, hi) below `me`; a is 16-byte aligned, read 8 values per load.
+__device__ inline uint32_t count_below(const uint16_t* a, uint32_t lo, uint32_t hi, uint16_t me) {
+  uint32_t r = 0, j = lo;
+  for (; j < hi && (j & 7u); ++j) r += a[j] < me ? 1u : 0u;
+  const uint4* v = reinterpret_cast<const uint4*>(a);
+  const uint32_t m = me;
+  auto below2 = [m](uint32_t w) { return ((w & 0xffffu) < m ? 1u : 0u) + ((w >> 16) < m ? 1u : 0u); };
+  for (; j + 8 <= hi; j += 8) {
+    const uint4 q = v[j >> 3];
+    r += below2(q.x) + below2(q.y) + below2(q.z) + below2(q.w);
+  }
+  for (; j < hi; ++j) r += a[j] < me ? 1u : 0u;
+  return r;
+}
+
 // Element e of the joint index space (data points [0, n), then queries).
 struct Elem {
   uint32_t idx;  // index within its set
@@ -202,10 +217,11 @@ __global__ __launch_bounds__(kThreads) void k_band_hist(const BoundsPartial* __r
   for (int d = threadIdx.x; d < kDigits; d += kThreads) hist[(size_t)blockIdx.x * kDigits + d] = h[d];
 }
 
-// For 8 digits per block: each digit's counts over the blocks -> their exclusive prefix (in
-// place), and the digit's total.  Thread (slice, j) walks a slice of the blocks for digit j.
-constexpr int kPrefixDigits = 8;
-constexpr int kPrefixSlices = 32;
+// For 64 digits per block: each digit's counts over the blocks -> their exclusive prefix (in
+// place), and the digit's total.  Thread (slice, j) walks a slice of the blocks for digit j, so
+// a wavefront reads 64 consecutive words of a block's row.
+constexpr int kPrefixDigits = 64;
+constexpr int kPrefixSlices = 16;
 __global__ __launch_bounds__(kPrefixDigits * kPrefixSlices) void k_band_prefix(uint32_t* __restrict__ hist, int nblk,
                                                                                uint32_t* __restrict__ totals) {
   __shared__ uint32_t part[kPrefixSlices][kPrefixDigits];
@@ -214,7 +230,14 @@ __global__ __launch_bounds__(kPrefixDigits * kPrefixSlices) void k_band_prefix(u
   const int per = (nblk + kPrefixSlices - 1) / kPrefixSlices;
   const int b0 = slice * per, b1 = min(nblk, b0 + per);
   uint32_t sum = 0;
-  for (int b = b0; b < b1; ++b) sum += hist[(size_t)b * kDigits + d];
+  int b = b0;
+  for (; b + 4 <= b1; b += 4) {
+    uint32_t v[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) v[u] = hist[(size_t)(b + u) * kDigits + d];
+    sum += v[0] + v[1] + v[2] + v[3];
+  }
+  for (; b < b1; ++b) sum += hist[(size_t)b * kDigits + d];
   part[slice][j] = sum;
   __syncthreads();
   uint32_t run = 0, tot = 0;
@@ -222,7 +245,17 @@ __global__ __launch_bounds__(kPrefixDigits * kPrefixSlices) void k_band_prefix(u
     if (s < slice) run += part[s][j];
     tot += part[s][j];
   }
-  for (int b = b0; b < b1; ++b) {
+  for (b = b0; b + 4 <= b1; b += 4) {
+    uint32_t v[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) v[u] = hist[(size_t)(b + u) * kDigits + d];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      hist[(size_t)(b + u) * kDigits + d] = run;
+      run += v[u];
+    }
+  }
+  for (; b < b1; ++b) {
     const size_t i = (size_t)b * kDigits + d;
     const uint32_t v = hist[i];
     hist[i] = run;
@@ -231,12 +264,19 @@ __global__ __launch_bounds__(kPrefixDigits * kPrefixSlices) void k_band_prefix(u
   if (slice == 0) totals[d] = tot;
 }
 
-// Stable counting sort of one tile by digit.  Round it (0 .. kItems) takes element
-// base + it * kThreads + thread: a wavefront ranks equal digits by ballots, earlier
-// wavefronts of the round are counted through wcnt (written by each digit's leader lane,
-// cleared by it after the round), earlier rounds through the running cursor cur.  Each
-// element's place in the tile's digit order goes to LDS; the sorted tile is then written
-// to each digit's segment at this block's prefix, one contiguous run per digit.
+// Stable counting sort of one tile by digit, then each digit's run written to its segment at
+// this block's prefix.  The tile's counts per digit (LDS atomics) and their exclusive scan give
+// each digit's run in the tile.  Two ways to order a run by index:
+//   rank path    (no digit holds more than kScatterRankMaxRun of the tile's elements): each
+//                element takes a slot of its run by an LDS atomic, then its place in the run
+//                is the number of the run's elements at a smaller tile position (tile position
+//                order is index order);
+//   ballot path  (otherwise): round it (0 .. kItems) takes element base + it * kThreads +
+//                thread; a wavefront ranks equal digits by ballots, earlier wavefronts of the
+//                round are counted through wcnt (written by each digit's leader lane, cleared
+//                by it after the round), earlier rounds through the running cursor cur.
+// The tile keeps tile positions (16 bits; the element is base + position) and coordinates.
+constexpr int kScatterRankMaxRun = 64;
 __global__ __launch_bounds__(kThreads) void k_band_scatter(const GridScalars* __restrict__ gs, int64_t n, int64_t total,
                                                            const float* __restrict__ x, const float* __restrict__ y,
                                                            const float* __restrict__ qx, const float* __restrict__ qy,
@@ -244,12 +284,16 @@ __global__ __launch_bounds__(kThreads) void k_band_scatter(const GridScalars* __
                                                            const uint32_t* __restrict__ totals,
                                                            uint32_t* __restrict__ dstart, uint32_t* __restrict__ oidx,
                                                            float* __restrict__ ox, float* __restrict__ oy) {
-  __shared__ uint32_t t_idx[kTile];
+  static_assert(kTile <= 65536, "tile positions are 16-bit");
+  __shared__ uint16_t t_pos[kTile];
   __shared__ float t_x[kTile], t_y[kTile];
-  __shared__ uint8_t wcnt[kWaves][kDigits];
-  __shared__ uint32_t cur[kDigits];
-  __shared__ uint32_t loff[kDigits];
-  __shared__ uint32_t gstart[kDigits];
+  __shared__ __align__(16) union {
+    uint16_t r_pos[kTile];            // rank path: tile positions in slot order
+    uint8_t wcnt[kWaves][kDigits];    // ballot path
+  } u;
+  __shared__ uint32_t loff[kDigits];  // the tile's counts, then each digit's run start in the tile
+  __shared__ uint32_t cur[kDigits];   // run cursors, then each digit's output start for this block
+  __shared__ uint32_t s_maxrun;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int64_t base = (int64_t)blockIdx.x * kTile;
   Elem el[kItems];
@@ -266,85 +310,116 @@ __global__ __launch_bounds__(kThreads) void k_band_scatter(const GridScalars* __
 #pragma unroll
   for (int it = 0; it < kItems; ++it)
     dig[it] = ok[it] ? (cell_of(el[it].x, el[it].y, g) >> g.band_shift) + (el[it].query ? nb : 0u) : 0u;
-  for (int d = tid; d < kDigits; d += kThreads) {
-    cur[d] = 0u;
-    gstart[d] = totals[d];
-  }
-  for (int i = tid; i < kWaves * kDigits; i += kThreads) (&wcnt[0][0])[i] = 0;
+  for (int d = tid; d < kDigits; d += kThreads) loff[d] = 0u;
+  if (tid == 0) s_maxrun = 0u;
   __syncthreads();
 #pragma unroll
   for (int it = 0; it < kItems; ++it)
-    if (ok[it]) atomicAdd(&cur[dig[it]], 1u);
+    if (ok[it]) atomicAdd(&loff[dig[it]], 1u);
   __syncthreads();
-  for (int d = tid; d < kDigits; d += kThreads) loff[d] = cur[d];
-  __syncthreads();
+  {
+    uint32_t mx = 0u;
+    for (int d = tid; d < kDigits; d += kThreads) mx = max(mx, loff[d]);
+    if (mx > 0u) atomicMax(&s_maxrun, mx);
+  }
   lds_exclusive_scan<kThreads>(loff, kDigits);
-  const uint32_t all = lds_exclusive_scan<kThreads>(gstart, kDigits);
+  for (int d = tid; d < kDigits; d += kThreads) cur[d] = loff[d];
+  __syncthreads();
+  if (s_maxrun <= (uint32_t)kScatterRankMaxRun) {
+#pragma unroll
+    for (int it = 0; it < kItems; ++it)
+      if (ok[it]) u.r_pos[atomicAdd(&cur[dig[it]], 1u)] = (uint16_t)(it * kThreads + tid);
+    __syncthreads();
+#pragma unroll
+    for (int it = 0; it < kItems; ++it)
+      if (ok[it]) {
+        const uint32_t d = dig[it], lo = loff[d], hi = cur[d];
+        const uint16_t me = (uint16_t)(it * kThreads + tid);
+        const uint32_t pos = lo + count_below(u.r_pos, lo, hi, me);
+        t_pos[pos] = me;
+        t_x[pos] = el[it].x;
+        t_y[pos] = el[it].y;
+      }
+  } else {
+    for (int i = tid; i < kWaves * kDigits; i += kThreads) (&u.wcnt[0][0])[i] = 0;
+    const uint64_t lt_mask = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+    __syncthreads();
+#pragma unroll
+    for (int it = 0; it < kItems; ++it) {
+      const uint32_t d = dig[it];
+      const uint64_t match = match_key(d, kDigitBits, __ballot(ok[it]));
+      const uint32_t rank = __popcll(match & lt_mask);
+      const uint32_t cnt = __popcll(match);
+      const bool leader = ok[it] && rank == 0;
+      if (leader) u.wcnt[wave][d] = (uint8_t)cnt;
+      __syncthreads();
+      if (ok[it]) {
+        uint32_t pre = 0;
+        for (int w = 0; w < wave; ++w) pre += u.wcnt[w][d];
+        const uint32_t pos = cur[d] + pre + rank;
+        t_pos[pos] = (uint16_t)(it * kThreads + tid);
+        t_x[pos] = el[it].x;
+        t_y[pos] = el[it].y;
+      }
+      __syncthreads();
+      if (leader) {
+        atomicAdd(&cur[d], cnt);
+        u.wcnt[wave][d] = 0;
+      }
+    }
+  }
+  __syncthreads();
+  // each digit's output start for this block: the digit's start (exclusive scan of the totals,
+  // stored by block 0) plus this block's prefix within the digit
+  for (int d = tid; d < kDigits; d += kThreads) cur[d] = totals[d];
+  __syncthreads();
+  const uint32_t all = lds_exclusive_scan<kThreads>(cur, kDigits);
   const uint32_t* row = prefix + (size_t)blockIdx.x * kDigits;
   for (int d = tid; d < kDigits; d += kThreads) {
-    if (blockIdx.x == 0) dstart[d] = gstart[d];
-    cur[d] = loff[d];
-    gstart[d] += row[d];
+    if (blockIdx.x == 0) dstart[d] = cur[d];
+    cur[d] += row[d];
   }
   if (blockIdx.x == 0 && tid == 0) dstart[kDigits] = all;
-  const uint64_t lt_mask = lane == 0 ? 0ull : (~0ull >> (64 - lane));
-  __syncthreads();
-#pragma unroll
-  for (int it = 0; it < kItems; ++it) {
-    const uint32_t d = dig[it];
-    const uint64_t match = match_key(d, kDigitBits, __ballot(ok[it]));
-    const uint32_t rank = __popcll(match & lt_mask);
-    const uint32_t cnt = __popcll(match);
-    const bool leader = ok[it] && rank == 0;
-    if (leader) wcnt[wave][d] = (uint8_t)cnt;
-    __syncthreads();
-    if (ok[it]) {
-      uint32_t pre = 0;
-      for (int w = 0; w < wave; ++w) pre += wcnt[w][d];
-      const uint32_t pos = cur[d] + pre + rank;
-      t_idx[pos] = el[it].idx;
-      t_x[pos] = el[it].x;
-      t_y[pos] = el[it].y;
-    }
-    __syncthreads();
-    if (leader) {
-      atomicAdd(&cur[d], cnt);
-      wcnt[wave][d] = 0;
-    }
-  }
   __syncthreads();
   const int64_t left = total - base;
   const int cnt_blk = left < kTile ? (int)left : kTile;
-  const int64_t dleft = n - base;
-  const int nd = dleft <= 0 ? 0 : (dleft < cnt_blk ? (int)dleft : cnt_blk);  // data points of this tile
   for (int i = tid; i < cnt_blk; i += kThreads) {
+    const int64_t e = base + t_pos[i];
+    const bool query = e >= n;
     const float px = t_x[i], py = t_y[i];
-    const uint32_t d = (cell_of(px, py, g) >> g.band_shift) + (i >= nd ? nb : 0u);
-    const uint32_t gp = gstart[d] + ((uint32_t)i - loff[d]);
-    oidx[gp] = t_idx[i];
+    const uint32_t d = (cell_of(px, py, g) >> g.band_shift) + (query ? nb : 0u);
+    const uint32_t gp = cur[d] + ((uint32_t)i - loff[d]);
+    oidx[gp] = (uint32_t)(query ? e - n : e);
     ox[gp] = px;
     oy[gp] = py;
   }
 }
 
 // One block per digit: the stable counting sort of the digit's segment by cell inside its
-// band.  The cells' counts (LDS atomics) and their exclusive scan give the CSR offsets, which
-// data blocks write (head of cell c = cell_start[c], size = cell_start[c + 1] - cell_start[c],
-// Section 3.2.3).  Two ways to order the points inside each cell by index:
-//   rank path    (the segment fits the LDS tile and no cell of the band holds more than
-//                kRankMaxCell points): every point takes a slot of its cell by an LDS atomic,
-//                then its place in the cell is the number of the cell's points with a smaller
-//                index; the sorted tile is written out in one coalesced pass.
-//   ballot path  (otherwise): the segment, which the stable scatter left in index order, is
-//                ranked in rounds of kLocalThreads points by wavefront ballots on the local
-//                cell key, earlier rounds counted by a running cursor per cell; a segment that
-//                fits the tile is sorted in LDS and written out, a longer one (a dense band) is
-//                written directly.
-// Query blocks write the queries in cell order (and their coordinates).  Dynamic LDS: cnt [CB]
-// (counts, then offsets / cursors), then a region used either by the rank path (slot indices,
-// sorted index, x, y [kLocalTile] each) or by the ballot path (wcnt [kLocalWaves][CB] bytes,
-// then the staged index, x, y [kLocalTile] each); CB = the largest band the host sized for.
-constexpr int kRankMaxCell = 64;
+// band.  The segment arrives in index order (the scatter is stable).  The cells' counts (LDS
+// atomics) and their exclusive scan give the CSR offsets, which data blocks write (head of
+// cell c = cell_start[c], size = cell_start[c + 1] - cell_start[c], Section 3.2.3).  Two ways
+// to order the points inside each cell by index:
+//   rank path    (no cell of the band holds more than kRankMaxCell points): the segment is
+//                taken in chunks of kLocalTile points in order; in a chunk every point takes a
+//                slot of its cell by an LDS atomic, its place among the chunk's points of the
+//                cell is the number of them at a smaller segment position, and the chunks
+//                before it add their counts of the cell;
+//   ballot path  (otherwise): the segment is ranked in rounds of kLocalThreads points by
+//                wavefront ballots on the local cell key, earlier rounds counted by a running
+//                cursor per cell.
+// A segment of one chunk is held in registers from the start (its counts come from them) and
+// its sorted points are staged in LDS and written out in one coalesced pass; otherwise each
+// point is written straight to its place in the segment.  Query blocks write the queries in
+// cell order (and their coordinates).  Dynamic LDS: cnt [CB] (counts, then the cells' offsets
+// in the segment), then one region used by one path:
+//   rank path, one chunk   r_pos (16-bit chunk positions in slot order) [kLocalTile], then the
+//                          sorted index, x, y [kLocalTile] each;
+//   rank path, chunks      r_pos [kLocalTile], then done, coff, ccur [CB] each (the cell's points
+//                          in earlier chunks; the chunk's run start and cursor per cell);
+//   ballot path            wcnt [kLocalWaves][CB] bytes;
+// CB = the largest band the host sized for.
+constexpr int kRankMaxCell = 256;
 __global__ __launch_bounds__(kLocalThreads) void k_band_local(const GridScalars* __restrict__ gs, int64_t n,
                                                               int cb_max, const uint32_t* __restrict__ dstart,
                                                               const uint32_t* __restrict__ bidx,
@@ -355,7 +430,8 @@ __global__ __launch_bounds__(kLocalThreads) void k_band_local(const GridScalars*
                                                               int32_t* __restrict__ sidx,
                                                               uint32_t* __restrict__ qorder, float* __restrict__ qsx,
                                                               float* __restrict__ qsy) {
-  extern __shared__ uint32_t lds[];
+  static_assert(kLocalTile <= 65536, "chunk positions are 16-bit");
+  extern __shared__ __align__(16) uint32_t lds[];
   __shared__ uint32_t s_max;  // the largest cell count of the band
   const GridScalars g = *gs;
   const int nb = g.nbands;
@@ -368,84 +444,59 @@ __global__ __launch_bounds__(kLocalThreads) void k_band_local(const GridScalars*
   const uint32_t cell0 = (uint32_t)band << shift;
   const int ncb = (int)(g.ncells - (int64_t)cell0 < cb ? g.ncells - (int64_t)cell0 : cb);
   uint32_t* cnt = lds;
-  uint32_t* region = lds + cb_max;
-  // rank path
-  uint32_t* r_slot = region;
-  uint32_t* r_idx = region + kLocalTile;
-  float* r_x = reinterpret_cast<float*>(region + 2 * kLocalTile);
-  float* r_y = reinterpret_cast<float*>(region + 3 * kLocalTile);
-  // ballot path
-  uint8_t* wcnt = reinterpret_cast<uint8_t*>(region);  // [kLocalWaves][cb]
-  uint32_t* t_idx = region + kLocalWaves * cb_max / 4;
-  float* t_x = reinterpret_cast<float*>(t_idx + kLocalTile);
-  float* t_y = t_x + kLocalTile;
+  uint32_t* region = lds + ((cb_max + 3) & ~3);            // 16-byte aligned
+  uint16_t* r_pos = reinterpret_cast<uint16_t*>(region);  // rank paths
+  uint32_t* o_idx = region + kLocalTile / 2;               // one chunk
+  float* o_x = reinterpret_cast<float*>(o_idx + kLocalTile);
+  float* o_y = o_x + kLocalTile;
+  uint32_t* done = region + kLocalTile / 2;                // chunks
+  uint32_t* coff = done + cb_max;
+  uint32_t* ccur = coff + cb_max;
+  uint8_t* wcnt = reinterpret_cast<uint8_t*>(region);     // ballot path: [kLocalWaves][cb]
   const uint32_t s = dstart[d], e = dstart[d + 1];
-  const uint32_t size = e - s;
-  const bool staged = size <= (uint32_t)kLocalTile;
+  const bool one_chunk = e - s <= (uint32_t)kLocalTile;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const uint64_t lt_mask = lane == 0 ? 0ull : (~0ull >> (64 - lane));
 
-  for (int i = tid; i < cb; i += kLocalThreads) cnt[i] = 0u;
-  if (tid == 0) s_max = 0u;
-  // a staged segment stays in registers: (local cell, index, x, y) per item
-  uint32_t lk[kLocalItems], id[kLocalItems];
-  float px[kLocalItems], py[kLocalItems];
-  if (staged) {
+  // in-place exclusive scan of a[0, cb); with `offsets`, the cells' CSR offsets are stored.
+  // Other threads' entries are only complete after the caller's next barrier.
+  auto scan_cells = [&](uint32_t* a, bool offsets) {
+    uint32_t carry = 0;
+    for (int c0 = 0; c0 < cb; c0 += kLocalThreads * 4) {
+      uint32_t v[4];
+      uint32_t sum = 0;
 #pragma unroll
-    for (int it = 0; it < kLocalItems; ++it) {
-      const uint32_t p = s + it * kLocalThreads + tid;
-      lk[it] = 0xffffffffu;
-      id[it] = 0u;
-      px[it] = py[it] = 0.0f;
-      if (p < e) {
-        px[it] = bx[p];
-        py[it] = by[p];
-        id[it] = bidx[p];
-        lk[it] = cell_of(px[it], py[it], g) - cell0;
+      for (int i = 0; i < 4; ++i) {
+        const int j = c0 + tid * 4 + i;
+        v[i] = j < cb ? a[j] : 0u;
+        sum += v[i];
       }
-    }
-  }
-  __syncthreads();
-  if (staged) {
+      uint32_t tot;
+      uint32_t run = carry + block_scan<kLocalThreads>(sum, &tot);
 #pragma unroll
-    for (int it = 0; it < kLocalItems; ++it)
-      if (lk[it] != 0xffffffffu) atomicAdd(&cnt[lk[it]], 1u);
-  } else {
-    for (uint32_t p = s + tid; p < e; p += kLocalThreads) atomicAdd(&cnt[cell_of(bx[p], by[p], g) - cell0], 1u);
-  }
-  __syncthreads();
-  if (staged) {
-    uint32_t mx = 0u;
-    for (int i = tid; i < cb; i += kLocalThreads) mx = max(mx, cnt[i]);
-    if (mx > 0u) atomicMax(&s_max, mx);
-  }
-  // exclusive scan of the band's counts; a data band writes its cells' offsets
-  uint32_t carry = 0;
-  for (int c0 = 0; c0 < cb; c0 += kLocalThreads * 4) {
-    uint32_t v[4];
-    uint32_t sum = 0;
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int j = c0 + tid * 4 + i;
-      v[i] = j < cb ? cnt[j] : 0u;
-      sum += v[i];
-    }
-    uint32_t tot;
-    uint32_t run = carry + block_scan<kLocalThreads>(sum, &tot);
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int j = c0 + tid * 4 + i;
-      if (j < cb) {
-        cnt[j] = run;
-        if (!query && j < ncb) cell_start[cell0 + j] = (int32_t)(s + run);
+      for (int i = 0; i < 4; ++i) {
+        const int j = c0 + tid * 4 + i;
+        if (j < cb) {
+          a[j] = run;
+          if (offsets && j < ncb) cell_start[cell0 + j] = (int32_t)(s + run);
+        }
+        run += v[i];
       }
-      run += v[i];
+      carry += tot;
     }
-    carry += tot;
-  }
-  if (!query && band == nb - 1 && tid == 0) cell_start[g.ncells] = (int32_t)e;
-  __syncthreads();
-  // writes the sorted point at segment position i (staged in LDS, or direct)
+  };
+  // the point at segment position p < end: local cell, index, x, y (lk = ~0u past the end)
+  auto load_point = [&](uint32_t p, uint32_t end, uint32_t& lk, uint32_t& id, float& px, float& py) {
+    lk = 0xffffffffu;
+    id = 0u;
+    px = py = 0.0f;
+    if (p < end) {
+      px = bx[p];
+      py = by[p];
+      id = bidx[p];
+      lk = cell_of(px, py, g) - cell0;
+    }
+  };
+  // writes the sorted point at segment position i
   auto emit = [&](uint32_t i, uint32_t pid, float fx, float fy) {
     if (!query) {
       sidx[s + i] = (int32_t)pid;
@@ -460,15 +511,49 @@ __global__ __launch_bounds__(kLocalThreads) void k_band_local(const GridScalars*
       }
     }
   };
-  if (staged && s_max <= (uint32_t)kRankMaxCell) {
-    // rank path: a slot of the point's cell, then its place among the cell's points by index
-    uint32_t slot[kLocalItems];
+
+  for (int i = tid; i < cb; i += kLocalThreads) cnt[i] = 0u;
+  if (tid == 0) s_max = 0u;
+  uint32_t lk[kLocalItems], id[kLocalItems];
+  float px[kLocalItems], py[kLocalItems];
+  if (one_chunk) {
+#pragma unroll
+    for (int it = 0; it < kLocalItems; ++it) load_point(s + it * kLocalThreads + tid, e, lk[it], id[it], px[it], py[it]);
+  }
+  __syncthreads();
+  if (one_chunk) {
 #pragma unroll
     for (int it = 0; it < kLocalItems; ++it)
-      if (lk[it] != 0xffffffffu) {
-        slot[it] = atomicAdd(&cnt[lk[it]], 1u);
-        r_slot[slot[it]] = id[it];
+      if (lk[it] != 0xffffffffu) atomicAdd(&cnt[lk[it]], 1u);
+  } else {
+    // eight loads in flight per thread
+    uint32_t p = s + tid;
+    for (; p + 7 * kLocalThreads < e; p += 8 * kLocalThreads) {
+      float ax[8], ay[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        ax[u] = bx[p + u * kLocalThreads];
+        ay[u] = by[p + u * kLocalThreads];
       }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) atomicAdd(&cnt[cell_of(ax[u], ay[u], g) - cell0], 1u);
+    }
+    for (; p < e; p += kLocalThreads) atomicAdd(&cnt[cell_of(bx[p], by[p], g) - cell0], 1u);
+  }
+  __syncthreads();
+  {
+    uint32_t mx = 0u;
+    for (int i = tid; i < cb; i += kLocalThreads) mx = max(mx, cnt[i]);
+    if (mx > 0u) atomicMax(&s_max, mx);
+  }
+  scan_cells(cnt, !query);
+  if (!query && band == nb - 1 && tid == 0) cell_start[g.ncells] = (int32_t)e;
+  __syncthreads();
+  if (s_max <= (uint32_t)kRankMaxCell && one_chunk) {
+    // a slot of the point's cell, then its place among the cell's points
+#pragma unroll
+    for (int it = 0; it < kLocalItems; ++it)
+      if (lk[it] != 0xffffffffu) r_pos[atomicAdd(&cnt[lk[it]], 1u)] = (uint16_t)(it * kLocalThreads + tid);
     __syncthreads();
     // cnt[c] is now the end of cell c, which is the start of cell c + 1
 #pragma unroll
@@ -476,22 +561,64 @@ __global__ __launch_bounds__(kLocalThreads) void k_band_local(const GridScalars*
       if (lk[it] != 0xffffffffu) {
         const uint32_t c = lk[it];
         const uint32_t c_end = cnt[c], c_begin = c == 0 ? 0u : cnt[c - 1];
-        uint32_t pos = c_begin;
-        for (uint32_t j = c_begin; j < c_end; ++j) pos += r_slot[j] < id[it] ? 1u : 0u;
-        r_idx[pos] = id[it];
-        r_x[pos] = px[it];
-        r_y[pos] = py[it];
+        const uint16_t me = (uint16_t)(it * kLocalThreads + tid);
+        const uint32_t pos = c_begin + count_below(r_pos, c_begin, c_end, me);
+        o_idx[pos] = id[it];
+        o_x[pos] = px[it];
+        o_y[pos] = py[it];
       }
     __syncthreads();
-    for (uint32_t i = tid; i < size; i += kLocalThreads) emit(i, r_idx[i], r_x[i], r_y[i]);
+    for (uint32_t i = tid; i < e - s; i += kLocalThreads) emit(i, o_idx[i], o_x[i], o_y[i]);
     return;
   }
-  // ballot path
+  if (s_max <= (uint32_t)kRankMaxCell) {
+    for (int i = tid; i < cb; i += kLocalThreads) done[i] = 0u;
+    for (uint32_t c0 = s; c0 < e; c0 += kLocalTile) {
+      const uint32_t c1 = e - c0 < (uint32_t)kLocalTile ? e : c0 + kLocalTile;
+      uint32_t ck[kLocalItems], cid[kLocalItems];
+      float cx[kLocalItems], cy[kLocalItems];
+#pragma unroll
+      for (int it = 0; it < kLocalItems; ++it) load_point(c0 + it * kLocalThreads + tid, c1, ck[it], cid[it], cx[it], cy[it]);
+      for (int i = tid; i < cb; i += kLocalThreads) coff[i] = 0u;
+      __syncthreads();
+#pragma unroll
+      for (int it = 0; it < kLocalItems; ++it)
+        if (ck[it] != 0xffffffffu) atomicAdd(&coff[ck[it]], 1u);
+      __syncthreads();
+      scan_cells(coff, false);
+      __syncthreads();
+      for (int i = tid; i < cb; i += kLocalThreads) ccur[i] = coff[i];
+      __syncthreads();
+#pragma unroll
+      for (int it = 0; it < kLocalItems; ++it)
+        if (ck[it] != 0xffffffffu) r_pos[atomicAdd(&ccur[ck[it]], 1u)] = (uint16_t)(it * kLocalThreads + tid);
+      __syncthreads();
+#pragma unroll
+      for (int it = 0; it < kLocalItems; ++it)
+        if (ck[it] != 0xffffffffu) {
+          const uint32_t c = ck[it];
+          const uint32_t lo = coff[c], hi = ccur[c];
+          const uint16_t me = (uint16_t)(it * kLocalThreads + tid);
+          const uint32_t pos = cnt[c] + done[c] + count_below(r_pos, lo, hi, me);
+          emit(pos, cid[it], cx[it], cy[it]);
+        }
+      __syncthreads();
+      for (int i = tid; i < cb; i += kLocalThreads) done[i] += ccur[i] - coff[i];
+      __syncthreads();
+    }
+    return;
+  }
+  // ballot path: rounds of kLocalThreads points in segment order; the point of this thread goes
+  // to cnt[key] + (earlier waves' and lanes' points of the same key in the round)
+  const uint64_t lt_mask = lane == 0 ? 0ull : (~0ull >> (64 - lane));
   for (int i = tid; i < kLocalWaves * cb / 4; i += kLocalThreads) reinterpret_cast<uint32_t*>(wcnt)[i] = 0u;
   __syncthreads();
-  // one ranking round: the point of this thread (valid, local cell key, index, x, y) goes to
-  // position cur[key] + (earlier waves' and lanes' points of the same key) of the segment
-  auto round = [&](bool valid, uint32_t key, uint32_t pid, float fx, float fy) {
+  for (uint32_t r0 = s; r0 < e; r0 += kLocalThreads) {
+    uint32_t key, pid;
+    float fx, fy;
+    load_point(r0 + tid, e, key, pid, fx, fy);
+    const bool valid = key != 0xffffffffu;
+    if (!valid) key = 0u;
     const uint64_t match = match_key(key, shift, __ballot(valid));
     const uint32_t rank = __popcll(match & lt_mask);
     const uint32_t c = __popcll(match);
@@ -501,40 +628,12 @@ __global__ __launch_bounds__(kLocalThreads) void k_band_local(const GridScalars*
     if (valid) {
       uint32_t pre = 0;
       for (int w = 0; w < wave; ++w) pre += wcnt[w * cb + key];
-      const uint32_t pos = cnt[key] + pre + rank;
-      if (staged) {
-        t_idx[pos] = pid;
-        t_x[pos] = fx;
-        t_y[pos] = fy;
-      } else {
-        emit(pos, pid, fx, fy);
-      }
+      emit(cnt[key] + pre + rank, pid, fx, fy);
     }
     __syncthreads();
     if (leader) {
       atomicAdd(&cnt[key], c);
       wcnt[wave * cb + key] = 0;
-    }
-  };
-  if (staged) {
-#pragma unroll
-    for (int it = 0; it < kLocalItems; ++it)
-      round(lk[it] != 0xffffffffu, lk[it] == 0xffffffffu ? 0u : lk[it], id[it], px[it], py[it]);
-    __syncthreads();
-    for (uint32_t i = tid; i < size; i += kLocalThreads) emit(i, t_idx[i], t_x[i], t_y[i]);
-  } else {
-    for (uint32_t r0 = s; r0 < e; r0 += kLocalThreads) {
-      const uint32_t p = r0 + tid;
-      const bool valid = p < e;
-      float fx = 0.0f, fy = 0.0f;
-      uint32_t pid = 0, key = 0;
-      if (valid) {
-        fx = bx[p];
-        fy = by[p];
-        pid = bidx[p];
-        key = cell_of(fx, fy, g) - cell0;
-      }
-      round(valid, key, pid, fx, fy);
     }
   }
 }
@@ -543,9 +642,13 @@ inline int div_up(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
 
 // Dynamic LDS of k_band_local for bands of at most cb cells.
 size_t local_lds_bytes(int cb) {
-  const size_t rank = 4 * sizeof(uint32_t) * (size_t)kLocalTile;
-  const size_t ballot = (size_t)kLocalWaves * cb + (sizeof(uint32_t) + 2 * sizeof(float)) * kLocalTile;
-  return sizeof(uint32_t) * (size_t)cb + (rank > ballot ? rank : ballot);
+  const size_t w = sizeof(uint32_t);
+  const size_t one_chunk = w * (kLocalTile / 2) + 3 * w * kLocalTile;
+  const size_t chunks = w * (kLocalTile / 2) + 3 * w * (size_t)cb;
+  const size_t ballot = (size_t)kLocalWaves * cb;
+  size_t region = one_chunk > chunks ? one_chunk : chunks;
+  region = region > ballot ? region : ballot;
+  return w * (size_t)((cb + 3) & ~3) + region;
 }
 
 }  // namespace
