@@ -83,7 +83,8 @@ def measured_rates():
 
 
 PAIR_SOURCES = {"k_interp": ("interp.hip", "pair_core.h", "api.hip"), "k_b_interp": ("batch.hip", "pair_core.h"),
-                "grid_knn": ("grid.hip", "grid_core.h", "knn.hip", "knn_core.h", "interp.hip", "api.hip")}
+                "grid_knn": ("grid.hip", "grid_band.hip", "grid_core.h", "knn.hip", "knn_core.h", "interp.hip",
+                             "api.hip")}
 HBM_PEAK = 8.0e12  # MI355X HBM3E, bytes/s
 
 
