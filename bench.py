@@ -271,6 +271,10 @@ def parse():
     ap.add_argument("--sweep-sizes", default="10,50,100,500,1000", help="sizes in units of 1024 points")
     ap.add_argument("--issue-rates", action="store_true",
                     help="only the VALU / transcendental issue-rate microbenchmark behind the pair roofline")
+    ap.add_argument("--knn-variants", action="store_true",
+                    help="only time the two kNN kernels (cache reads; cells staged in LDS) on the 2^20 and 2^18 "
+                         "workloads")
+    ap.add_argument("--knn-workloads", default="uniform_1m,clustered_256k,learned_1m")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MB",
                     help="only run a plain device copy of MB megabytes (reference for HBM traffic counters)")
     return ap.parse_args()
@@ -349,6 +353,44 @@ def issue_rates(args):
             "note": "rates per clock per CU, *_nominal at 2.4 GHz (the launch's wall time over 2.4e9 clocks); "
                     "clock_GHz is block 0's s_memtime / s_memrealtime.  A mixed stream at <= 1.0 of the serial "
                     "model means transcendentals and VALU operations do not overlap."}
+
+
+def knn_variants(args):
+    """aidw_knn on every query of each workload with the cache-read kernel and with each workgroup's cells
+    staged in LDS (aidw_set_knn_config): device time of the call (query binning included; median of 5 after
+    one warm-up) and whether the two give the same r_obs, d1^2 and index sets bit for bit."""
+    import torch
+
+    import paper_1601_05904_amd as aidw
+    from paper_1601_05904_amd import workloads as W
+
+    rows = []
+    for name in args.knn_workloads.split(","):
+        ds = W.WORKLOADS[name]()
+        t = {a: torch.from_numpy(getattr(ds, a)).cuda() for a in ("x", "y", "qx", "qy")}
+        g = aidw.build_grid(t["x"], t["y"], t["qx"], t["qy"], aidw.Params(k=ds.k))
+        res, outs = {}, {}
+        for win in (0, 1):
+            aidw.set_knn_config(win)
+            try:
+                ts = []
+                for rep in range(6):
+                    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                    e0.record()
+                    outs[win] = aidw.knn(g, t["qx"], t["qy"], ds.k, want_d1sq=True, want_idx=True)
+                    e1.record()
+                    torch.cuda.synchronize()
+                    if rep:
+                        ts.append(e0.elapsed_time(e1))
+            finally:
+                aidw.set_knn_config(0)
+            res[win] = float(np.median(ts))
+        g.close()
+        same = all(torch.equal(a, b) for a, b in zip(outs[0], outs[1]))
+        rows.append({"workload": name, "m": ds.m, "k": ds.k, "cache_read_ms": res[0], "lds_window_ms": res[1],
+                     "bitwise_equal": same})
+        print(json.dumps(rows[-1]), file=sys.stderr, flush=True)
+    return rows
 
 
 def copy_calibration(mb):
@@ -777,6 +819,9 @@ def main():
     aidw.load(build_if_missing=True)
     if args.issue_rates:
         print(json.dumps(issue_rates(args)))
+        return
+    if args.knn_variants:
+        print(json.dumps({"knn_variants": knn_variants(args), "unit": "ms"}))
         return
     if args.sweep:
         print(json.dumps({"sweep": sweep_measurement(args), "unit": "ms", "dtype": "f32",

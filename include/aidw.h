@@ -309,6 +309,18 @@ aidw_status aidw_last_timing(aidw_timing* out);
  * use w = rsq(t)^p (one transcendental instead of two). */
 aidw_status aidw_set_interp_config(int32_t q, int32_t split, int32_t integer_powers);
 
+/*
+ * kNN kernel choice for later aidw_knn / aidw_run calls on the calling thread
+ * (Section 3.2.4 and 4.1.4: the ring search over the grid): lds_window = 0
+ * (default) reads every candidate through the caches; 1 stages, per workgroup
+ * of 256 binned queries, the cells within two of theirs (when they fit 2048
+ * points) in LDS and reads the candidates of those cells from there.  Both give
+ * the same index sets, r_obs and d1^2 bit for bit; the choice applies to query
+ * sets of 2^17 or more (smaller ones take the four-lanes-per-query kernel).
+ * Errors: AIDW_EINVAL for any other value.
+ */
+aidw_status aidw_set_knn_config(int32_t lds_window);
+
 /* ---------------------------------------------------------------------------
  * Learned-R form.  A small network predicts the nearest-neighbour statistic R
  * of Eq. 4 from the grid's occupancy around each query (inputs: the counts of

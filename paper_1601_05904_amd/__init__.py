@@ -148,6 +148,7 @@ def load(build_if_missing: bool = True):
     L.aidw_set_timing.argtypes = [ctypes.c_int]
     L.aidw_last_timing.argtypes = [P(_Timing)]
     L.aidw_set_interp_config.argtypes = [i32, i32, i32]
+    L.aidw_set_knn_config.argtypes = [i32]
     L.aidw_release_cached_memory.argtypes = []
     L.aidw_status_string.argtypes = [ctypes.c_int]
     L.aidw_status_string.restype = ctypes.c_char_p
@@ -186,7 +187,8 @@ def load(build_if_missing: bool = True):
     L.aidw_batch_tune.argtypes = [P(_Job), i32, P(_BatchConfig), i32, i32, P(ctypes.c_float), _VP]
     for name in ("aidw_build_grid", "aidw_nn_statistic", "aidw_grid_describe", "aidw_grid_info", "aidw_grid_arrays", "aidw_grid_copy_arrays", "aidw_knn",
                  "aidw_interpolate", "aidw_run", "aidw_knn_paper", "aidw_knn_bruteforce", "aidw_interpolate_naive",
-                 "aidw_set_timing", "aidw_last_timing", "aidw_set_interp_config",
+                 "aidw_set_timing", "aidw_last_timing", "aidw_set_interp_config", "aidw_set_knn_config",
+                 "aidw_run_noalloc",
                  "aidw_mlp_create", "aidw_mlp_set_params", "aidw_mlp_get_params", "aidw_mlp_save", "aidw_mlp_load",
                  "aidw_features", "aidw_mlp_forward", "aidw_mlp_gradients", "aidw_mlp_train", "aidw_run_learned",
                  "aidw_learned_routes",
@@ -380,6 +382,12 @@ def set_interp_config(q: int = 0, split: int = 0, integer_powers: int = -1):
     """Pair-kernel launch shape for later calls on this thread (0 = built-in choice);
     integer_powers = 0 forces the general exp2/log2 weight for every query."""
     _check(load().aidw_set_interp_config(int(q), int(split), int(integer_powers)))
+
+
+def set_knn_config(lds_window: bool):
+    """aidw_set_knn_config: stage each workgroup's cells in LDS in the one-lane kNN (later calls on
+    this thread)."""
+    _check(load().aidw_set_knn_config(1 if lds_window else 0))
 
 
 def release_cached_memory():

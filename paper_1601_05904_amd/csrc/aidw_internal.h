@@ -24,6 +24,17 @@ struct GridScalars {
 };
 
 // Per-block partial of the bounds reduction.
+// Workgroups are dealt to the chip's 8 XCDs in turn (workgroup b to XCD b mod 8), and each XCD
+// has its own L2.  This maps the hardware workgroup id to a logical one so that XCD x takes a
+// contiguous range of logical workgroups: with binned queries, an XCD then reads one region
+// of the grid through its L2 instead of every region.  A bijection of [0, nblk).
+__device__ inline int xcd_block(int bid, int nblk) {
+  constexpr int kXcds = 8;
+  const int per = nblk / kXcds, rem = nblk % kXcds;
+  const int x = bid % kXcds, s = bid / kXcds;
+  return x * per + min(x, rem) + s;
+}
+
 struct BoundsPartial {
   float minx, miny, maxx, maxy;
   int32_t nonfinite;
@@ -170,6 +181,10 @@ hipError_t launch_knn(const GridScalars* gs, const int32_t* cell_start, const fl
                       const int32_t* sidx, const float* qx, const float* qy, const uint32_t* qperm,
                       const uint32_t* active, int m, int k, float* r_obs, float* d1sq, int32_t* nn_idx,
                       hipStream_t s);
+// The same search with each workgroup's neighbourhood of cells staged in LDS (k_knn_window).
+hipError_t launch_knn_window(const GridScalars* gs, const int32_t* cell_start, const float* sx, const float* sy,
+                             const int32_t* sidx, const float* qx, const float* qy, const uint32_t* qperm, int m, int k,
+                             float* r_obs, float* d1sq, int32_t* nn_idx, hipStream_t s);
 // Brute-force kNN over all n points per query (the method the grid search replaces); exact.
 hipError_t launch_knn_brute(const float* x, const float* y, int n, const float* qx, const float* qy, int m, int k,
                             float* r_obs, float* d1sq, int32_t* nn_idx, hipStream_t s);

@@ -21,6 +21,7 @@ thread_local std::string g_detail;
 thread_local int g_timing = 0;
 thread_local int g_cfg_q = 0, g_cfg_split = 0, g_cfg_intpow = 1;
 thread_local int g_split_cap = 0;  // > 0: at most this many data-axis splits (aidw_run_noalloc)
+thread_local int g_knn_window = 0;  // 1: the one-lane kNN stages each workgroup's cells in LDS
 
 // A fixed device region that a call carves its temporaries from instead of allocating
 // (aidw_run_noalloc): 256-byte aligned pieces in request order, nothing is freed.
@@ -449,6 +450,12 @@ aidw_status knn_impl(const aidw_grid* g, const float* qx, const float* qy, int64
     return AIDW_OK;
   }
   // below 2^17 queries one lane per query leaves the chip idle: four lanes share each query
+  if (m >= (1 << 17) && g_knn_window) {
+    HIP_TRY(launch_knn_window(g->dev, g->cell_start, g->sx, g->sy, g->sidx, qx, qy, order, (int)m, k, r_obs, d1sq,
+                              nn_idx, s),
+            "kNN kernel (LDS window)");
+    return AIDW_OK;
+  }
   auto knn = m < (1 << 17) ? launch_knn4 : launch_knn;
   HIP_TRY(knn(g->dev, g->cell_start, g->sx, g->sy, g->sidx, qx, qy, order, nullptr, (int)m, k, r_obs, d1sq, nn_idx, s),
           "kNN kernel");
@@ -1322,6 +1329,13 @@ aidw_status aidw_last_timing(aidw_timing* out) {
   out->finish_ms = d;
   out->interp_q = g_tm.q;
   out->interp_split = g_tm.split;
+  return AIDW_OK;
+}
+
+aidw_status aidw_set_knn_config(int32_t lds_window) {
+  g_detail.clear();
+  if (lds_window != 0 && lds_window != 1) return fail(AIDW_EINVAL, "lds_window must be 0 or 1");
+  g_knn_window = lds_window;
   return AIDW_OK;
 }
 

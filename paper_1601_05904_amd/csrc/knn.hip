@@ -33,6 +33,7 @@ namespace aidw {
 
 namespace {
 
+
 template <int KMAX, bool PAPER = false>
 __global__ __launch_bounds__(256) void k_knn(const GridScalars* __restrict__ gs, const int32_t* __restrict__ cell_start,
                                              const float* __restrict__ sx, const float* __restrict__ sy,
@@ -41,7 +42,10 @@ __global__ __launch_bounds__(256) void k_knn(const GridScalars* __restrict__ gs,
                                              const uint32_t* __restrict__ active, int m, int k,
                                              float* __restrict__ r_obs, float* __restrict__ d1sq,
                                              int32_t* __restrict__ nn_idx) {
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  // XCD-aware order only when every workgroup has queries (with a device-side count, the live
+  // workgroups are the first ones, which the remap would put on one XCD)
+  const int blk = active ? (int)blockIdx.x : xcd_block(blockIdx.x, gridDim.x);
+  const int t = blk * blockDim.x + threadIdx.x;
   if (t >= m || (active && (uint32_t)t >= *active) || gs->status != AIDW_OK) return;
   const double slack = slack_cells(gs->ncol, gs->nrow);
   const int q = qperm ? (int)qperm[t] : t;
@@ -50,6 +54,93 @@ __global__ __launch_bounds__(256) void k_knn(const GridScalars* __restrict__ gs,
   double bk[KMAX];
   int32_t bi[KMAX];
   knn::search<KMAX, 1, PAPER>(g, cell_start, sx, sy, sidx, fx, fy, k, slack, bk, bi);
+  float ro, d1;
+  knn::summarise<KMAX>(bk, k, ro, d1);
+  r_obs[q] = ro;
+  if (d1sq) d1sq[q] = d1;
+  if (nn_idx) {
+    int32_t* row = nn_idx + (size_t)q * k;
+#pragma unroll
+    for (int s = 0; s < KMAX; ++s)
+      if (s >= KMAX - k) row[s - (KMAX - k)] = bi[s];
+  }
+}
+
+// The kNN of 256 binned queries per workgroup with their cells' neighbourhood staged in LDS:
+// the queries of a workgroup lie in consecutive cells of one grid row (or two), so the window
+// is that column range widened by kWinHalo cells on each side over the rows within kWinHalo of
+// theirs (all columns when the queries span two rows).  A window row is one contiguous run of
+// the cell-ordered arrays, copied with coalesced loads.  A segment of a ring inside the window
+// is read from LDS, any other from global memory; a window of more than kWinCap points is not
+// staged (every read goes to global memory, as in k_knn).
+constexpr int kWinHalo = 2;
+constexpr int kWinCap = 2048;
+constexpr int kWinRowsMax = 2 + 2 * kWinHalo;
+template <int KMAX>
+__global__ __launch_bounds__(256) void k_knn_window(const GridScalars* __restrict__ gs,
+                                                    const int32_t* __restrict__ cell_start,
+                                                    const float* __restrict__ sx, const float* __restrict__ sy,
+                                                    const int32_t* __restrict__ sidx, const float* __restrict__ qx,
+                                                    const float* __restrict__ qy, const uint32_t* __restrict__ qperm,
+                                                    int m, int k, float* __restrict__ r_obs, float* __restrict__ d1sq,
+                                                    int32_t* __restrict__ nn_idx) {
+  __shared__ float w_x[kWinCap], w_y[kWinCap];
+  __shared__ int32_t w_i[kWinCap];
+  __shared__ int w_p0[kWinRowsMax], w_base[kWinRowsMax + 1], w_off[kWinRowsMax];
+  __shared__ int w_dims[4];  // r0, r1 (r1 < r0: no window), c0, c1
+  if (gs->status != AIDW_OK) return;
+  const knn::View g{gs->minx, gs->miny, gs->inv_cw, gs->ncol, gs->nrow, gs->cwd};
+  const int ncol = g.ncol, nrow = g.nrow;
+  const int t0 = xcd_block(blockIdx.x, gridDim.x) * blockDim.x;
+  const int t = t0 + threadIdx.x;
+  if (threadIdx.x == 0) {
+    // the first and last query of the workgroup bound its cells (binned order is cell order)
+    const int qa = qperm ? (int)qperm[t0] : t0;
+    const int tl = min(m - 1, t0 + (int)blockDim.x - 1);
+    const int qb = qperm ? (int)qperm[tl] : tl;
+    const int ca = knn::clamp_cell((qx[qa] - g.minx) * g.inv, ncol), ra = knn::clamp_cell((qy[qa] - g.miny) * g.inv, nrow);
+    const int cb = knn::clamp_cell((qx[qb] - g.minx) * g.inv, ncol), rb = knn::clamp_cell((qy[qb] - g.miny) * g.inv, nrow);
+    int r0 = max(0, min(ra, rb) - kWinHalo), r1 = min(nrow - 1, max(ra, rb) + kWinHalo);
+    int c0 = 0, c1 = ncol - 1;
+    if (ra == rb) {
+      c0 = max(0, min(ca, cb) - kWinHalo);
+      c1 = min(ncol - 1, max(ca, cb) + kWinHalo);
+    }
+    if (r1 - r0 + 1 > kWinRowsMax) r1 = r0 - 1;
+    int total = 0;
+    for (int r = r0; r <= r1; ++r) {
+      const int p0 = cell_start[r * ncol + c0], p1 = cell_start[r * ncol + c1 + 1];
+      w_p0[r - r0] = p0;
+      w_base[r - r0] = total;
+      w_off[r - r0] = total - p0;
+      total += p1 - p0;
+    }
+    if (total > kWinCap) r1 = r0 - 1;
+    w_base[r1 >= r0 ? r1 - r0 + 1 : 0] = total;
+    w_dims[0] = r0;
+    w_dims[1] = r1;
+    w_dims[2] = c0;
+    w_dims[3] = c1;
+  }
+  __syncthreads();
+  const int r0 = w_dims[0], r1 = w_dims[1];
+  const int nrows = r1 >= r0 ? r1 - r0 + 1 : 0;
+  for (int r = 0; r < nrows; ++r) {
+    const int b0 = w_base[r], len = w_base[r + 1] - b0, p0 = w_p0[r];
+    for (int i = threadIdx.x; i < len; i += blockDim.x) {
+      w_x[b0 + i] = sx[p0 + i];
+      w_y[b0 + i] = sy[p0 + i];
+      w_i[b0 + i] = sidx[p0 + i];
+    }
+  }
+  __syncthreads();
+  if (t >= m) return;
+  const knn::Window win{r0, r1, w_dims[2], w_dims[3], w_off, w_x, w_y, w_i};
+  const double slack = slack_cells(ncol, nrow);
+  const int q = qperm ? (int)qperm[t] : t;
+  double bk[KMAX];
+  int32_t bi[KMAX];
+  knn::search<KMAX, 1, false, true>(g, cell_start, sx, sy, sidx, qx[q], qy[q], k, slack, bk, bi, 0, &win);
   float ro, d1;
   knn::summarise<KMAX>(bk, k, ro, d1);
   r_obs[q] = ro;
@@ -74,7 +165,9 @@ __global__ __launch_bounds__(256) void k_knn_lanes(const GridScalars* __restrict
                                               float* __restrict__ r_obs, float* __restrict__ d1sq,
                                               int32_t* __restrict__ nn_idx, AlphaParams ap,
                                               float* __restrict__ alpha_f) {
-  const int gt = blockIdx.x * blockDim.x + threadIdx.x;
+  // XCD-aware order only without a device-side count (see k_knn)
+  const int blk = active ? (int)blockIdx.x : xcd_block(blockIdx.x, gridDim.x);
+  const int gt = blk * blockDim.x + threadIdx.x;
   const int t = gt / LANES, sub = gt % LANES;
   // the lanes of a query leave together
   if (t >= m || (active && (uint32_t)t >= *active) || gs->status != AIDW_OK) return;
@@ -228,6 +321,19 @@ hipError_t launch_knn4(const GridScalars* gs, const int32_t* cell_start, const f
                        const uint32_t* active, int m, int k, float* r_obs, float* d1sq, int32_t* nn_idx,
                        hipStream_t s) {
   return launch_knn_lanes(gs, cell_start, sx, sy, sidx, qx, qy, qperm, active, m, k, r_obs, d1sq, nn_idx, 4, s);
+}
+
+hipError_t launch_knn_window(const GridScalars* gs, const int32_t* cell_start, const float* sx, const float* sy,
+                             const int32_t* sidx, const float* qx, const float* qy, const uint32_t* qperm, int m, int k,
+                             float* r_obs, float* d1sq, int32_t* nn_idx, hipStream_t s) {
+  if (m <= 0) return hipSuccess;
+  const dim3 grid((m + 255) / 256), block(256);
+#define AIDW_KNNW(K)                                                                                            \
+  hipLaunchKernelGGL(k_knn_window<K>, grid, block, 0, s, gs, cell_start, sx, sy, sidx, qx, qy, qperm, m, k, r_obs, \
+                     d1sq, nn_idx)
+  AIDW_FOR_KNN_SLOTS(k, AIDW_KNNW)
+#undef AIDW_KNNW
+  return hipGetLastError();
 }
 
 hipError_t launch_knn(const GridScalars* gs, const int32_t* cell_start, const float* sx, const float* sy,

@@ -59,11 +59,25 @@ __device__ __forceinline__ double group_kth(const double (&bk)[KMAX], int k) {
   return v;
 }
 
-template <int KMAX, int LANES = 1, bool PAPER = false>
+// A copy of part of the grid in LDS: rows [r0, r1], columns [c0, c1] (rows empty when r1 < r0).
+// Each of its rows is one contiguous run of the cell-ordered arrays; row r's points sit at
+// x[p + off[r - r0]] (and y, idx) for the global position p.  The pointers are generic, so a
+// lane reads a segment from LDS or from global memory with the same loads; the pointers stay
+// at the arrays' starts and the shift goes into the index, which is in range.
+struct Window {
+  int r0, r1, c0, c1;
+  const int* off;
+  const float* x;
+  const float* y;
+  const int32_t* idx;
+};
+
+template <int KMAX, int LANES = 1, bool PAPER = false, bool WIN = false>
 __device__ __forceinline__ void search(const View& g, const int32_t* __restrict__ cell_start,
                                        const float* __restrict__ sx, const float* __restrict__ sy,
                                        const int32_t* __restrict__ sidx, float fx, float fy, int k,
-                                       double slack_cells, double (&bk)[KMAX], int32_t (&bi)[KMAX], int sub = 0) {
+                                       double slack_cells, double (&bk)[KMAX], int32_t (&bi)[KMAX], int sub = 0,
+                                       const Window* win = nullptr) {
   const double px = fx, py = fy;
   const int ncol = g.ncol, nrow = g.nrow;
   const double cwd = g.cwd;
@@ -120,11 +134,23 @@ __device__ __forceinline__ void search(const View& g, const int32_t* __restrict_
       const int p0 = cell_start[base + a];
       const int p1 = cell_start[base + b + 1];
       count += p1 - p0;
+      const float* X = sx;
+      const float* Y = sy;
+      const int32_t* I = sidx;
+      int shift = 0;
+      if constexpr (WIN) {
+        if (row >= win->r0 && row <= win->r1 && a >= win->c0 && b <= win->c1) {
+          shift = win->off[row - win->r0];
+          X = win->x;
+          Y = win->y;
+          I = win->idx;
+        }
+      }
       for (int p = p0 + sub; p < p1; p += LANES) {
-        const double dx = (double)sx[p] - px;
-        const double dy = (double)sy[p] - py;
+        const double dx = (double)X[p + shift] - px;
+        const double dy = (double)Y[p + shift] - py;
         const double d2 = dx * dx + dy * dy;
-        const int32_t id = sidx[p];
+        const int32_t id = I[p + shift];
         // the comparisons of the (d2, index) order are combined with bitwise operators: each is
         // then one vector compare, where short-circuit forms compile to branches on the exec mask
         const bool take = (d2 < bk[KMAX - 1]) | ((d2 == bk[KMAX - 1]) & (id < bi[KMAX - 1]));

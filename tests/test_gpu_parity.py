@@ -349,6 +349,38 @@ def test_full_size_sampled(T, name):
     assert T.equal(ro2, ro) and T.equal(al2, al) and T.equal(qz2, qz)
 
 
+@pytest.mark.parametrize("name", ["uniform_1m", "clustered_256k", "ragged_rect"])
+def test_knn_lds_window_equals_cache_read(T, name):
+    """The kNN with each workgroup's cells staged in LDS (aidw_set_knn_config(1)) gives every
+    query the same index set, r_obs and d1^2 bit for bit as the cache-read kernel, and index sets
+    equal to the oracle's brute force on sampled queries.  ragged_rect: 2^17 + 37 queries over a
+    1/4 x 1 rectangle (a ragged last workgroup, windows at the grid's edges)."""
+    aidw = aidw_mod()
+    if name == "ragged_rect":
+        ds = W.make(90001, (1 << 17) + 37, 7, 41)
+        ds.x = (ds.x * np.float32(0.25)).astype(np.float32)
+        ds.qx = (ds.qx * np.float32(0.25)).astype(np.float32)
+    else:
+        ds = W.WORKLOADS[name]()
+    x, y, z, qx, qy = upload(T, ds)
+    p = aidw.Params(k=ds.k)
+    g = aidw.build_grid(x, y, qx, qy, p)
+    out = []
+    for win in (0, 1):
+        aidw.set_knn_config(win)
+        try:
+            out.append(aidw.knn(g, qx, qy, ds.k, want_d1sq=True, want_idx=True))
+            T.cuda.synchronize()
+        finally:
+            aidw.set_knn_config(0)
+    g.close()
+    for a, b in zip(out[0], out[1]):
+        assert T.equal(a, b)
+    sel = W.sample_queries(ds.m, 1024, ds.seed)
+    ref_i, _ = O.knn(ds.x, ds.y, ds.qx[sel], ds.qy[sel], ds.k)
+    assert np.array_equal(out[1][2].cpu().numpy()[sel], ref_i)
+
+
 # ------------------------------------------------------------------ the paper's stop rule
 
 @pytest.mark.parametrize("case", ["constructed_miss", "uniform_4k_cw_rexp", "mixture_cw_rexp", "uniform_occ2"])
