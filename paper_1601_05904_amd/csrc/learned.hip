@@ -586,8 +586,8 @@ __global__ __launch_bounds__(256) void k_mlp_forward_mfma(MlpDevice d, const flo
 // there the registers of the loads in flight across the network spill 3 dwords to scratch,
 // which still measured faster than issuing those loads after the network (no spill) or
 // than three wavefronts per SIMD.
-// kCert: the certificate, from block counts and 3 x 3 distances (rules 2, 3); kNet: the network
-// (rules 0, 1, 3).
+// kCert: the certificate, from block counts and 3 x 3 distances (rules 3, 4; rule 2, the
+// certificate alone, runs k_cert_front); kNet: the network (rules 0, 1, 3, 4).
 template <bool kCert, bool kNet>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_learned_front(
     MlpDevice d, const GridScalars* __restrict__ gs, const int32_t* __restrict__ cell_start,
@@ -847,6 +847,125 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
   }
 }
 
+
+// The front of rule 2 (the certificate alone, no network), one lane per query: the queries of
+// a wavefront are 64 consecutive positions of the binned order, so they share most of their
+// blocks' cells.  It makes the decision and writes the outputs that k_learned_front would with
+// the certificate and without the network (whose matrix operands are what the tiles of 16
+// queries there exist for): c_0, c_1, c_2 are differences of row offsets (a row of a block is
+// one run of the cell order), the certificate from the counts, then, for a query it certifies
+// or may still certify, one scan of the 3 x 3 block (three runs) for the nearest distance and
+// the statistics below D_1.
+__global__ __launch_bounds__(256) void k_cert_front(const GridScalars* __restrict__ gs,
+                                                    const int32_t* __restrict__ cell_start,
+                                                    const float* __restrict__ sx, const float* __restrict__ sy,
+                                                    const float* __restrict__ qx, const float* __restrict__ qy,
+                                                    const uint32_t* __restrict__ perm, int m, AlphaParams ap, int k,
+                                                    double cert_factor, uint32_t* __restrict__ flag,
+                                                    float* __restrict__ alpha_f, float* __restrict__ d1sq,
+                                                    float* __restrict__ r_hat_out, uint8_t* __restrict__ route) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= m || gs->status != AIDW_OK) return;
+  const int q = perm ? (int)perm[t] : t;
+  const float minx = gs->minx, miny = gs->miny, inv = gs->inv_cw;
+  const int ncol = gs->ncol, nrow = gs->nrow;
+  const double cwd = gs->cwd, minxd = minx, minyd = miny;
+  const double slack_cells = aidw::slack_cells(ncol, nrow);
+  const float fx = qx[q], fy = qy[q];
+  const int c0 = clamp_cell((fx - minx) * inv, ncol), r0 = clamp_cell((fy - miny) * inv, nrow);
+  // row runs of the blocks: columns [c0 - L, c0 + L] clamped, so a run's end is the start of
+  // the cell after it (the next row's first cell at the right edge)
+  const int a2 = max(c0 - 2, 0), e2 = min(c0 + 3, ncol), a1 = max(c0 - 1, 0), e1 = min(c0 + 2, ncol);
+  int s1[3], t1[3];
+  int n2 = 0;
+#pragma unroll
+  for (int i = 0; i < 5; ++i) {
+    const int r = r0 - 2 + i;
+    const bool in = r >= 0 && r < nrow;
+    const int base = in ? r * ncol : 0;
+    const int u = in ? cell_start[base + a2] : 0, v = in ? cell_start[base + e2] : 0;
+    n2 += v - u;
+    if (i >= 1 && i <= 3) {
+      s1[i - 1] = in ? cell_start[base + a1] : 0;
+      t1[i - 1] = in ? cell_start[base + e1] : 0;
+    }
+  }
+  const int n1 = (t1[0] - s1[0]) + (t1[1] - s1[1]) + (t1[2] - s1[2]);
+  const int n0 = cell_start[r0 * ncol + c0 + 1] - cell_start[r0 * ncol + c0];
+  const double px = fx, py = fy;
+  const double cert_sum_min = cert_factor * gs->r_exp;
+  bool cert = certified_saturated(px, py, c0, r0, ncol, nrow, minxd, minyd, cwd, slack_cells, n0, n1, n2, k,
+                                  cert_sum_min);
+  const bool cert_counts = cert;
+  // mode 0: the exact kNN in any case (no scan); 1: certified, needs d1; 2: may be certified
+  // by the distances (a 3 x 3 block over 8 k + 16 points is left to the exact path)
+  const int mode = cert ? 1 : (n1 <= 8 * k + 16 ? 2 : 0);
+  float best = INFINITY;
+  bool hit = false;
+  double d_1 = 0.0, v_sum = 0.0;
+  float d_1sq = 0.0f, v_max = 0.0f;
+  int v_cnt = 0;
+  if (mode == 2) {
+    d_1 = block_side_distance(px, py, c0, r0, 1, ncol, nrow, minxd, minyd, cwd, slack_cells);
+    d_1sq = (float)(d_1 * d_1);
+  }
+  if (mode != 0) {
+    // four points per step, their loads issued together
+    constexpr int kStep = 4;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      for (int p = s1[i]; p < t1[i]; p += kStep) {
+        float px4[kStep], py4[kStep];
+#pragma unroll
+        for (int j = 0; j < kStep; ++j) {
+          const bool in = p + j < t1[i];
+          px4[j] = in ? sx[p + j] : INFINITY;
+          py4[j] = in ? sy[p + j] : INFINITY;
+        }
+#pragma unroll
+        for (int j = 0; j < kStep; ++j) {
+          if (p + j >= t1[i]) break;
+          const float dx = px4[j] - fx, dy = py4[j] - fy;
+          const float dd = __builtin_fmaf(dx, dx, dy * dy);
+          hit |= (dx == 0.0f) & (dy == 0.0f);
+          best = fminf(best, dd);
+          if (dd < d_1sq) {
+            const float dist = __builtin_sqrtf(dd);
+            v_sum += (double)dist;
+            v_max = fmaxf(v_max, dist);
+            ++v_cnt;
+          }
+        }
+      }
+    }
+  }
+  // d1: the block's nearest when it lies within the block's open sides (less the slack),
+  // else that distance as a lower bound
+  double dout = INFINITY;
+  if (c0 - 1 > 0) dout = fmin(dout, px - (minxd + (double)(c0 - 1) * cwd));
+  if (c0 + 1 < ncol - 1) dout = fmin(dout, (minxd + (double)(c0 + 2) * cwd) - px);
+  if (r0 - 1 > 0) dout = fmin(dout, py - (minyd + (double)(r0 - 1) * cwd));
+  if (r0 + 1 < nrow - 1) dout = fmin(dout, (minyd + (double)(r0 + 2) * cwd) - py);
+  dout -= slack_cells * cwd;
+  const double v = (dout == INFINITY || (double)best < dout * dout) ? (double)best : (dout > 0 ? dout * dout : 0.0);
+  const float d1 = hit ? 0.0f : fmaxf((float)v, FLT_MIN);
+  bool fall = true;
+  if (mode != 0 && d1 != 0.0f) {
+    if (mode == 2)
+      cert = certified_by_distances(
+          v_sum, v_cnt, v_max, n2, k, d_1,
+          block_side_distance(px, py, c0, r0, 2, ncol, nrow, minxd, minyd, cwd, slack_cells), cert_sum_min);
+    fall = !cert;
+  }
+  flag[t] = fall ? 1u : 0u;
+  if (!fall) {
+    alpha_f[q] = (float)ap.levels[4];
+    d1sq[q] = d1;
+  }
+  if (r_hat_out) r_hat_out[q] = __builtin_nanf("");
+  if (route) route[q] = fall ? (mode == 2 ? 1 : 0) : (cert_counts ? 2 : 3);
+}
+
 }  // namespace
 
 hipError_t launch_features(const GridScalars* gs, const int32_t* cell_start, const float* sx, const float* sy,
@@ -899,9 +1018,10 @@ hipError_t launch_learned_front(const MlpDevice& d, const GridScalars* gs, const
   hipLaunchKernelGGL((k_learned_front<CERT, NET>), dim3(tile_blocks((const void*)k_learned_front<CERT, NET>, m)), \
                      dim3(256), 0, s, d, gs, cell_start, sx, sy, qx, qy, perm, m, n, ap, rule, delta, r_sat_lo,   \
                      r_sat_hi, k, cert_factor, flag, alpha_f, d1sq, r_hat_out, route)
-  if (rule == 2)
-    FRONT(true, false);
-  else if (rule == 3 || rule == 4)
+  if (rule == 2) {
+    hipLaunchKernelGGL(k_cert_front, dim3((m + 255) / 256), dim3(256), 0, s, gs, cell_start, sx, sy, qx, qy, perm, m,
+                       ap, k, cert_factor, flag, alpha_f, d1sq, r_hat_out, route);
+  } else if (rule == 3 || rule == 4)
     FRONT(true, true);
   else
     FRONT(false, true);
