@@ -501,6 +501,17 @@ struct MfmaNet {
 };
 constexpr int kNetOperands = 4 * 64 + 8 * 64;
 
+// The same operands read from global memory (through the caches), for a kernel that runs the
+// network only on some of its wavefronts.
+struct MfmaNetGlobal {
+  const uint4* w1a;
+  const uint4* w2a;
+  __device__ inline bf16x8_t w1(int t, int lane) const { return __builtin_bit_cast(bf16x8_t, w1a[t * 64 + lane]); }
+  __device__ inline bf16x8_t w2(int t, int st, int lane) const {
+    return __builtin_bit_cast(bf16x8_t, w2a[(t * 2 + st) * 64 + lane]);
+  }
+};
+
 __device__ inline bf16x8_t as_bf16x8(uint4 v) { return __builtin_bit_cast(bf16x8_t, v); }
 
 // Copies the operands into the workgroup's LDS (every thread of the workgroup calls it).
@@ -514,7 +525,8 @@ __device__ inline MfmaNet stage_net(const MlpDevice& d, uint4* lds) {
 
 // R_hat of query (lane & 15) from its 8 packed bf16 inputs held by lane (the 4 lanes of a
 // query return the same value).
-__device__ inline float mlp_tile(const MlpDevice& d, const MfmaNet& net, int lane, uint4 x) {
+template <typename Net>
+__device__ inline float mlp_tile(const MlpDevice& d, const Net& net, int lane, uint4 x) {
   const int g = lane >> 4;
   floatx4_t a1[4];
 #pragma unroll
@@ -848,31 +860,45 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
 }
 
 
-// The front of rule 2 (the certificate alone, no network), one lane per query: the queries of
-// a wavefront are 64 consecutive positions of the binned order, so they share most of their
-// blocks' cells.  It makes the decision and writes the outputs that k_learned_front would with
-// the certificate and without the network (whose matrix operands are what the tiles of 16
-// queries there exist for): c_0, c_1, c_2 are differences of row offsets (a row of a block is
-// one run of the cell order), the certificate from the counts, then, for a query it certifies
-// or may still certify, one scan of the 3 x 3 block (three runs) for the nearest distance and
-// the statistics below D_1.
-__global__ __launch_bounds__(256) void k_cert_front(const GridScalars* __restrict__ gs,
+// The front of rules 2 and 4, one lane per query: the queries of a wavefront are 64
+// consecutive positions of the binned order, so they share most of their blocks' cells.  It
+// makes the decision and writes the outputs that k_learned_front would with the certificate
+// (whose tiles of 16 queries exist for the network's matrix operands on every query):
+// c_0, c_1, c_2 are differences of row offsets (a row of a block is one run of the cell
+// order), the certificate from the counts, then, for a query it certifies or may still
+// certify, one scan of the 3 x 3 block (three runs) for the nearest distance and the
+// statistics below D_1.
+// kGate (rule 4): the network decides which of the queries the counts leave open are scanned.
+// A wavefront gathers those queries (a ballot), stores their 27 features as bf16 in LDS in
+// the order of their lanes, and runs the network on the matrix cores over tiles of 16 of
+// them, so a wavefront without such a query does not evaluate it.  r_hat_out receives the
+// prediction for those queries and NaN for the others.
+template <bool kGate>
+__global__ __launch_bounds__(256) void k_cert_front(MlpDevice d, const GridScalars* __restrict__ gs,
                                                     const int32_t* __restrict__ cell_start,
                                                     const float* __restrict__ sx, const float* __restrict__ sy,
                                                     const float* __restrict__ qx, const float* __restrict__ qy,
-                                                    const uint32_t* __restrict__ perm, int m, AlphaParams ap, int k,
-                                                    double cert_factor, uint32_t* __restrict__ flag,
-                                                    float* __restrict__ alpha_f, float* __restrict__ d1sq,
-                                                    float* __restrict__ r_hat_out, uint8_t* __restrict__ route) {
+                                                    const uint32_t* __restrict__ perm, int m, int64_t n,
+                                                    AlphaParams ap, int k, double cert_factor, double gate_min,
+                                                    uint32_t* __restrict__ flag, float* __restrict__ alpha_f,
+                                                    float* __restrict__ d1sq, float* __restrict__ r_hat_out,
+                                                    uint8_t* __restrict__ route) {
+  constexpr int kWaves = 256 / 64;
+  __shared__ __align__(16) uint16_t s_feat[kGate ? kWaves : 1][64][32];  // bf16 bits, 27 used
+  __shared__ float s_y[kGate ? kWaves : 1][64];
+  if (gs->status != AIDW_OK) return;  // a failed grid build: nothing to decide (the whole grid)
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= m || gs->status != AIDW_OK) return;
-  const int q = perm ? (int)perm[t] : t;
+  // with the network every lane stays to the barriers; without it the tail leaves at once
+  const bool valid = t < m;
+  if (!kGate && !valid) return;
+  const int q = valid ? (perm ? (int)perm[t] : t) : 0;
   const float minx = gs->minx, miny = gs->miny, inv = gs->inv_cw;
   const int ncol = gs->ncol, nrow = gs->nrow;
   const double cwd = gs->cwd, minxd = minx, minyd = miny;
   const double slack_cells = aidw::slack_cells(ncol, nrow);
-  const float fx = qx[q], fy = qy[q];
-  const int c0 = clamp_cell((fx - minx) * inv, ncol), r0 = clamp_cell((fy - miny) * inv, nrow);
+  const float fx = valid ? qx[q] : minx, fy = valid ? qy[q] : miny;
+  const float tx = (fx - minx) * inv, ty = (fy - miny) * inv;
+  const int c0 = clamp_cell(tx, ncol), r0 = clamp_cell(ty, nrow);
   // row runs of the blocks: columns [c0 - L, c0 + L] clamped, so a run's end is the start of
   // the cell after it (the next row's first cell at the right edge)
   const int a2 = max(c0 - 2, 0), e2 = min(c0 + 3, ncol), a1 = max(c0 - 1, 0), e1 = min(c0 + 2, ncol);
@@ -894,12 +920,58 @@ __global__ __launch_bounds__(256) void k_cert_front(const GridScalars* __restric
   const int n0 = cell_start[r0 * ncol + c0 + 1] - cell_start[r0 * ncol + c0];
   const double px = fx, py = fy;
   const double cert_sum_min = cert_factor * gs->r_exp;
-  bool cert = certified_saturated(px, py, c0, r0, ncol, nrow, minxd, minyd, cwd, slack_cells, n0, n1, n2, k,
-                                  cert_sum_min);
+  bool cert = valid && certified_saturated(px, py, c0, r0, ncol, nrow, minxd, minyd, cwd, slack_cells, n0, n1, n2,
+                                           k, cert_sum_min);
   const bool cert_counts = cert;
+  // the queries the counts leave open whose 3 x 3 block the certificate may scan (a block over
+  // 8 k + 16 points is left to the exact path: such a query's R lies far below saturation)
+  const bool open = valid && !cert && n1 <= 8 * k + 16;
+  bool scan = open;
+  float y = __builtin_nanf("");
+  if constexpr (kGate) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const uint64_t open_mask = __ballot(open);
+    const int nopen = __popcll(open_mask);
+    const int slot = __popcll(open_mask & (lane == 0 ? 0ull : (~0ull >> (64 - lane))));
+    if (open) {
+      // the 27 features: counts of the 5 x 5 block (row-major) over the mean occupancy, then
+      // the offset inside the cell (a count is the difference of two offsets; columns clamped
+      // to [0, ncol] count 0 beyond the edges, rows outside the grid count 0)
+      const double inv_occ = (double)gs->ncells / (double)n;
+      uint16_t* f = s_feat[wave][slot];
+#pragma unroll
+      for (int br = 0; br < 5; ++br) {
+        const int r = r0 + br - 2;
+        const bool in = r >= 0 && r < nrow;
+        int o[6];
+#pragma unroll
+        for (int j = 0; j < 6; ++j) o[j] = in ? cell_start[r * ncol + min(max(c0 + j - 2, 0), ncol)] : 0;
+#pragma unroll
+        for (int bc = 0; bc < 5; ++bc)
+          f[5 * br + bc] = __builtin_bit_cast(uint16_t, (__bf16)(float)((double)(o[bc + 1] - o[bc]) * inv_occ));
+      }
+      f[25] = __builtin_bit_cast(uint16_t, (__bf16)(tx - (float)c0));
+      f[26] = __builtin_bit_cast(uint16_t, (__bf16)(ty - (float)r0));
+#pragma unroll
+      for (int j = 27; j < 32; ++j) f[j] = 0;
+    }
+    __syncthreads();
+    const MfmaNetGlobal net{reinterpret_cast<const uint4*>(d.w1a), reinterpret_cast<const uint4*>(d.w2a)};
+    for (int tile = 0; tile * 16 < nopen; ++tile) {  // uniform over the wavefront: every lane runs the MFMA
+      const int c = lane & 15, g = lane >> 4, sl = tile * 16 + c;
+      const uint4 x = sl < nopen ? *reinterpret_cast<const uint4*>(&s_feat[wave][sl][8 * g]) : uint4{0u, 0u, 0u, 0u};
+      const float yy = mlp_tile(d, net, lane, x);
+      if (g == 0 && sl < nopen) s_y[wave][sl] = yy;
+    }
+    __syncthreads();
+    if (open) y = s_y[wave][slot];
+    // the scan is tried only where the prediction reaches the saturation point less delta
+    scan = open && (double)y >= gate_min;
+    if (!valid) return;
+  }
   // mode 0: the exact kNN in any case (no scan); 1: certified, needs d1; 2: may be certified
-  // by the distances (a 3 x 3 block over 8 k + 16 points is left to the exact path)
-  const int mode = cert ? 1 : (n1 <= 8 * k + 16 ? 2 : 0);
+  // by the distances
+  const int mode = cert ? 1 : (scan ? 2 : 0);
   float best = INFINITY;
   bool hit = false;
   double d_1 = 0.0, v_sum = 0.0;
@@ -962,7 +1034,7 @@ __global__ __launch_bounds__(256) void k_cert_front(const GridScalars* __restric
     alpha_f[q] = (float)ap.levels[4];
     d1sq[q] = d1;
   }
-  if (r_hat_out) r_hat_out[q] = __builtin_nanf("");
+  if (r_hat_out) r_hat_out[q] = y;
   if (route) route[q] = fall ? (mode == 2 ? 1 : 0) : (cert_counts ? 2 : 3);
 }
 
@@ -1018,10 +1090,16 @@ hipError_t launch_learned_front(const MlpDevice& d, const GridScalars* gs, const
   hipLaunchKernelGGL((k_learned_front<CERT, NET>), dim3(tile_blocks((const void*)k_learned_front<CERT, NET>, m)), \
                      dim3(256), 0, s, d, gs, cell_start, sx, sy, qx, qy, perm, m, n, ap, rule, delta, r_sat_lo,   \
                      r_sat_hi, k, cert_factor, flag, alpha_f, d1sq, r_hat_out, route)
-  if (rule == 2) {
-    hipLaunchKernelGGL(k_cert_front, dim3((m + 255) / 256), dim3(256), 0, s, gs, cell_start, sx, sy, qx, qy, perm, m,
-                       ap, k, cert_factor, flag, alpha_f, d1sq, r_hat_out, route);
-  } else if (rule == 3 || rule == 4)
+  if (rule == 2 || rule == 4) {
+    // rule 4 tries the 3 x 3 certificate where the prediction is >= r_sat_hi - delta
+    const double gate_min = r_sat_hi - delta;
+    if (rule == 2)
+      hipLaunchKernelGGL(k_cert_front<false>, dim3((m + 255) / 256), dim3(256), 0, s, d, gs, cell_start, sx, sy, qx,
+                         qy, perm, m, n, ap, k, cert_factor, gate_min, flag, alpha_f, d1sq, r_hat_out, route);
+    else
+      hipLaunchKernelGGL(k_cert_front<true>, dim3((m + 255) / 256), dim3(256), 0, s, d, gs, cell_start, sx, sy, qx,
+                         qy, perm, m, n, ap, k, cert_factor, gate_min, flag, alpha_f, d1sq, r_hat_out, route);
+  } else if (rule == 3)
     FRONT(true, true);
   else
     FRONT(false, true);
