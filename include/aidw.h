@@ -353,8 +353,8 @@ typedef enum {
                                                    certificate is tried on: those the block counts do not already
                                                    certify and whose r_hat >= (R where mu = 0.9) - delta; the others
                                                    go to the exact kNN without that scan.  The network runs only on
-                                                   tiles of 16 queries holding such a query (r_hat_out: NaN
-                                                   elsewhere) */
+                                                   the queries the counts leave open whose 3 x 3 block holds at
+                                                   most 8 k + 16 points (r_hat_out: NaN for the others) */
 } aidw_fallback_rule;
 
 /* New network with weights drawn from `seed` (uniform in +-sqrt(6 / fan_in),

@@ -958,6 +958,7 @@ __global__ __launch_bounds__(256) void k_cert_front(MlpDevice d, const GridScala
     __syncthreads();
     const MfmaNetGlobal net{reinterpret_cast<const uint4*>(d.w1a), reinterpret_cast<const uint4*>(d.w2a)};
     for (int tile = 0; tile * 16 < nopen; ++tile) {  // uniform over the wavefront: every lane runs the MFMA
+      __asm__ volatile("" ::: "memory");  // keeps the operand reads from LDS inside the loop (registers)
       const int c = lane & 15, g = lane >> 4, sl = tile * 16 + c;
       const uint4 x = sl < nopen ? *reinterpret_cast<const uint4*>(&s_feat[wave][sl][8 * g]) : uint4{0u, 0u, 0u, 0u};
       const float yy = mlp_tile(d, net, lane, x);
