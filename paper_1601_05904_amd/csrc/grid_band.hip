@@ -38,8 +38,8 @@ constexpr int kWaves = kThreads / 64;
 constexpr int kDigits = 2 * kMaxBands;    // data bands, then query bands
 constexpr int kDigitBits = 11;            // kDigits = 2^kDigitBits
 static_assert(kDigits == 1 << kDigitBits, "digit count");
-constexpr int kLocalThreads = 256;        // k_band_local
-constexpr int kLocalItems = 16;
+constexpr int kLocalThreads = 512;        // k_band_local
+constexpr int kLocalItems = 8;
 constexpr int kLocalTile = kLocalThreads * kLocalItems;  // points staged in LDS per band
 constexpr int kLocalWaves = kLocalThreads / 64;
 
