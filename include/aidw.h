@@ -347,7 +347,9 @@ typedef enum {
                                     1, 3 x 3 and 5 x 5 cell blocks around the query and the exact distances of
                                     the 3 x 3 block's points.  Every query gets the alpha of the exact path; the
                                     network is not evaluated (r_hat_out receives NaN); delta is checked, unused */
-  AIDW_FALLBACK_CERTIFIED_THEN_ALPHA_EXACT = 3, /* skip when certified as in 2, else apply rule 1 */
+  AIDW_FALLBACK_CERTIFIED_THEN_ALPHA_EXACT = 3, /* skip when certified as in 2, else apply rule 1; the network runs
+                                                   only on the queries the block counts do not certify (r_hat_out:
+                                                   NaN for the others) */
   AIDW_FALLBACK_NETWORK_GATED_CERTIFICATE = 4   /* skip only when certified as in 2 (every alpha is the exact
                                                    path's); the network decides which queries the 3 x 3 distance
                                                    certificate is tried on: those the block counts do not already

@@ -588,32 +588,29 @@ __global__ __launch_bounds__(256) void k_mlp_forward_mfma(MlpDevice d, const flo
   }
 }
 
-// Fused front of the learned run for the queries at positions t of the order perm (may be
-// null): the 27 features (as k_features), the network, and the fallback rule; flag[t] = 1
-// marks a query that takes the exact kNN.  Lane 16 g + c works on the query at position
+// Fused front of the learned run under the network's own rules (0 and 1, where the network
+// runs on every query) for the queries at positions t of the order perm (may be null): the
+// 27 features (as k_features), the network, and the fallback rule; flag[t] = 1 marks a query
+// that takes the exact kNN.  (The rules that start from the certificate run k_cert_front.)  Lane 16 g + c works on the query at position
 // 16 tile + c: it computes features 8 g .. 8 g + 7, takes a quarter of the query's own cell
 // in the scan of the 3 x 3 block for the nearest distance, and one of its four neighbour
 // segments.
 // Four wavefronts per SIMD (at most 128 registers per lane) hide more of the loads' latency;
-// there the registers of the loads in flight across the network spill 3 dwords to scratch,
+// there the registers of the loads in flight across the network spill 6 dwords to scratch,
 // which still measured faster than issuing those loads after the network (no spill) or
 // than three wavefronts per SIMD.
-// kCert: the certificate, from block counts and 3 x 3 distances (rules 3, 4; rule 2, the
-// certificate alone, runs k_cert_front); kNet: the network (rules 0, 1, 3, 4).
-template <bool kCert, bool kNet>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_learned_front(
     MlpDevice d, const GridScalars* __restrict__ gs, const int32_t* __restrict__ cell_start,
     const float* __restrict__ sx, const float* __restrict__ sy, const float* __restrict__ qx,
     const float* __restrict__ qy, const uint32_t* __restrict__ perm, int m, int64_t n, AlphaParams ap, int rule,
-    double delta, double r_sat_lo, double r_sat_hi, int k, double cert_factor, uint32_t* __restrict__ flag,
-    float* __restrict__ alpha_f, float* __restrict__ d1sq, float* __restrict__ r_hat_out, uint8_t* __restrict__ route) {
+    double delta, double r_sat_lo, double r_sat_hi, uint32_t* __restrict__ flag, float* __restrict__ alpha_f,
+    float* __restrict__ d1sq, float* __restrict__ r_hat_out, uint8_t* __restrict__ route) {
   if (gs->status != AIDW_OK) return;  // a failed grid build: nothing to decide
   const int lane = threadIdx.x & 63, c = lane & 15, g = lane >> 4;
   const double inv_occ = (double)gs->ncells / (double)n;
   const double slack_cells = aidw::slack_cells(gs->ncol, gs->nrow);
-  const double cert_sum_min = cert_factor * gs->r_exp;
   __shared__ uint4 lds[kNetOperands];
-  const MfmaNet net = kNet ? stage_net(d, lds) : MfmaNet{lds};
+  const MfmaNet net = stage_net(d, lds);
   const float minx = gs->minx, miny = gs->miny, inv = gs->inv_cw;
   const int ncol = gs->ncol, nrow = gs->nrow;
   const double cwd = gs->cwd, minxd = minx, minyd = miny;
@@ -694,58 +691,22 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
     // features 8 g .. 8 g + 7: counts of the 5 x 5 block (row-major), then the in-cell offset
     // and this lane's share of the data points in the blocks of 1, 3 x 3 and 5 x 5 cells
     float f[8];
-    int n0 = 0, n1 = 0, n2 = 0;
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
       const int kk = 8 * g + j;
       const int end = j == j1 ? cur.e0 : (j == j1 + 5 ? cur.e1 : cur.a[j + 1]);
       const int cnt = kk < 25 ? end - cur.a[j] : 0;
-      if constexpr (kCert) {
-        const int br = kk / 5, bc = kk % 5;
-        n2 += cnt;
-        n1 += br >= 1 && br <= 3 && bc >= 1 && bc <= 3 ? cnt : 0;
-        n0 += kk == 12 ? cnt : 0;
-      }
       f[j] = kk < 25 ? (float)((double)cnt * inv_occ)
                      : (kk == 25 ? tx - (float)c0 : (kk == 26 ? ty - (float)r0 : 0.0f));
     }
     const double px = fx, py = fy;
-    // What the scan below has to find depends on what is decided without it (all inputs
-    // here are the same on a query's four lanes): a query that takes the exact kNN in any case
-    // needs no scan (that search gives its d1); a skipped one needs its nearest distance
-    // (mode 1); one the certificate may still accept needs the statistics of its 3 x 3 block
-    // (mode 2).  A 3 x 3 block holding more than 8 k + 16 points is left to the exact path:
-    // such a query's R lies far below the saturation point (k neighbours within about a cell).
-    bool cert = false;
-    if constexpr (kCert) {
-      n0 += __shfl_xor(n0, 16, 64);
-      n1 += __shfl_xor(n1, 16, 64);
-      n2 += __shfl_xor(n2, 16, 64);
-      n0 += __shfl_xor(n0, 32, 64);
-      n1 += __shfl_xor(n1, 32, 64);
-      n2 += __shfl_xor(n2, 32, 64);
-      cert = certified_saturated(px, py, c0, r0, ncol, nrow, minxd, minyd, cwd, slack_cells, n0, n1, n2, k,
-                                 cert_sum_min);
-    }
-    const bool cert_counts = cert;
-    // rule 4 runs the network only on tiles holding a query the counts did not certify and
-    // whose 3 x 3 block the certificate would scan (the MFMA tile is the wavefront's)
-    const bool scan_ok = kCert && valid && !cert && n1 <= 8 * k + 16;
-    float y = __builtin_nanf("");
-    if constexpr (kNet) {
-      if (rule != 4 || __ballot(scan_ok) != 0ull) y = mlp_tile(d, net, lane, pack8(f));
-    }
+    const float y = mlp_tile(d, net, lane, pack8(f));
     double alpha_net = 0.0;
-    bool net_fall = true;
-    if constexpr (kNet) {
-      if (rule != 4)
-        net_fall = decide_one((double)y, 1.0f, ap, rule == 3 ? 1 : rule, delta, r_sat_lo, r_sat_hi, &alpha_net);
-    }
-    // rule 4: the 3 x 3 certificate is tried only where the network predicts R at or beyond
-    // r_sat_hi - delta; elsewhere the query goes to the exact kNN without the scan
-    const bool gate = rule != 4 || (double)y >= r_sat_hi - delta;
-    const int mode = !valid ? 0 : cert ? 1 : (scan_ok && gate) ? 2 : !net_fall ? 1 : 0;
-    if (mode == 0) {
+    const bool net_fall = decide_one((double)y, 1.0f, ap, rule, delta, r_sat_lo, r_sat_hi, &alpha_net);
+    // a query that takes the exact kNN needs no scan (that search gives its d1); a skipped one
+    // needs its nearest distance (all inputs here are the same on a query's four lanes)
+    const bool scan = valid && !net_fall;
+    if (!scan) {
       o1 = o0;
       p1 = p0;
     }
@@ -753,31 +714,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
     // neighbour segment unless all of it lies farther than the own cell's nearest, then the
     // minimum over the 4 lanes.  float32 suffices: the value only sets the power-of-two
     // scale of the pair weights; a coincident point (which lies in the own cell) is found
-    // exactly, as a zero difference.  In mode 2 every point of the block nearer than D_1
-    // (the distance to the block's open sides, less the binning slack) is also counted and
-    // its distance summed, and a segment is left out only when it lies wholly beyond D_1.
+    // exactly, as a zero difference.
     float best = INFINITY;
     int hit = 0;
-    double d_1 = 0.0, v_sum = 0.0;
-    float d_1sq = 0.0f, v_max = 0.0f;
-    int v_cnt = 0;
-    if (kCert && mode == 2) {
-      d_1 = block_side_distance(px, py, c0, r0, 1, ncol, nrow, minxd, minyd, cwd, slack_cells);
-      d_1sq = (float)(d_1 * d_1);
-    }
     for (int p = o0 + g; p < o1; p += 4) {
       const float dx = sx[p] - fx, dy = sy[p] - fy;
       const float dd = __builtin_fmaf(dx, dx, dy * dy);
       hit |= (dx == 0.0f) & (dy == 0.0f);
       best = fminf(best, dd);
-      if constexpr (kCert) {
-        if (dd < d_1sq) {
-          const float dist = __builtin_sqrtf(dd);
-          v_sum += (double)dist;
-          v_max = fmaxf(v_max, dist);
-          ++v_cnt;
-        }
-      }
     }
     best = fminf(best, __shfl_xor(best, 16, 64));
     best = fminf(best, __shfl_xor(best, 32, 64));
@@ -789,35 +733,18 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
                        : g == 1 ? (minyd + ((double)r0 + 1.0 - slack_cells) * cwd) - py
                        : g == 2 ? px - (minxd + ((double)c0 + slack_cells) * cwd)
                                 : (minxd + ((double)c0 + 1.0 - slack_cells) * cwd) - px;
-      if (e > 0.0 && e * e > (double)best && (mode != 2 || e >= d_1)) p1 = p0;
+      if (e > 0.0 && e * e > (double)best) p1 = p0;
     }
     if (seg) {
       for (int p = p0; p < p1; ++p) {
         const float dx = sx[p] - fx, dy = sy[p] - fy;
-        const float dd = __builtin_fmaf(dx, dx, dy * dy);
-        best = fminf(best, dd);
-        if constexpr (kCert) {
-          if (dd < d_1sq) {
-            const float dist = __builtin_sqrtf(dd);
-            v_sum += (double)dist;
-            v_max = fmaxf(v_max, dist);
-            ++v_cnt;
-          }
-        }
+        best = fminf(best, __builtin_fmaf(dx, dx, dy * dy));
       }
     }
     best = fminf(best, __shfl_xor(best, 16, 64));
     best = fminf(best, __shfl_xor(best, 32, 64));
     hit |= __shfl_xor(hit, 16, 64);
     hit |= __shfl_xor(hit, 32, 64);
-    if constexpr (kCert) {
-      v_cnt += __shfl_xor(v_cnt, 16, 64);
-      v_cnt += __shfl_xor(v_cnt, 32, 64);
-      v_sum += __shfl_xor(v_sum, 16, 64);
-      v_sum += __shfl_xor(v_sum, 32, 64);
-      v_max = fmaxf(v_max, __shfl_xor(v_max, 16, 64));
-      v_max = fmaxf(v_max, __shfl_xor(v_max, 32, 64));
-    }
     if (g != 0 || !valid) continue;
     double dout = INFINITY;
     if (c0 - 1 > 0) dout = fmin(dout, px - (minxd + (double)(c0 - 1) * cwd));
@@ -831,66 +758,53 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
     else
       v = dout > 0 ? dout * dout : 0;  // lower bound
     const float d1 = hit ? 0.0f : fmaxf((float)v, FLT_MIN);
-    // the decision: a coincident query (d1 = 0) and a query not scanned take the exact path;
-    // then the certificate (counts, else the 3 x 3 distances), then the network's rule
-    double alpha = 0.0;
-    bool fall = true;
-    if (mode != 0 && d1 != 0.0f) {
-      if (kCert && mode == 2 && !cert)
-        cert = certified_by_distances(
-            v_sum, v_cnt, v_max, n2, k, d_1,
-            block_side_distance(px, py, c0, r0, 2, ncol, nrow, minxd, minyd, cwd, slack_cells), cert_sum_min);
-      if (cert) {
-        fall = false;
-        alpha = ap.levels[4];
-      } else if (!net_fall) {
-        fall = false;
-        alpha = alpha_net;
-      }
-    }
+    // the decision: a coincident query (d1 = 0) takes the exact path, else the network's rule
+    const bool fall = !scan || d1 == 0.0f;
     flag[t] = fall ? 1u : 0u;
     if (!fall) {
-      alpha_f[q] = (float)alpha;
+      alpha_f[q] = (float)alpha_net;
       d1sq[q] = d1;
     }
     if (r_hat_out) r_hat_out[q] = y;
-    if (route)
-      route[q] = fall ? (mode == 2 ? 1 : 0) : (cert ? (cert_counts ? 2 : 3) : 4);
+    if (route) route[q] = fall ? 0 : 4;
   }
 }
 
 
-// The front of rules 2 and 4, one lane per query: the queries of a wavefront are 64
-// consecutive positions of the binned order, so they share most of their blocks' cells.  It
-// makes the decision and writes the outputs that k_learned_front would with the certificate
-// (whose tiles of 16 queries exist for the network's matrix operands on every query):
-// c_0, c_1, c_2 are differences of row offsets (a row of a block is one run of the cell
-// order), the certificate from the counts, then, for a query it certifies or may still
-// certify, one scan of the 3 x 3 block (three runs) for the nearest distance and the
-// statistics below D_1.
-// kGate (rule 4): the network decides which of the queries the counts leave open are scanned.
-// A wavefront gathers those queries (a ballot), stores their 27 features as bf16 in LDS in
-// the order of their lanes, and runs the network on the matrix cores over tiles of 16 of
-// them, so a wavefront without such a query does not evaluate it.  r_hat_out receives the
-// prediction for those queries and NaN for the others.
-template <bool kGate>
+// The front of the rules that start from the certificate (2, 3 and 4), one lane per query: the
+// queries of a wavefront are 64 consecutive positions of the binned order, so they share most
+// of their blocks' cells.  c_0, c_1, c_2 are differences of row offsets (a row of a block is
+// one run of the cell order), the certificate from the counts, then, for a query it certifies
+// or may still certify (or, rule 3, that the network lets skip the kNN), one scan of the 3 x 3
+// block (three runs) for the nearest distance and the statistics below D_1.
+// The network runs only on the queries the counts do not certify: rule 4 those whose 3 x 3
+// block the certificate may scan (the network decides which of them are scanned), rule 3 all
+// of them (the network's alpha-exact rule where the certificate fails).  A wavefront gathers
+// those queries (a ballot), stores their 27 features as bf16 in LDS in the order of their
+// lanes, and runs the network on the matrix cores over tiles of 16 of them, so a wavefront
+// without such a query does not evaluate it.  r_hat_out receives the prediction for those
+// queries and NaN for the others.
+template <int kRule>
 __global__ __launch_bounds__(256) void k_cert_front(MlpDevice d, const GridScalars* __restrict__ gs,
                                                     const int32_t* __restrict__ cell_start,
                                                     const float* __restrict__ sx, const float* __restrict__ sy,
                                                     const float* __restrict__ qx, const float* __restrict__ qy,
                                                     const uint32_t* __restrict__ perm, int m, int64_t n,
-                                                    AlphaParams ap, int k, double cert_factor, double gate_min,
+                                                    AlphaParams ap, int k, double cert_factor, double delta,
+                                                    double r_sat_lo, double r_sat_hi,
                                                     uint32_t* __restrict__ flag, float* __restrict__ alpha_f,
                                                     float* __restrict__ d1sq, float* __restrict__ r_hat_out,
                                                     uint8_t* __restrict__ route) {
+  static_assert(kRule >= 2 && kRule <= 4, "rules 2, 3, 4");
+  constexpr bool kNet = kRule != 2;
   constexpr int kWaves = 256 / 64;
-  __shared__ __align__(16) uint16_t s_feat[kGate ? kWaves : 1][64][32];  // bf16 bits, 27 used
-  __shared__ float s_y[kGate ? kWaves : 1][64];
+  __shared__ __align__(16) uint16_t s_feat[kNet ? kWaves : 1][64][32];  // bf16 bits, 27 used
+  __shared__ float s_y[kNet ? kWaves : 1][64];
   if (gs->status != AIDW_OK) return;  // a failed grid build: nothing to decide (the whole grid)
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   // with the network every lane stays to the barriers; without it the tail leaves at once
   const bool valid = t < m;
-  if (!kGate && !valid) return;
+  if (!kNet && !valid) return;
   const int q = valid ? (perm ? (int)perm[t] : t) : 0;
   const float minx = gs->minx, miny = gs->miny, inv = gs->inv_cw;
   const int ncol = gs->ncol, nrow = gs->nrow;
@@ -928,12 +842,15 @@ __global__ __launch_bounds__(256) void k_cert_front(MlpDevice d, const GridScala
   const bool open = valid && !cert && n1 <= 8 * k + 16;
   bool scan = open;
   float y = __builtin_nanf("");
-  if constexpr (kGate) {
+  bool net_fall = true;  // rule 3: the network's alpha-exact rule sends the query to the exact kNN
+  double alpha_net = 0.0;
+  if constexpr (kNet) {
+    const bool net_q = kRule == 4 ? open : valid && !cert;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const uint64_t open_mask = __ballot(open);
-    const int nopen = __popcll(open_mask);
-    const int slot = __popcll(open_mask & (lane == 0 ? 0ull : (~0ull >> (64 - lane))));
-    if (open) {
+    const uint64_t net_mask = __ballot(net_q);
+    const int nnet = __popcll(net_mask);
+    const int slot = __popcll(net_mask & (lane == 0 ? 0ull : (~0ull >> (64 - lane))));
+    if (net_q) {
       // the 27 features: counts of the 5 x 5 block (row-major) over the mean occupancy, then
       // the offset inside the cell (a count is the difference of two offsets; columns clamped
       // to [0, ncol] count 0 beyond the edges, rows outside the grid count 0)
@@ -957,22 +874,26 @@ __global__ __launch_bounds__(256) void k_cert_front(MlpDevice d, const GridScala
     }
     __syncthreads();
     const MfmaNetGlobal net{reinterpret_cast<const uint4*>(d.w1a), reinterpret_cast<const uint4*>(d.w2a)};
-    for (int tile = 0; tile * 16 < nopen; ++tile) {  // uniform over the wavefront: every lane runs the MFMA
+    for (int tile = 0; tile * 16 < nnet; ++tile) {  // uniform over the wavefront: every lane runs the MFMA
       __asm__ volatile("" ::: "memory");  // keeps the operand reads from LDS inside the loop (registers)
       const int c = lane & 15, g = lane >> 4, sl = tile * 16 + c;
-      const uint4 x = sl < nopen ? *reinterpret_cast<const uint4*>(&s_feat[wave][sl][8 * g]) : uint4{0u, 0u, 0u, 0u};
+      const uint4 x = sl < nnet ? *reinterpret_cast<const uint4*>(&s_feat[wave][sl][8 * g]) : uint4{0u, 0u, 0u, 0u};
       const float yy = mlp_tile(d, net, lane, x);
-      if (g == 0 && sl < nopen) s_y[wave][sl] = yy;
+      if (g == 0 && sl < nnet) s_y[wave][sl] = yy;
     }
     __syncthreads();
-    if (open) y = s_y[wave][slot];
-    // the scan is tried only where the prediction reaches the saturation point less delta
-    scan = open && (double)y >= gate_min;
+    if (net_q) y = s_y[wave][slot];
+    if constexpr (kRule == 4) {
+      // the scan is tried only where the prediction reaches the saturation point less delta
+      scan = open && (double)y >= r_sat_hi - delta;
+    } else {
+      if (net_q) net_fall = decide_one((double)y, 1.0f, ap, 1, delta, r_sat_lo, r_sat_hi, &alpha_net);
+    }
     if (!valid) return;
   }
-  // mode 0: the exact kNN in any case (no scan); 1: certified, needs d1; 2: may be certified
-  // by the distances
-  const int mode = cert ? 1 : (scan ? 2 : 0);
+  // mode 0: the exact kNN in any case (no scan); 1: skipped (certified, or by the network's
+  // rule), needs d1; 2: may be certified by the distances
+  const int mode = cert ? 1 : (scan ? 2 : (!net_fall ? 1 : 0));
   float best = INFINITY;
   bool hit = false;
   double d_1 = 0.0, v_sum = 0.0;
@@ -1022,21 +943,30 @@ __global__ __launch_bounds__(256) void k_cert_front(MlpDevice d, const GridScala
   dout -= slack_cells * cwd;
   const double v = (dout == INFINITY || (double)best < dout * dout) ? (double)best : (dout > 0 ? dout * dout : 0.0);
   const float d1 = hit ? 0.0f : fmaxf((float)v, FLT_MIN);
+  // a coincident query (d1 = 0) and a query not scanned take the exact path; then the
+  // certificate (counts, else the 3 x 3 distances), then (rule 3) the network's rule
   bool fall = true;
+  double alpha = 0.0;
   if (mode != 0 && d1 != 0.0f) {
     if (mode == 2)
       cert = certified_by_distances(
           v_sum, v_cnt, v_max, n2, k, d_1,
           block_side_distance(px, py, c0, r0, 2, ncol, nrow, minxd, minyd, cwd, slack_cells), cert_sum_min);
-    fall = !cert;
+    if (cert) {
+      fall = false;
+      alpha = ap.levels[4];
+    } else if (!net_fall) {
+      fall = false;
+      alpha = alpha_net;
+    }
   }
   flag[t] = fall ? 1u : 0u;
   if (!fall) {
-    alpha_f[q] = (float)ap.levels[4];
+    alpha_f[q] = (float)alpha;
     d1sq[q] = d1;
   }
   if (r_hat_out) r_hat_out[q] = y;
-  if (route) route[q] = fall ? (mode == 2 ? 1 : 0) : (cert_counts ? 2 : 3);
+  if (route) route[q] = fall ? (mode == 2 ? 1 : 0) : (cert ? (cert_counts ? 2 : 3) : 4);
 }
 
 }  // namespace
@@ -1087,24 +1017,20 @@ hipError_t launch_learned_front(const MlpDevice& d, const GridScalars* gs, const
                                 double r_sat_hi, int k, double cert_factor, uint32_t* flag, float* alpha_f,
                                 float* d1sq, float* r_hat_out, uint8_t* route, hipStream_t s) {
   if (m <= 0) return hipSuccess;
-#define FRONT(CERT, NET)                                                                                       \
-  hipLaunchKernelGGL((k_learned_front<CERT, NET>), dim3(tile_blocks((const void*)k_learned_front<CERT, NET>, m)), \
-                     dim3(256), 0, s, d, gs, cell_start, sx, sy, qx, qy, perm, m, n, ap, rule, delta, r_sat_lo,   \
-                     r_sat_hi, k, cert_factor, flag, alpha_f, d1sq, r_hat_out, route)
-  if (rule == 2 || rule == 4) {
-    // rule 4 tries the 3 x 3 certificate where the prediction is >= r_sat_hi - delta
-    const double gate_min = r_sat_hi - delta;
-    if (rule == 2)
-      hipLaunchKernelGGL(k_cert_front<false>, dim3((m + 255) / 256), dim3(256), 0, s, d, gs, cell_start, sx, sy, qx,
-                         qy, perm, m, n, ap, k, cert_factor, gate_min, flag, alpha_f, d1sq, r_hat_out, route);
-    else
-      hipLaunchKernelGGL(k_cert_front<true>, dim3((m + 255) / 256), dim3(256), 0, s, d, gs, cell_start, sx, sy, qx,
-                         qy, perm, m, n, ap, k, cert_factor, gate_min, flag, alpha_f, d1sq, r_hat_out, route);
-  } else if (rule == 3)
-    FRONT(true, true);
+#define CERT_FRONT(R)                                                                                        \
+  hipLaunchKernelGGL(k_cert_front<R>, dim3((m + 255) / 256), dim3(256), 0, s, d, gs, cell_start, sx, sy, qx, qy, \
+                     perm, m, n, ap, k, cert_factor, delta, r_sat_lo, r_sat_hi, flag, alpha_f, d1sq, r_hat_out, route)
+  if (rule == 2)
+    CERT_FRONT(2);
+  else if (rule == 3)
+    CERT_FRONT(3);
+  else if (rule == 4)
+    CERT_FRONT(4);
   else
-    FRONT(false, true);
-#undef FRONT
+    hipLaunchKernelGGL(k_learned_front, dim3(tile_blocks((const void*)k_learned_front, m)), dim3(256), 0, s, d, gs,
+                       cell_start, sx, sy, qx, qy, perm, m, n, ap, rule, delta, r_sat_lo, r_sat_hi, flag, alpha_f,
+                       d1sq, r_hat_out, route);
+#undef CERT_FRONT
   return hipGetLastError();
 }
 
