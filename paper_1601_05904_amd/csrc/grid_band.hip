@@ -8,7 +8,7 @@
 //                     of points per digit: the digit of a data point is its band (the
 //                     cell index >> band_shift), a query's is nbands + its band.
 //   k_band_prefix     per digit, the exclusive scan of its counts over the blocks, and the
-//                     digit's total (64 digits per block).
+//                     digit's total (16 digits per block).
 //   k_band_scatter    a stable counting sort of each tile by digit: ranks from wavefront
 //                     ballots, the tile sorted in LDS, then written out in runs, so each
 //                     block writes contiguous pieces of every digit's segment.
@@ -217,11 +217,12 @@ __global__ __launch_bounds__(kThreads) void k_band_hist(const BoundsPartial* __r
   for (int d = threadIdx.x; d < kDigits; d += kThreads) hist[(size_t)blockIdx.x * kDigits + d] = h[d];
 }
 
-// For 64 digits per block: each digit's counts over the blocks -> their exclusive prefix (in
+// For 16 digits per block: each digit's counts over the blocks -> their exclusive prefix (in
 // place), and the digit's total.  Thread (slice, j) walks a slice of the blocks for digit j, so
-// a wavefront reads 64 consecutive words of a block's row.
-constexpr int kPrefixDigits = 64;
-constexpr int kPrefixSlices = 16;
+// a wavefront reads 16 consecutive words of four blocks' rows; 64 slices keep each thread's
+// chain of dependent loads short (at 2^21 points, 8 rows per slice).
+constexpr int kPrefixDigits = 16;
+constexpr int kPrefixSlices = 64;
 __global__ __launch_bounds__(kPrefixDigits * kPrefixSlices) void k_band_prefix(uint32_t* __restrict__ hist, int nblk,
                                                                                uint32_t* __restrict__ totals) {
   __shared__ uint32_t part[kPrefixSlices][kPrefixDigits];
