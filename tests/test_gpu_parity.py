@@ -57,9 +57,13 @@ def tiny_lattice(seed, n, m, res=8):
 
 # ------------------------------------------------------------------ grid build
 
-def _check_grid(T, ds, params):
+def _check_grid(T, ds, params, offset=0):
     aidw = aidw_mod()
     x, y, z, qx, qy = upload(T, ds)
+    if offset:
+        # views that start `offset` floats into their buffers: device pointers off 16-byte alignment
+        x, y, qx, qy = (T.cat([T.zeros(offset, dtype=a.dtype, device=a.device), a])[offset:] for a in (x, y, qx, qy))
+        assert all(a.data_ptr() % 16 != 0 for a in (x, y, qx, qy))
     g = aidw.build_grid(x, y, qx, qy, params)
     d = g.describe()
     b = O.bounds(ds.x, ds.y, ds.qx, ds.qy)
@@ -92,13 +96,15 @@ def dense_cells(seed, n=30000, m=3000, spots=50, dup=100):
     return ds
 
 
-@pytest.mark.parametrize("name", ["uniform_4k", "mixture", "ragged_rect", "lattice", "dense_cells", "uniform_1m",
-                                  "clustered_1m"])
+@pytest.mark.parametrize("name", ["uniform_4k", "mixture", "ragged_rect", "unaligned", "lattice", "dense_cells",
+                                  "uniform_1m", "clustered_1m"])
 def test_grid_matches_oracle(T, name):
     """The grid (bounds, scalars, CSR offsets, points in cell order with each cell by index)
     bit for bit against the oracle's stable sort by cell.  uniform_1m takes the rank-ordered
     local sort in every band, dense_cells the ballot-ranked one in the bands of its crowded
-    cells, clustered_1m (the 2^20 mixture) also bands too large for the LDS tile."""
+    cells, clustered_1m (the 2^20 mixture) also bands too large for the LDS tile; ragged_rect
+    has lengths that are not multiples of four, unaligned coordinate arrays (views) that do
+    not start on a 16-byte boundary."""
     aidw = aidw_mod()
     if name == "uniform_1m":
         ds, p = W.WORKLOADS["uniform_1m"](), aidw.Params()
@@ -115,6 +121,10 @@ def test_grid_matches_oracle(T, name):
         ds.x = (ds.x * np.float32(0.25)).astype(np.float32)  # a 1/4 x 1 rectangle
         ds.qx = (ds.qx * np.float32(0.25)).astype(np.float32)
         p = aidw.Params(k=7, occupancy=3.0)
+    elif name == "unaligned":
+        ds, p = W.make(5003, 1201, 10, 34), aidw.Params()
+        _check_grid(T, ds, p, offset=1)
+        return
     else:
         ds, p = tiny_lattice(5, 300, 50), aidw.Params(k=8, occupancy=0.5)
     _check_grid(T, ds, p)
