@@ -296,7 +296,10 @@ __global__ __launch_bounds__(kThreads) void k_band_scatter(const GridScalars* __
   __shared__ uint32_t cur[kDigits];   // run cursors, then each digit's output start for this block
   __shared__ uint32_t s_maxrun;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int64_t base = (int64_t)blockIdx.x * kTile;
+  // tiles in XCD-aware order: consecutive tiles write adjacent runs of each digit's segment
+  // (partial cache lines), so on one XCD they meet in its L2 before going to HBM
+  const int tile = xcd_block(blockIdx.x, gridDim.x);
+  const int64_t base = (int64_t)tile * kTile;
   Elem el[kItems];
   bool ok[kItems];
 #pragma unroll
@@ -375,12 +378,12 @@ __global__ __launch_bounds__(kThreads) void k_band_scatter(const GridScalars* __
   for (int d = tid; d < kDigits; d += kThreads) cur[d] = totals[d];
   __syncthreads();
   const uint32_t all = lds_exclusive_scan<kThreads>(cur, kDigits);
-  const uint32_t* row = prefix + (size_t)blockIdx.x * kDigits;
+  const uint32_t* row = prefix + (size_t)tile * kDigits;
   for (int d = tid; d < kDigits; d += kThreads) {
-    if (blockIdx.x == 0) dstart[d] = cur[d];
+    if (tile == 0) dstart[d] = cur[d];
     cur[d] += row[d];
   }
-  if (blockIdx.x == 0 && tid == 0) dstart[kDigits] = all;
+  if (tile == 0 && tid == 0) dstart[kDigits] = all;
   __syncthreads();
   const int64_t left = total - base;
   const int cnt_blk = left < kTile ? (int)left : kTile;
