@@ -463,6 +463,34 @@ def test_certified_then_network_rule(T):
     assert np.all(np.isfinite(qz_3))
 
 
+@pytest.mark.parametrize("case", ["mixture", "small_grid"])
+def test_gated_rule_prediction(T, case):
+    """Rule 4 evaluates the network in the one-lane front, on the queries the block counts leave
+    open (gathered per wavefront into tiles), with the features and network of rule 1: where it
+    ran, its prediction equals rule 1's bit for bit; where it did not, the query is certified by
+    the counts (route 2) or takes the exact kNN without a scan (route 0); and every query it
+    sent to the 3 x 3 scan had a prediction at or beyond r_sat_hi - delta."""
+    aidw, L = mods()
+    if case == "mixture":
+        ds, k = W.make(30000, 9000, 15, 261, "mixture", 16), 15
+    else:
+        ds, k = W.make(60, 500, 5, 262, "mixture", 4), 5
+    mlp = L.MLP(seed=8)
+    mlp.set_params(random_params(13, 0.2))
+    x, y, qx, qy = (dev(T, getattr(ds, a)) for a in ("x", "y", "qx", "qy"))
+    p = aidw.Params(k=k)
+    _, rh1 = L.learned_routes(x, y, qx, qy, p, mlp, L.ALPHA_EXACT, 0.3, want_rhat=True)
+    r4, rh4 = L.learned_routes(x, y, qx, qy, p, mlp, L.NETWORK_GATED_CERTIFICATE, 0.3, want_rhat=True)
+    rh1, rh4, r4 = rh1.cpu().numpy(), rh4.cpu().numpy(), r4.cpu().numpy()
+    ev = ~np.isnan(rh4)
+    assert ev.any()
+    assert np.array_equal(rh1[ev], rh4[ev])
+    assert np.all(np.isin(r4[~ev], (0, 2)))
+    scanned = (r4 == 1) | (r4 == 3)
+    assert np.all(ev[scanned])
+    assert np.all(rh4[scanned].astype(np.float64) >= 2 / np.pi * np.arccos(-0.8) - 0.3)
+
+
 def test_certified_rule_full_size(T):
     """Rule 2 on the clustered 2^20 workload in the configuration the benchmark times: every
     query's alpha equals the plain path's (bitwise), most queries skip the kNN search, and z
