@@ -44,7 +44,15 @@ struct BoundsPartial {
 // Length of the register k-list of the kNN kernels for a given k: the insertion of a
 // candidate runs one compare-and-swap step per slot, so the list is kept close to k.
 __host__ __device__ inline int knn_slots(int k) {
-  return k <= 8 ? 8 : k <= 10 ? 10 : k <= 12 ? 12 : k <= 16 ? 16 : k <= 24 ? 24 : k <= 32 ? 32 : k <= 48 ? 48 : 64;
+  return k <= 8    ? 8
+         : k <= 10 ? 10
+         : k <= 12 ? 12
+         : k <= 15 ? 15
+         : k <= 16 ? 16
+         : k <= 24 ? 24
+         : k <= 32 ? 32
+         : k <= 48 ? 48
+                   : 64;
 }
 // M(KMAX) for the list length of k (a statement).
 #define AIDW_FOR_KNN_SLOTS(k, M)   \
@@ -52,6 +60,7 @@ __host__ __device__ inline int knn_slots(int k) {
     case 8: M(8); break;           \
     case 10: M(10); break;         \
     case 12: M(12); break;         \
+    case 15: M(15); break;         \
     case 16: M(16); break;         \
     case 24: M(24); break;         \
     case 32: M(32); break;         \
