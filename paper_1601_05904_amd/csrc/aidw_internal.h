@@ -284,7 +284,9 @@ hipError_t launch_mlp_repack(const MlpDevice& d, hipStream_t s);
 hipError_t launch_mlp_forward(const MlpDevice& d, const float* feat, int m, float* out, hipStream_t s);
 // Fused inference front of the learned run, per position t of the order perm (may be null):
 // features, the network (MFMA) and the fallback decision in one kernel; flag[t] = 1 marks a
-// query that takes the exact kNN.  route[q] (may be null) receives the query's route: 0 exact
+// query that takes the exact kNN.  Rules 2-4 may instead append those queries to list (with
+// *count cleared before; both null: flag), a wavefront's queries together in binned order.
+// route[q] (may be null) receives the query's route: 0 exact
 // kNN, 1 exact kNN after a failed 3 x 3 certificate, 2 certified by the block counts, 3
 // certified by the 3 x 3 distances, 4 alpha from the network.
 // The certificate's threshold on the sum of the k nearest distances is cert_factor * r_exp (r_exp
@@ -292,8 +294,9 @@ hipError_t launch_mlp_forward(const MlpDevice& d, const float* feat, int m, floa
 hipError_t launch_learned_front(const MlpDevice& d, const GridScalars* gs, const int32_t* cell_start, const float* sx,
                                 const float* sy, const float* qx, const float* qy, const uint32_t* perm, int m,
                                 int64_t n, const AlphaParams& ap, int rule, double delta, double r_sat_lo,
-                                double r_sat_hi, int k, double cert_factor, uint32_t* flag, float* alpha_f,
-                                float* d1sq, float* r_hat_out, uint8_t* route, hipStream_t s);
+                                double r_sat_hi, int k, double cert_factor, uint32_t* flag, uint32_t* list,
+                                uint32_t* count, float* alpha_f, float* d1sq, float* r_hat_out, uint8_t* route,
+                                hipStream_t s);
 size_t mlp_batch_scratch_floats(int B);
 // grad [AIDW_MLP_PARAMS + 1]: the batch gradient, then the batch's mean squared error.
 hipError_t launch_mlp_gradients(const MlpDevice& d, const float* feat, const float* target, const uint32_t* sel, int B,

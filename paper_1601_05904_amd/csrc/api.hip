@@ -1191,8 +1191,10 @@ aidw_status aidw_run_learned(const float* x, const float* y, const float* z, int
     if (ev) e = hipEventRecord(ev[1], stream);
     // Queries are processed in cell order (as the kNN kernel takes them): one kernel computes
     // the features, the network (on the matrix cores) and the decision per position of that
-    // order; the fallback list is the flagged positions, compacted in order by a prefix sum,
-    // so the kNN kernel sees them binned as well (its locality depends on that order).
+    // order.  The fallback list keeps that order, so the kNN kernel sees the queries binned as
+    // well (its locality depends on it): the front of rules 2-4 appends each wavefront's
+    // fallback queries together (one atomic per wavefront); for rules 0 and 1 the list is the
+    // flagged positions, compacted in order by a prefix sum.
     float *d1sq = nullptr, *alpha_f = nullptr, *r_obs = nullptr;
     uint32_t *flag = nullptr, *list = nullptr, *stmp = nullptr, *count = nullptr;
     const int mm = (int)m;
@@ -1221,10 +1223,14 @@ aidw_status aidw_run_learned(const float* x, const float* y, const float* z, int
     const double cert_factor = (double)p->k * fmin(r_sat_hi, p->r_max) * (1.0 + 1e-6);
 #define STEP(expr, what) \
   if (st == AIDW_OK && (e = (expr)) != hipSuccess) st = hip_fail(e, what)
+    const bool append = rule == AIDW_FALLBACK_CERTIFIED || rule == AIDW_FALLBACK_CERTIFIED_THEN_ALPHA_EXACT ||
+                        rule == AIDW_FALLBACK_NETWORK_GATED_CERTIFICATE;
+    if (append) STEP(hipMemsetAsync(count, 0, sizeof(uint32_t), stream), "clearing the fallback count");
     STEP(launch_learned_front(mlp->d, g->dev, g->cell_start, g->sx, g->sy, qx, qy, order, mm, n, ap, rule, delta,
-                              r_sat_lo, r_sat_hi, p->k, cert_factor, flag, alpha_f, d1sq, r_hat_out, nullptr, stream),
+                              r_sat_lo, r_sat_hi, p->k, cert_factor, flag, append ? list : nullptr,
+                              append ? count : nullptr, alpha_f, d1sq, r_hat_out, nullptr, stream),
          "features / network / decision kernel");
-    STEP(compact_flags(flag, order, mm, stmp, list, count, stream), "fallback compaction");
+    if (!append) STEP(compact_flags(flag, order, mm, stmp, list, count, stream), "fallback compaction");
     // the fallback queries are few and hard (cluster edges): eight lanes per query measured best
     STEP(launch_knn_lanes(g->dev, g->cell_start, g->sx, g->sy, g->sidx, qx, qy, list, count, mm, p->k, r_obs, d1sq,
                           nullptr, 8, stream, &ap, alpha_f),
@@ -1299,8 +1305,8 @@ aidw_status aidw_learned_routes(const float* x, const float* y, int64_t n, const
     const double cert_factor = (double)p->k * fmin(r_sat_hi, p->r_max) * (1.0 + 1e-6);
     if (st == AIDW_OK &&
         (e = launch_learned_front(mlp->d, g->dev, g->cell_start, g->sx, g->sy, qx, qy, order, mm, n, ap, rule, delta,
-                                  r_sat_lo, r_sat_hi, p->k, cert_factor, flag, alpha_f, d1sq, r_hat_out, route_out,
-                                  stream)) != hipSuccess)
+                                  r_sat_lo, r_sat_hi, p->k, cert_factor, flag, nullptr, nullptr, alpha_f, d1sq,
+                                  r_hat_out, route_out, stream)) != hipSuccess)
       st = hip_fail(e, "features / network / decision kernel");
   }
   if (st == AIDW_OK && !g->host_valid) st = sync_grid_host(g, stream);

@@ -791,8 +791,9 @@ __global__ __launch_bounds__(256) void k_cert_front(MlpDevice d, const GridScala
                                                     const float* __restrict__ qx, const float* __restrict__ qy,
                                                     const uint32_t* __restrict__ perm, int m, int64_t n,
                                                     AlphaParams ap, int k, double cert_factor, double delta,
-                                                    double r_sat_lo, double r_sat_hi,
-                                                    uint32_t* __restrict__ flag, float* __restrict__ alpha_f,
+                                                    double r_sat_lo, double r_sat_hi, uint32_t* __restrict__ flag,
+                                                    uint32_t* __restrict__ list, uint32_t* __restrict__ count,
+                                                    float* __restrict__ alpha_f,
                                                     float* __restrict__ d1sq, float* __restrict__ r_hat_out,
                                                     uint8_t* __restrict__ route) {
   static_assert(kRule >= 2 && kRule <= 4, "rules 2, 3, 4");
@@ -960,7 +961,19 @@ __global__ __launch_bounds__(256) void k_cert_front(MlpDevice d, const GridScala
       alpha = alpha_net;
     }
   }
-  flag[t] = fall ? 1u : 0u;
+  if (list) {
+    // the wavefront's exact-kNN queries go to the list together, in binned order (one atomic)
+    const uint64_t fb = __ballot(fall);
+    if (fb) {
+      const int lane = threadIdx.x & 63, lead = __ffsll((long long)fb) - 1;
+      uint32_t base = 0;
+      if (lane == lead) base = atomicAdd(count, (uint32_t)__popcll(fb));
+      base = __shfl(base, lead, 64);
+      if (fall) list[base + __popcll(fb & (lane == 0 ? 0ull : (~0ull >> (64 - lane))))] = (uint32_t)q;
+    }
+  } else {
+    flag[t] = fall ? 1u : 0u;
+  }
   if (!fall) {
     alpha_f[q] = (float)alpha;
     d1sq[q] = d1;
@@ -1014,12 +1027,16 @@ int tile_blocks(const void* kernel, int m) {
 hipError_t launch_learned_front(const MlpDevice& d, const GridScalars* gs, const int32_t* cell_start, const float* sx,
                                 const float* sy, const float* qx, const float* qy, const uint32_t* perm, int m,
                                 int64_t n, const AlphaParams& ap, int rule, double delta, double r_sat_lo,
-                                double r_sat_hi, int k, double cert_factor, uint32_t* flag, float* alpha_f,
-                                float* d1sq, float* r_hat_out, uint8_t* route, hipStream_t s) {
+                                double r_sat_hi, int k, double cert_factor, uint32_t* flag, uint32_t* list,
+                                uint32_t* count, float* alpha_f, float* d1sq, float* r_hat_out, uint8_t* route,
+                                hipStream_t s) {
   if (m <= 0) return hipSuccess;
+  if ((list != nullptr) != (count != nullptr) || (list && rule != 2 && rule != 3 && rule != 4))
+    return hipErrorInvalidValue;
 #define CERT_FRONT(R)                                                                                        \
   hipLaunchKernelGGL(k_cert_front<R>, dim3((m + 255) / 256), dim3(256), 0, s, d, gs, cell_start, sx, sy, qx, qy, \
-                     perm, m, n, ap, k, cert_factor, delta, r_sat_lo, r_sat_hi, flag, alpha_f, d1sq, r_hat_out, route)
+                     perm, m, n, ap, k, cert_factor, delta, r_sat_lo, r_sat_hi, flag, list, count, alpha_f, d1sq,  \
+                     r_hat_out, route)
   if (rule == 2)
     CERT_FRONT(2);
   else if (rule == 3)
