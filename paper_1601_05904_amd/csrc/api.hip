@@ -1195,15 +1195,17 @@ aidw_status aidw_run_learned(const float* x, const float* y, const float* z, int
     // well (its locality depends on it): the front of rules 2-4 appends each wavefront's
     // fallback queries together (one atomic per wavefront); for rules 0 and 1 the list is the
     // flagged positions, compacted in order by a prefix sum.
+    const bool append = rule == AIDW_FALLBACK_CERTIFIED || rule == AIDW_FALLBACK_CERTIFIED_THEN_ALPHA_EXACT ||
+                        rule == AIDW_FALLBACK_NETWORK_GATED_CERTIFICATE;
     float *d1sq = nullptr, *alpha_f = nullptr, *r_obs = nullptr;
     uint32_t *flag = nullptr, *list = nullptr, *stmp = nullptr, *count = nullptr;
     const int mm = (int)m;
     if (e == hipSuccess) e = t.get(&d1sq, mm);
     if (e == hipSuccess) e = t.get(&alpha_f, mm);
     if (e == hipSuccess) e = t.get(&r_obs, mm);
-    if (e == hipSuccess) e = t.get(&flag, mm);
+    if (e == hipSuccess && !append) e = t.get(&flag, mm);
     if (e == hipSuccess) e = t.get(&list, mm);
-    if (e == hipSuccess) e = t.get(&stmp, scan_tmp_words(mm));
+    if (e == hipSuccess && !append) e = t.get(&stmp, scan_tmp_words(mm));
     if (e == hipSuccess) e = t.get(&count, 1);
     if (e != hipSuccess) st = hip_fail(e, "allocating learned-R buffers");
     const uint32_t* order = nullptr;
@@ -1223,8 +1225,6 @@ aidw_status aidw_run_learned(const float* x, const float* y, const float* z, int
     const double cert_factor = (double)p->k * fmin(r_sat_hi, p->r_max) * (1.0 + 1e-6);
 #define STEP(expr, what) \
   if (st == AIDW_OK && (e = (expr)) != hipSuccess) st = hip_fail(e, what)
-    const bool append = rule == AIDW_FALLBACK_CERTIFIED || rule == AIDW_FALLBACK_CERTIFIED_THEN_ALPHA_EXACT ||
-                        rule == AIDW_FALLBACK_NETWORK_GATED_CERTIFICATE;
     if (append) STEP(hipMemsetAsync(count, 0, sizeof(uint32_t), stream), "clearing the fallback count");
     STEP(launch_learned_front(mlp->d, g->dev, g->cell_start, g->sx, g->sy, qx, qy, order, mm, n, ap, rule, delta,
                               r_sat_lo, r_sat_hi, p->k, cert_factor, flag, append ? list : nullptr,
