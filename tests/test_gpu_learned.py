@@ -277,9 +277,12 @@ def test_learned_prediction_small_grids(T, case):
     check_outputs(rh.cpu().numpy(), params, feat)
 
 
-def test_all_fallback_equals_plain_path(T):
+@pytest.mark.parametrize("m", [3000, 1 << 18])
+def test_all_fallback_equals_plain_path(T, m):
+    """Every query takes the exact kNN (delta beyond any prediction): alpha and z equal the plain
+    path's bit for bit, also with a fallback list of 2^18 queries."""
     aidw, L = mods()
-    ds = W.make(6000, 3000, 15, 231, "mixture", 8)
+    ds = W.make(6000 if m < 10000 else 1 << 16, m, 15, 231, "mixture", 8)
     mlp = L.MLP(seed=4)
     qz_p, al_p, _, qz_l, al_l, _, nfb = _plain_and_learned(T, ds, mlp, L.ALPHA_EXACT, 1e9, 15)
     assert nfb == ds.m
