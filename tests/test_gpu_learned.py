@@ -251,7 +251,7 @@ def _strip(n, m, seed):
 
 @pytest.mark.parametrize("case", ["n5_m37", "n40_m16", "n200_m33", "strip"])
 def test_learned_prediction_small_grids(T, case):
-    """R_hat of the fused front on grids where most of the 5 x 5 window lies outside the
+    """R_hat of the fused fronts on grids where most of the 5 x 5 window lies outside the
     grid (a handful of cells, a one-row strip) and with a ragged last tile of queries."""
     aidw, L = mods()
     if case == "strip":
@@ -275,6 +275,12 @@ def test_learned_prediction_small_grids(T, case):
         assert d["nrow"] <= 2 and d["ncol"] > 100
     feat = O.features(x, y, qx, qy, d["min_x"], d["min_y"], d["inv_cell_width"], d["ncol"], d["nrow"])
     check_outputs(rh.cpu().numpy(), params, feat)
+    # the one-lane front (rule 3) runs the same network on the queries the counts leave open,
+    # gathered per wavefront: its predictions there are rule 1's, bit for bit
+    _, _, rh3, _ = L.run_learned(dx, dy, dz, dqx, dqy, p, mlp, L.CERTIFIED_THEN_ALPHA_EXACT, 0.3, want_rhat=True)
+    rh, rh3 = rh.cpu().numpy(), rh3.cpu().numpy()
+    ev = ~np.isnan(rh3)
+    assert np.array_equal(rh[ev], rh3[ev])
 
 
 @pytest.mark.parametrize("m", [3000, 1 << 18])
