@@ -866,10 +866,10 @@ __global__ __launch_bounds__(256) void k_cert_front(MlpDevice d, const GridScala
         for (int j = 0; j < 6; ++j) o[j] = in ? cell_start[r * ncol + min(max(c0 + j - 2, 0), ncol)] : 0;
 #pragma unroll
         for (int bc = 0; bc < 5; ++bc)
-          f[5 * br + bc] = __builtin_bit_cast(uint16_t, (__bf16)(float)((double)(o[bc + 1] - o[bc]) * inv_occ));
+          f[5 * br + bc] = (uint16_t)bf16_bits((float)((double)(o[bc + 1] - o[bc]) * inv_occ));
       }
-      f[25] = __builtin_bit_cast(uint16_t, (__bf16)(tx - (float)c0));
-      f[26] = __builtin_bit_cast(uint16_t, (__bf16)(ty - (float)r0));
+      f[25] = (uint16_t)bf16_bits(tx - (float)c0);
+      f[26] = (uint16_t)bf16_bits(ty - (float)r0);
 #pragma unroll
       for (int j = 27; j < 32; ++j) f[j] = 0;
     }
