@@ -295,6 +295,15 @@ def test_small_and_edge_sizes(T, n, m, k):
     _run_case(T, ds)
 
 
+@pytest.mark.parametrize("n,m,k", [((1 << 22) + 13, 300, 10), (37, (1 << 19) + 5, 7)])
+def test_skewed_shapes(T, n, m, k):
+    """Few queries over many data points (the data axis split as finely as the partials allow,
+    256 splits with a ragged last one) and many queries over a handful of points (one chunk and
+    a tail per query, the kNN over a grid of a few cells): sampled queries against the oracle."""
+    ds = W.make(n, m, k, 95 + k)
+    _run_case(T, ds, qsel=W.sample_queries(m, 256, ds.seed))
+
+
 def test_error_paths_on_gpu(T):
     aidw = aidw_mod()
     ds = W.make(100, 20, 5, 90)
