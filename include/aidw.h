@@ -258,14 +258,15 @@ aidw_status aidw_run(const float* x, const float* y, const float* z, int64_t n, 
                      hipStream_t stream);
 
 /*
- * aidw_run for callers that cannot allocate device memory (code under HIP graph
- * capture, serving loops or harnesses that forbid hipMalloc): the same method,
+ * aidw_run for callers that cannot allocate device memory (serving loops or
+ * harnesses that forbid hipMalloc): the same method,
  * arguments, outputs and errors as aidw_run, with every temporary (grid, band
  * sort, query bins, r_obs / d1^2, alpha and class keys, padded data, float64
  * partials) taken from one fixed device array of AIDW_NOALLOC_SCRATCH_BYTES
  * that the library holds on each GPU it runs on until the process ends.  The
  * call makes no hipMalloc / hipFree or other allocation; it reads the grid's
- * status once at the end with a pageable copy (the stream is synchronised).
+ * status once at the end with a pageable copy (the stream is synchronised), so
+ * it cannot be recorded into a HIP graph as it stands.
  *   - The grid is sized by occupancy: params.cell_width must be <= 0
  *     (AIDW_EINVAL otherwise).
  *   - Sizes whose scratch exceeds the array are rejected before any work with
