@@ -408,8 +408,9 @@ aidw_status aidw_mlp_train(aidw_mlp* mlp, const float* feat, const float* target
  * interpolation of aidw_interpolate for every query.  p->cell_width must be
  * <= 0 and p->occupancy must equal the network's.  r_hat_out [m] (may be NULL)
  * receives the predictions; *fallback_count (host, may be NULL) the number of
- * queries that took the exact kNN path (this synchronises).  Timing as aidw_run
- * (the kNN stage time covers features, network and the fallback search). */
+ * queries that took the exact kNN path.  Synchronises the stream once at the
+ * end (the grid build's status, and the count).  Timing as aidw_run (the kNN
+ * stage time covers features, network and the fallback search). */
 aidw_status aidw_run_learned(const float* x, const float* y, const float* z, int64_t n, const float* qx,
                              const float* qy, int64_t m, const aidw_params* p, const aidw_mlp* mlp, int32_t rule,
                              double delta, float* qz, float* alpha_out, float* r_hat_out, int64_t* fallback_count,
