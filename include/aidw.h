@@ -109,9 +109,11 @@ typedef struct {
  * is described by two integers (Section 3.2.3: head and size, stored here as
  * CSR offsets cell_start[c] .. cell_start[c + 1]).
  * Waits once for the device-computed scalars (an event behind their copy to the
- * host: the grid's size depends on the bounds); the cell keys and the sort's
- * first pass are queued before that wait.  On success *out owns device memory
- * until aidw_grid_destroy.
+ * host): in occupancy mode (p->cell_width <= 0) after the whole build is queued,
+ * to report its status; with an explicit cell width after the bounds (the
+ * grid's size depends on them), with the cell keys and the sort's first pass
+ * queued before that wait.  On success *out owns device memory until
+ * aidw_grid_destroy.
  * Errors: AIDW_EINVAL (null pointers, n < 1, m < 0, sizes > INT32_MAX, invalid p),
  * AIDW_ENONFINITE (a NaN / inf coordinate), AIDW_EDEGENERATE (A <= 0),
  * AIDW_ECAPACITY (more than AIDW_MAX_CELLS cells), AIDW_ENOMEM, AIDW_EDEVICE.
