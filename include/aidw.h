@@ -204,8 +204,10 @@ aidw_status aidw_nn_statistic(const aidw_grid* g, const float* qx, const float* 
  * For each query j: R = r_obs[j] / r_exp with r_exp = 1 / (2 sqrt(n / A)),
  * mu(R) by Eq. 5 and alpha(mu) by Eq. 6 (float64), then
  *   qz[j] = sum_i z_i d_ij^-alpha / sum_i d_ij^-alpha  over all n data points.
- * Pairs are evaluated in float32 as w = 2^(-(alpha/2) log2(d^2 / d1sq[j]))
- * (the common factor d1sq^(alpha/2) cancels and keeps w <= ~1); the data are
+ * Pairs are evaluated in float32 on t = s^2 d^2, with s the smallest power of
+ * two such that s^2 d1sq[j] >= 1 (an exact scaling, so t is s^2 times the float32
+ * d^2 and the common factor s^-alpha cancels; it keeps w <= ~1): w = rsq(t)^p
+ * when alpha is an integer p in 1..8, else w = 2^(-(alpha/2) log2 t); the data are
  * streamed through the chip in tiles shared by every query of a wavefront, the
  * per-tile float32 partial sums are folded into compensated (two-sum) pairs,
  * and the final numerator / denominator are combined in float64.
