@@ -472,6 +472,35 @@ def test_certified_then_network_rule(T):
     assert np.all(np.isfinite(qz_3))
 
 
+@pytest.mark.parametrize("rule", ["certified", "gated"])
+def test_certificate_other_levels(T, rule):
+    """Rules 2 and 4 with R_min = 0.2, R_max = 1.8 and levels (0.5, 1.5, 2, 2.5, 3.7): the
+    saturation point the certificate must clear moves with R_min and R_max (mu >= 0.9 from
+    R = R_min + R_max acos(-0.8) / pi on, Eq. 5), and a skipped query takes alpha_5 = 3.7, a
+    level that is not an integer (the general pair form).  Every query's alpha equals the plain
+    path's, most queries skip the kNN search, and z stays within the bar of the FP64 oracle."""
+    aidw, L = mods()
+    ds = W.make(40000, 6000, 15, 271, "mixture", 16)
+    kw = dict(levels=(0.5, 1.5, 2.0, 2.5, 3.7), r_min=0.2, r_max=1.8)
+    p = aidw.Params(k=15, **kw)
+    mlp = L.MLP(seed=9)
+    x, y, z, qx, qy = (dev(T, getattr(ds, a)) for a in ("x", "y", "z", "qx", "qy"))
+    qz_p, al_p, _ = aidw.run(x, y, z, qx, qy, p, want_alpha=True)
+    r = L.CERTIFIED if rule == "certified" else L.NETWORK_GATED_CERTIFICATE
+    qz_l, al_l, _, nfb = L.run_learned(x, y, z, qx, qy, p, mlp, r, 0.3, want_alpha=True)
+    T.cuda.synchronize()
+    al_p, al_l, qz_l = al_p.cpu().numpy(), al_l.cpu().numpy(), qz_l.cpu().numpy()
+    assert 0 < nfb < ds.m // 2
+    assert np.array_equal(al_l, al_p)
+    assert np.count_nonzero(al_l == np.float32(3.7)) > ds.m // 2
+    assert np.allclose(qz_l, qz_p.cpu().numpy(), rtol=2e-6, atol=1e-7)
+    sel = np.arange(0, ds.m, max(1, ds.m // 400))
+    ref = O.aidw(ds.x, ds.y, ds.z, ds.qx, ds.qy, k=15, qsel=sel, **kw)
+    e = np.abs(qz_l[sel].astype(np.float64) - ref["z"]) / np.maximum(np.abs(ref["z"]), ref["s"])
+    assert e.max() <= 1e-5
+    assert np.allclose(al_l[sel], ref["alpha"], rtol=0, atol=2e-6)
+
+
 @pytest.mark.parametrize("case", ["mixture", "small_grid"])
 def test_gated_rule_prediction(T, case):
     """Rule 4 evaluates the network in the one-lane front, on the queries the block counts leave
